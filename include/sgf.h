@@ -1,0 +1,290 @@
+/*
+ * sgf.h -- C ABI of the MI355X shifted-COCG Green's-function library.
+ *
+ * The method (paper, Introduction): instead of the generalized eigenproblem
+ * H y = lambda S y, solve the generalized shifted linear equations
+ * (z S - H) x = b for many complex energies z; the cost grows linearly with
+ * the number of atoms N.  Each basis column b = e_j is solved inside its own
+ * local subspace (the atoms near the atom that carries orbital j), and all
+ * energies of a column share one Krylov subspace (shifted COCG).  The
+ * outputs are Green's-function elements G_ij(z_k) = [(z_k S - H)^{-1}]_ij on
+ * projection rows i in P(j) and density-matrix entries
+ *     rho_ij = -(1/pi) sum_k Im(w_k G_ij(z_k)).
+ * The tight-binding model is the paper's ab-initio-based tight binding,
+ * here a Slater-Koster sp model with 4x4 blocks (one block row per atom).
+ *
+ * Conventions for every entry point:
+ *  - Every call returns sgf_status; nothing throws across the ABI and nothing
+ *    calls exit().  On a non-OK status, sgf_last_error() returns a
+ *    thread-local description of the failure.
+ *  - Pointers prefixed d_ are DEVICE pointers owned by the caller, who keeps
+ *    them alive until the stream has completed the call.  Pointers without a
+ *    prefix are host pointers, read only during the call.
+ *  - The library makes no device allocation.  Scratch memory comes from the
+ *    caller through a query -> allocate -> call pattern (*_workspace).
+ *  - Calls are asynchronous on `stream` (a hipStream_t; NULL = the default
+ *    stream) unless marked SYNCHRONOUS, which means the call waits for the
+ *    stream because it returns a device-computed size to the host.
+ *  - Arguments are validated before any launch; an invalid argument returns
+ *    SGF_EINVAL and launches nothing.  A HIP runtime failure returns SGF_EHIP.
+ *    Numerical outcomes never fail a call; they go to per-column status codes.
+ *  - Complex numbers are interleaved (re, im) doubles.
+ *  - BSR layout: row_ptr int32[n_atoms+1], col int32[nnzb] (sorted within each
+ *    row, diagonal block included), values [nnzb][4][4] row-major.  Global
+ *    orbital index = 4*atom + o, o in (s, px, py, pz).
+ */
+#ifndef SGF_H
+#define SGF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SGF_OK = 0,
+    SGF_EINVAL = -1,       /* invalid argument; nothing was launched */
+    SGF_ENOMEM = -2,       /* caller-provided workspace too small */
+    SGF_EHIP = -3,         /* HIP runtime error */
+    SGF_EUNSUPPORTED = -4  /* valid request outside the built kernels' limits */
+} sgf_status;
+
+/* Per-column outcome written to d_status by sgf_shifted_solve. */
+typedef enum {
+    SGF_CONVERGED = 0,  /* every shift reached the tolerance */
+    SGF_MAXITER = 1,    /* max_iter reached with at least one shift unconverged */
+    SGF_BREAKDOWN = 2,  /* mu = p^T (z_s S - H) p or rho = r^T s vanished with s != 0 */
+    SGF_NONFINITE = 3,  /* a recurrence scalar became Inf/NaN */
+    SGF_DRIFT = 4,      /* mixed path: recursive and FP64 true residual disagree */
+    SGF_BADCOLUMN = 5   /* column, plan index or plan sizes inconsistent; nothing computed */
+} sgf_col_status;
+
+/* Thread-local text of the last non-OK status returned on this thread. */
+const char *sgf_last_error(void);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int sgf_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Model and system                                                           */
+/* ------------------------------------------------------------------------ */
+
+/* Slater-Koster sp parameters (eV, nm).  Hopping blocks scale as
+ * V0 * (r0/r)^power for r <= r_cut (hard cutoff).  overlap = 0: S = I;
+ * overlap = 1: S_ab = s_amp * exp(-(r - r0)/s_decay) * I4 on the bond
+ * pattern and S_aa = I4. */
+typedef struct {
+    double e_s, e_p, v_sss, v_sps, v_pps, v_ppp;
+    double r0, power, r_cut;
+    int32_t overlap;
+    double s_amp, s_decay;
+} sgf_tb_params;
+
+/* Device view of a built system (all pointers device, caller-owned).
+ * s / s32 are NULL when S = I.  h32 / s32 are FP32 shadows used by the
+ * mixed-precision path (NULL when it is not used).  xyz (nm, [n_atoms][3])
+ * may be NULL when every plan uses the whole system (radius <= 0). */
+typedef struct {
+    int64_t n_atoms;
+    int64_t nnzb;
+    const int32_t *row_ptr;
+    const int32_t *col;
+    const double *h;
+    const double *s;
+    const float *h32;
+    const float *s32;
+    const double *xyz;
+} sgf_system;
+
+/* Bytes of scratch needed by sgf_build_pattern for n_atoms atoms. */
+sgf_status sgf_build_workspace(int64_t n_atoms, size_t *ws_bytes);
+
+/* Bond pattern (neighbour list).  Atom pairs a != b with
+ * (dx*dx + dy*dy) + dz*dz <= r_cut^2 (FP64, evaluated without fused
+ * multiply-add) are bonded.  Writes d_row_ptr[n_atoms+1] (each row counts
+ * its bonds plus the diagonal block) and returns the block count in *nnzb.
+ * d_ws keeps a spatial hash of the atoms that sgf_build_hamiltonian reuses.
+ * SYNCHRONOUS (reads nnzb back).  EINVAL on n_atoms < 1, r_cut <= 0, NULL
+ * pointers or ws_bytes below sgf_build_workspace. */
+sgf_status sgf_build_pattern(int64_t n_atoms, const double *d_xyz, double r_cut, void *d_ws, size_t ws_bytes,
+                             int32_t *d_row_ptr, int64_t *nnzb, void *stream);
+
+/* Tight-binding H (and S when p->overlap) on the pattern from
+ * sgf_build_pattern (same d_ws, not modified in between).  Fills d_col
+ * (sorted per row) and d_h [nnzb][4][4]; d_s likewise when p->overlap
+ * (d_s must then be non-NULL).  d_onsite (nullable) gives 4*n_atoms on-site
+ * energies, otherwise diag(e_s, e_p, e_p, e_p).  Hopping block for the bond
+ * a -> b with direction cosines c = (R_b - R_a)/r and f = (r0/r)^power
+ * (Slater and Koster 1954, Table I):
+ *   [s][s] = v_sss f, [s][pA] = c_A v_sps f, [pA][s] = -c_A v_sps f,
+ *   [pA][pB] = (c_A c_B (v_pps - v_ppp) + delta_AB v_ppp) f.
+ * EINVAL on inconsistent sizes or NULL pointers. */
+sgf_status sgf_build_hamiltonian(int64_t n_atoms, const double *d_xyz, const double *d_onsite,
+                                 const sgf_tb_params *p, const void *d_ws, size_t ws_bytes,
+                                 const int32_t *d_row_ptr, int64_t nnzb, int32_t *d_col, double *d_h,
+                                 double *d_s, void *stream);
+
+/* One-orbital chain grouped four sites to a block: H_ii = eps_i,
+ * H_{i,i+1} = H_{i+1,i} = t, open ends, S = I.  n_sites must be a multiple
+ * of 4; nnzb = 3*(n_sites/4) - 2 (1 when n_sites == 4).  Writes
+ * d_row_ptr[n_sites/4 + 1], d_col[nnzb], d_h[nnzb][4][4]. */
+sgf_status sgf_build_chain(int64_t n_sites, const double *d_eps, double t, int32_t *d_row_ptr, int32_t *d_col,
+                           double *d_h, void *stream);
+
+/* FP32 shadow of a block array: d_out[i] = (float)d_in[i], n_values values. */
+sgf_status sgf_to_f32(const double *d_in, int64_t n_values, float *d_out, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Local subspaces                                                            */
+/* ------------------------------------------------------------------------ */
+
+/* A plan describes the local subspace of one centre atom c: the atoms a with
+ * (dx*dx + dy*dy) + dz*dz <= R^2 (all atoms when R <= 0), in increasing
+ * global order; with prune != 0 only those connected to c through stored
+ * blocks inside that ball are kept (the solution of (zS - H)x = e_j vanishes
+ * outside that component, so the result is unchanged).  The local operator
+ * is the principal sub-block of H (and S) on those atoms.  The projection
+ * atoms P are c and every atom that shares a stored block with c, inside the
+ * subspace, in increasing global order.  Columns j = 4c + o of one centre
+ * (and one radius) share a plan.
+ *
+ * Inputs (device): center[n_plans] int32, radius[n_plans] double.
+ * Outputs (device, caller-allocated):
+ *   atom_off, blk_off, pa_off  int64[n_plans+1]  -- filled by sgf_plan_count
+ *   loc_atom  int32[atom_off[n]]  global atom of each local atom
+ *   lrow      int32[atom_off[n]]  start of each local block row, relative to blk_off[p]
+ *   lblk      int32[2*blk_off[n]] (local column atom, global block index) pairs
+ *   pa_loc    int32[pa_off[n]]    local index of each projection atom
+ *   center_loc int32[n_plans]     local index of the centre atom
+ */
+typedef struct {
+    int64_t n_plans;
+    const int32_t *center;
+    const double *radius;
+    int32_t prune;
+    int64_t *atom_off;
+    int64_t *blk_off;
+    int64_t *pa_off;
+    int32_t *loc_atom;
+    int32_t *lrow;
+    int32_t *lblk;
+    int32_t *pa_loc;
+    int32_t *center_loc;
+} sgf_plan;
+
+/* Totals of a plan batch, returned to the host. */
+typedef struct {
+    int64_t n_loc_atoms;   /* atom_off[n_plans] */
+    int64_t n_loc_blocks;  /* blk_off[n_plans] */
+    int64_t n_proj_atoms;  /* pa_off[n_plans] */
+    int32_t max_loc_atoms, max_loc_blocks, max_proj_atoms, pad;
+} sgf_plan_totals;
+
+/* Scratch bytes for planning n_plans centres with at most max_loc_atoms
+ * local atoms each (the ball before pruning). */
+sgf_status sgf_plan_workspace(const sgf_system *sys, int64_t n_plans, int32_t max_loc_atoms, size_t *ws_bytes);
+
+/* Count local atoms, local blocks and projection atoms per plan and write
+ * the offsets atom_off / blk_off / pa_off.  The spatial hash of the build
+ * workspace (d_build_ws, from sgf_build_pattern on the same xyz) finds the
+ * atoms in the ball.  SYNCHRONOUS (returns totals).  A ball larger than
+ * max_loc_atoms returns SGF_EUNSUPPORTED with the offending plan named. */
+sgf_status sgf_plan_count(const sgf_system *sys, sgf_plan *plan, int32_t max_loc_atoms, const void *d_build_ws,
+                          size_t build_ws_bytes, void *d_ws, size_t ws_bytes, sgf_plan_totals *totals,
+                          void *stream);
+
+/* Fill loc_atom, lrow, lblk, pa_loc and center_loc (after sgf_plan_count with
+ * the same arguments). */
+sgf_status sgf_plan_build(const sgf_system *sys, sgf_plan *plan, int32_t max_loc_atoms, const void *d_build_ws,
+                          size_t build_ws_bytes, void *d_ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Shifted solve                                                              */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t precision;     /* 0: FP64 throughout; 1: mixed (complex-FP32 vectors and operator,
+                              FP64 recurrence scalars, FP64 true-residual monitor and FP64 epilogue) */
+    double tol;            /* shift k stops when ||s_{n+1}||_2 / |pi^k_{n+1}| <= tol ||b||_2 */
+    int32_t max_iter;      /* <= 0: 10 * (local orbitals) per column */
+    int32_t seed_index;    /* < 0: n_shifts / 2 */
+    int32_t monitor_every; /* mixed: FP64 true residual every K iterations (0: only at the end) */
+    int32_t stage_lds;     /* 1: copy each local operator to LDS; 0: read it from global; -1: auto */
+    int32_t grid;          /* seed-pass persistent workgroups; 0: fill the device */
+    int32_t profile;       /* 1: record HIP events around each pass (read with sgf_solve_profile) */
+    int64_t batch_cols;    /* columns per history batch for sgf_solve_workspace (0: all) */
+} sgf_solve_opts;
+
+/* Output offsets: d_proj_off[c+1] - d_proj_off[c] = 4 * |P(plan of column c)|
+ * (int64[n_cols+1]); also writes d_proj_row (global orbital of every
+ * projection row) when it is non-NULL on a second call.  SYNCHRONOUS
+ * (returns the total row count). */
+sgf_status sgf_proj_layout(const sgf_plan *plan, int64_t n_cols, const int64_t *d_cols, const int32_t *d_col_plan,
+                           int64_t *d_proj_off, int32_t *d_proj_row, int64_t *total_rows, void *stream);
+
+/* Scratch bytes for sgf_shifted_solve with opts->batch_cols columns per
+ * batch (0: every column at once).  Per column the workspace holds the seed
+ * history: (max_iter) x 32 bytes of recurrence scalars and (max_iter + 1) x
+ * 16 x 4|P|max bytes of projected residuals.  sgf_shifted_solve accepts any
+ * workspace of at least one column's worth and processes the columns in as
+ * many batches as it needs. */
+sgf_status sgf_solve_workspace(const sgf_system *sys, const sgf_plan_totals *totals, int64_t n_cols,
+                               int32_t n_shifts, const sgf_solve_opts *opts, size_t *ws_bytes);
+
+/*
+ * Shifted COCG for n_cols columns (b = e_j, j = d_cols[c], local subspace
+ * d_col_plan[c]) at n_shifts energies z (HOST array, all Im z_k > 0; copied
+ * into the workspace on the stream), seed z_s = z[seed_index].  For every
+ * column, on its local subspace:
+ *   w = z_s q - H p;  mu = p^T w;  alpha = rho / mu
+ *   s -= alpha w;  r = S^{-1} s;  rho' = r^T s;  beta = rho' / rho
+ *   p = r + beta p;  q = s + beta q
+ *   per active shift k (sigma_k = z_k - z_s):
+ *     pi^k_{n+1} = (1 + alpha sigma_k) pi^k_n + (alpha beta_old / alpha_old)(pi^k_n - pi^k_{n-1})
+ *     frozen after step n once ||s_{n+1}|| / |pi^k_{n+1}| <= tol  (N_k = n + 1 steps)
+ *   G^k_P = (x^k)_P for the N_k-step shifted iterate
+ *     x^k = sum_n alpha^k_n p^k_n,  alpha^k = alpha pi^k_n / pi^k_{n+1},
+ *     p^k = r_{n+1} / pi^k_{n+1} + (pi^k_n / pi^k_{n+1})^2 beta p^k
+ * (COCG, van der Vorst and Melissen 1990; shifted form with collinear
+ * residuals, Frommer 2003 and Takayama et al. 2006).  The library evaluates
+ * x^k_P from the recorded seed scalars by a backward sweep over the
+ * tridiagonal T_{N_k} + sigma_k of the seed iteration, which yields the same
+ * iterate.
+ *
+ * Outputs (device): d_G complex [total_rows][n_shifts] (nullable: rho only),
+ * d_rho double[total_rows] with rho_ij = -(1/pi) sum_k Im(w_k G_ij(z_k))
+ * (w: HOST complex[n_shifts] quadrature weights; NULL: all zero),
+ * d_iters / d_status int32[n_cols], d_resid double[n_cols][n_shifts]
+ * (nullable): ||s|| / |pi^k| when shift k froze (or at the last step).
+ * d_shift_iters (nullable) int32[n_cols][n_shifts]: N_k, the steps shift k took.
+ * d_order (nullable) int32[n_cols]: the order in which columns are taken
+ * from the work queue (a permutation of 0..n_cols-1); results do not depend
+ * on it (entries outside [0, n_cols) are skipped).  Device arrays are
+ * checked where they are read: a column whose plan index is out of range,
+ * whose atom is not its plan's centre, or whose plan exceeds `totals`
+ * gets SGF_BADCOLUMN and no output.  EINVAL on bad sizes, Im z_k <= 0, tol <= 0, NULL required
+ * pointers or a workspace below one column's worth; EUNSUPPORTED when a plan
+ * is larger than the kernels' LDS allows, a column has more than 8
+ * projection atoms or n_shifts > 512.
+ */
+sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *plan, const sgf_plan_totals *totals,
+                             int64_t n_cols, const int64_t *d_cols, const int32_t *d_col_plan,
+                             const int32_t *d_order, int32_t n_shifts, const double *z, const double *w,
+                             const sgf_solve_opts *opts, void *d_ws, size_t ws_bytes, const int64_t *d_proj_off,
+                             double *d_G, double *d_rho, int32_t *d_iters, int32_t *d_status, double *d_resid,
+                             int32_t *d_shift_iters, void *stream);
+
+/* Kernel times of the last sgf_shifted_solve on this thread that ran with
+ * opts->profile = 1, from HIP events recorded on its stream around every
+ * launch of the seed pass and of the shift pass.  SYNCHRONOUS (waits for
+ * those events).  *batches = number of launches of each pass.  EINVAL if no
+ * profiled solve is pending; the events are released by this call. */
+sgf_status sgf_solve_profile(double *seed_ms, double *shift_ms, int32_t *batches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGF_H */

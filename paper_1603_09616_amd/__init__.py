@@ -1,0 +1,429 @@
+"""Python binding of the gfx950 shifted-COCG Green's-function library.
+
+Argument marshalling only: every step of the path (neighbour search,
+Hamiltonian assembly, local subspaces, the shifted solve) runs in the HIP
+kernels of ``libsgf.so`` behind the C ABI declared in ``include/sgf.h``.
+PyTorch supplies device memory and the stream.  Importing this module does
+not load the library; the first call does, and raises if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsgf.so")
+
+SGF_OK, SGF_EINVAL, SGF_ENOMEM, SGF_EHIP, SGF_EUNSUPPORTED = 0, -1, -2, -3, -4
+CONVERGED, MAXITER, BREAKDOWN, NONFINITE, DRIFT, BADCOLUMN = 0, 1, 2, 3, 4, 5
+
+EXPORTED = (
+    "sgf_last_error", "sgf_version", "sgf_build_workspace", "sgf_build_pattern", "sgf_build_hamiltonian",
+    "sgf_build_chain", "sgf_to_f32", "sgf_plan_workspace", "sgf_plan_count", "sgf_plan_build", "sgf_proj_layout",
+    "sgf_solve_workspace", "sgf_shifted_solve", "sgf_solve_profile",
+)
+
+
+class SgfError(RuntimeError):
+    def __init__(self, fn: str, code: int, msg: str):
+        super().__init__(f"{fn} returned {code}: {msg}")
+        self.code = code
+
+
+# --- C structures (mirror include/sgf.h) --------------------------------------
+P = ctypes.c_void_p
+i32, i64, dbl, szt = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+
+
+class TBParamsC(ctypes.Structure):
+    _fields_ = [("e_s", dbl), ("e_p", dbl), ("v_sss", dbl), ("v_sps", dbl), ("v_pps", dbl), ("v_ppp", dbl),
+                ("r0", dbl), ("power", dbl), ("r_cut", dbl), ("overlap", i32), ("s_amp", dbl), ("s_decay", dbl)]
+
+
+class SystemC(ctypes.Structure):
+    _fields_ = [("n_atoms", i64), ("nnzb", i64), ("row_ptr", P), ("col", P), ("h", P), ("s", P), ("h32", P),
+                ("s32", P), ("xyz", P)]
+
+
+class PlanC(ctypes.Structure):
+    _fields_ = [("n_plans", i64), ("center", P), ("radius", P), ("prune", i32), ("atom_off", P), ("blk_off", P),
+                ("pa_off", P), ("loc_atom", P), ("lrow", P), ("lblk", P), ("pa_loc", P), ("center_loc", P)]
+
+
+class PlanTotalsC(ctypes.Structure):
+    _fields_ = [("n_loc_atoms", i64), ("n_loc_blocks", i64), ("n_proj_atoms", i64), ("max_loc_atoms", i32),
+                ("max_loc_blocks", i32), ("max_proj_atoms", i32), ("pad", i32)]
+
+
+class SolveOptsC(ctypes.Structure):
+    _fields_ = [("precision", i32), ("tol", dbl), ("max_iter", i32), ("seed_index", i32), ("monitor_every", i32),
+                ("stage_lds", i32), ("grid", i32), ("profile", i32), ("batch_cols", i64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsgf.so (built by ``paper_1603_09616_amd.build``); raise if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1603_09616_amd.build` "
+                              "(or __graft_entry__.build()); there is no fallback path")
+        L = ctypes.CDLL(LIB_PATH)
+        L.sgf_last_error.restype = ctypes.c_char_p
+        L.sgf_version.restype = ctypes.c_int
+        sigs = {
+            "sgf_build_workspace": [i64, P],
+            "sgf_build_pattern": [i64, P, dbl, P, szt, P, P, P],
+            "sgf_build_hamiltonian": [i64, P, P, P, P, szt, P, i64, P, P, P, P],
+            "sgf_build_chain": [i64, P, dbl, P, P, P, P],
+            "sgf_to_f32": [P, i64, P, P],
+            "sgf_plan_workspace": [P, i64, i32, P],
+            "sgf_plan_count": [P, P, i32, P, szt, P, szt, P, P],
+            "sgf_plan_build": [P, P, i32, P, szt, P, szt, P],
+            "sgf_proj_layout": [P, i64, P, P, P, P, P, P],
+            "sgf_solve_workspace": [P, P, i64, i32, P, P],
+            "sgf_shifted_solve": [P, P, P, i64, P, P, P, i32, P, P, P, P, szt, P, P, P, P, P, P, P, P],
+            "sgf_solve_profile": [P, P, P],
+        }
+        for name, args in sigs.items():
+            f = getattr(L, name)
+            f.restype = ctypes.c_int
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(fn: str, code: int):
+    if code != SGF_OK:
+        raise SgfError(fn, code, lib().sgf_last_error().decode())
+
+
+def _call(name: str, *args):
+    _check(name, getattr(lib(), name)(*args))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _dev(a, dtype, device="cuda"):
+    torch = _torch()
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=device)
+
+
+def _bytes(n: int, device="cuda"):
+    torch = _torch()
+    return torch.empty(max(int(n), 1), dtype=torch.uint8, device=device)
+
+
+# --- system -----------------------------------------------------------------
+
+@dataclasses.dataclass
+class System:
+    """Device-resident block-sparse H (and S), with the spatial hash of its atoms."""
+    n_atoms: int
+    nnzb: int
+    row_ptr: "object"
+    col: "object"
+    h: "object"
+    s: "object" = None
+    h32: "object" = None
+    s32: "object" = None
+    xyz: "object" = None
+    build_ws: "object" = None
+
+    def c(self) -> SystemC:
+        return SystemC(self.n_atoms, self.nnzb, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.h), _ptr(self.s),
+                       _ptr(self.h32), _ptr(self.s32), _ptr(self.xyz))
+
+    def add_f32(self, stream=None) -> "System":
+        """FP32 shadows of H (and S) for the mixed-precision path."""
+        torch = _torch()
+        self.h32 = torch.empty(self.h.shape, dtype=torch.float32, device=self.h.device)
+        _call("sgf_to_f32", _ptr(self.h), self.h.numel(), _ptr(self.h32), _stream(stream))
+        if self.s is not None:
+            self.s32 = torch.empty(self.s.shape, dtype=torch.float32, device=self.s.device)
+            _call("sgf_to_f32", _ptr(self.s), self.s.numel(), _ptr(self.s32), _stream(stream))
+        return self
+
+
+def _tb_c(p) -> TBParamsC:
+    return TBParamsC(p.e_s, p.e_p, p.v_sss, p.v_sps, p.v_pps, p.v_ppp, p.r0, p.power, p.r_cut, int(p.overlap),
+                     p.s_amp, p.s_decay)
+
+
+def build_hamiltonian(xyz, params, onsite=None, device="cuda", stream=None) -> System:
+    """Neighbour search and Slater-Koster assembly of H (and S) on the GPU."""
+    torch = _torch()
+    d_xyz = _dev(xyz, torch.float64, device)
+    n = d_xyz.shape[0]
+    ws = ctypes.c_size_t()
+    _call("sgf_build_workspace", n, ctypes.byref(ws))
+    d_ws = _bytes(ws.value, device)
+    row_ptr = torch.empty(n + 1, dtype=torch.int32, device=device)
+    nnzb = ctypes.c_int64()
+    st = _stream(stream)
+    _call("sgf_build_pattern", n, _ptr(d_xyz), float(params.r_cut), _ptr(d_ws), ws.value, _ptr(row_ptr),
+          ctypes.byref(nnzb), st)
+    nb = nnzb.value
+    col = torch.empty(nb, dtype=torch.int32, device=device)
+    h = torch.empty((nb, 4, 4), dtype=torch.float64, device=device)
+    s = torch.empty((nb, 4, 4), dtype=torch.float64, device=device) if params.overlap else None
+    d_on = None if onsite is None else _dev(onsite, torch.float64, device)
+    tb = _tb_c(params)
+    _call("sgf_build_hamiltonian", n, _ptr(d_xyz), _ptr(d_on), ctypes.byref(tb), _ptr(d_ws), ws.value,
+          _ptr(row_ptr), nb, _ptr(col), _ptr(h), _ptr(s), st)
+    return System(n, nb, row_ptr, col, h, s, xyz=d_xyz, build_ws=d_ws)
+
+
+def build_chain(eps, t: float, device="cuda", stream=None) -> System:
+    """One-orbital chain (four sites per 4x4 block), S = I."""
+    torch = _torch()
+    d_eps = _dev(eps, torch.float64, device)
+    n_sites = d_eps.numel()
+    nb = n_sites // 4
+    nnzb = 1 if nb == 1 else 3 * nb - 2
+    row_ptr = torch.empty(nb + 1, dtype=torch.int32, device=device)
+    col = torch.empty(nnzb, dtype=torch.int32, device=device)
+    h = torch.empty((nnzb, 4, 4), dtype=torch.float64, device=device)
+    _call("sgf_build_chain", n_sites, _ptr(d_eps), float(t), _ptr(row_ptr), _ptr(col), _ptr(h), _stream(stream))
+    return System(nb, nnzb, row_ptr, col, h)
+
+
+def system_for(wl, device="cuda") -> System:
+    """GPU-built system of a workload from ``workloads``."""
+    if wl.kind == "chain":
+        return build_chain(wl.onsite, wl.hopping, device)
+    return build_hamiltonian(wl.xyz, wl.tb, device=device)
+
+
+# --- plans --------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Plan:
+    n_plans: int
+    center: "object"
+    radius: "object"
+    prune: int
+    atom_off: "object"
+    blk_off: "object"
+    pa_off: "object"
+    loc_atom: "object"
+    lrow: "object"
+    lblk: "object"
+    pa_loc: "object"
+    center_loc: "object"
+    totals: PlanTotalsC
+
+    def c(self) -> PlanC:
+        return PlanC(self.n_plans, _ptr(self.center), _ptr(self.radius), int(self.prune), _ptr(self.atom_off),
+                     _ptr(self.blk_off), _ptr(self.pa_off), _ptr(self.loc_atom), _ptr(self.lrow), _ptr(self.lblk),
+                     _ptr(self.pa_loc), _ptr(self.center_loc))
+
+
+def make_plan(system: System, centers, radii, prune: bool = True, max_loc_atoms: int = 2048, stream=None) -> Plan:
+    """Local subspaces (ball of each radius around each centre atom)."""
+    torch = _torch()
+    dev = system.row_ptr.device
+    center = _dev(centers if isinstance(centers, torch.Tensor) else np.asarray(centers, np.int32), torch.int32, dev)
+    radius = _dev(radii if isinstance(radii, torch.Tensor) else np.asarray(radii, np.float64), torch.float64, dev)
+    n = center.numel()
+    off = [torch.zeros(n + 1, dtype=torch.int64, device=dev) for _ in range(3)]
+    ws = ctypes.c_size_t()
+    sc = system.c()
+    _call("sgf_plan_workspace", ctypes.byref(sc), n, int(max_loc_atoms), ctypes.byref(ws))
+    d_ws = _bytes(ws.value, dev)
+    plan = Plan(n, center, radius, int(prune), off[0], off[1], off[2], None, None, None, None, None,
+                PlanTotalsC())
+    pc = plan.c()
+    bws = system.build_ws
+    bws_bytes = 0 if bws is None else bws.numel()
+    st = _stream(stream)
+    _call("sgf_plan_count", ctypes.byref(sc), ctypes.byref(pc), int(max_loc_atoms), _ptr(bws), bws_bytes,
+          _ptr(d_ws), ws.value, ctypes.byref(plan.totals), st)
+    t = plan.totals
+    plan.loc_atom = torch.empty(max(t.n_loc_atoms, 1), dtype=torch.int32, device=dev)
+    plan.lrow = torch.empty(max(t.n_loc_atoms, 1), dtype=torch.int32, device=dev)
+    plan.lblk = torch.empty(max(2 * t.n_loc_blocks, 1), dtype=torch.int32, device=dev)
+    plan.pa_loc = torch.empty(max(t.n_proj_atoms, 1), dtype=torch.int32, device=dev)
+    plan.center_loc = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    pc = plan.c()
+    _call("sgf_plan_build", ctypes.byref(sc), ctypes.byref(pc), int(max_loc_atoms), _ptr(bws), bws_bytes,
+          _ptr(d_ws), ws.value, st)
+    return plan
+
+
+def plan_columns(columns, radius=0.0, radius_per_col=None):
+    """Group columns by (atom, radius): returns (centers, radii, col_plan)."""
+    cols = np.asarray(columns, np.int64)
+    atoms = cols // 4
+    rad = np.full(cols.size, float(radius)) if radius_per_col is None else np.asarray(radius_per_col, np.float64)
+    keys = np.stack([atoms.astype(np.float64), rad], axis=1)
+    uniq, inv = np.unique(keys, axis=0, return_inverse=True)
+    return uniq[:, 0].astype(np.int32), uniq[:, 1].copy(), inv.reshape(-1).astype(np.int32)
+
+
+# --- solve --------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Result:
+    proj_off: "object"   # int64 [n_cols+1]
+    proj_row: "object"   # int32 [rows]
+    G: "object"          # complex128 [rows, n_shifts] or None
+    rho: "object"        # float64 [rows]
+    iters: "object"      # int32 [n_cols]
+    status: "object"     # int32 [n_cols]
+    resid: "object"      # float64 [n_cols, n_shifts] or None
+
+    def numpy(self):
+        cv = (lambda t: None if t is None else t.cpu().numpy())
+        return Result(*(cv(getattr(self, f.name)) for f in dataclasses.fields(self)))
+
+    def column(self, c: int):
+        a, b = int(self.proj_off[c]), int(self.proj_off[c + 1])
+        return self.proj_row[a:b], (None if self.G is None else self.G[a:b]), self.rho[a:b]
+
+
+@dataclasses.dataclass
+class Prepared:
+    """Everything a repeated solve reuses: plan, column map, output layout, workspace."""
+    system: System
+    plan: Plan
+    cols: "object"
+    col_plan: "object"
+    proj_off: "object"
+    proj_row: "object"
+    n_rows: int
+
+
+def prepare(system: System, columns, radius=0.0, radius_per_col=None, prune=True, max_loc_atoms=2048,
+            stream=None) -> Prepared:
+    """Plans (one per distinct atom and radius) and the output layout of the columns."""
+    torch = _torch()
+    dev = system.row_ptr.device
+    centers, radii, col_plan = plan_columns(columns, radius, radius_per_col)
+    return prepare_planned(system, _dev(np.asarray(columns, np.int64), torch.int64, dev),
+                           _dev(col_plan, torch.int32, dev), _dev(centers, torch.int32, dev),
+                           _dev(radii, torch.float64, dev), prune, max_loc_atoms, stream)
+
+
+def prepare_planned(system: System, d_cols, d_col_plan, d_centers, d_radii, prune=True, max_loc_atoms=2048,
+                    stream=None) -> Prepared:
+    """Same as prepare() for inputs already on the device: columns, their plan
+    index, and the centre atom and radius of every plan."""
+    torch = _torch()
+    dev = system.row_ptr.device
+    plan = make_plan(system, d_centers, d_radii, prune, max_loc_atoms, stream)
+    n = d_cols.numel()
+    proj_off = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    total = ctypes.c_int64()
+    pc = plan.c()
+    _call("sgf_proj_layout", ctypes.byref(pc), n, _ptr(d_cols), _ptr(d_col_plan), _ptr(proj_off), None,
+          ctypes.byref(total), _stream(stream))
+    proj_row = torch.empty(max(total.value, 1), dtype=torch.int32, device=dev)
+    _call("sgf_proj_layout", ctypes.byref(pc), n, _ptr(d_cols), _ptr(d_col_plan), _ptr(proj_off), _ptr(proj_row),
+          ctypes.byref(total), _stream(stream))
+    return Prepared(system, plan, d_cols, d_col_plan, proj_off, proj_row[:total.value], total.value)
+
+
+def _cplx_host(a) -> Optional[np.ndarray]:
+    if a is None:
+        return None
+    return np.ascontiguousarray(np.asarray(a, np.complex128)).view(np.float64)
+
+
+def solve_prepared(prep: Prepared, z, w=None, tol=1e-10, precision="fp64", max_iter=0, seed_index=-1,
+                   g_out=True, order=None, batch_cols=0, stage_lds=-1, grid=0, monitor_every=50, out=None,
+                   profile=False, shift_iters=False, stream=None) -> Result:
+    """Shifted COCG on every prepared column (asynchronous on the stream)."""
+    torch = _torch()
+    dev = prep.cols.device
+    n = prep.cols.numel()
+    zh = _cplx_host(z)
+    wh = _cplx_host(w)
+    ns = zh.size // 2
+    opts = SolveOptsC({"fp64": 0, "mixed": 1}[precision], float(tol), int(max_iter), int(seed_index),
+                      int(monitor_every), int(stage_lds), int(grid), int(bool(profile)), int(batch_cols))
+    sc = prep.system.c()
+    pc = prep.plan.c()
+    ws = ctypes.c_size_t()
+    _call("sgf_solve_workspace", ctypes.byref(sc), ctypes.byref(prep.plan.totals), n, ns, ctypes.byref(opts),
+          ctypes.byref(ws))
+    if out is None:
+        out = {
+            "ws": _bytes(ws.value, dev),
+            "G": torch.empty((max(prep.n_rows, 1), ns), dtype=torch.complex128, device=dev) if g_out else None,
+            "rho": torch.empty(max(prep.n_rows, 1), dtype=torch.float64, device=dev),
+            "iters": torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+            "status": torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+            "resid": torch.empty((max(n, 1), ns), dtype=torch.float64, device=dev),
+            "nk": torch.empty((max(n, 1), ns), dtype=torch.int32, device=dev) if shift_iters else None,
+        }
+    d_order = None if order is None else _dev(np.asarray(order, np.int32), torch.int32, dev)
+    out["order"] = d_order
+    _call("sgf_shifted_solve", ctypes.byref(sc), ctypes.byref(pc), ctypes.byref(prep.plan.totals), n,
+          _ptr(prep.cols), _ptr(prep.col_plan), _ptr(d_order), ns, zh.ctypes.data_as(P),
+          None if wh is None else wh.ctypes.data_as(P), ctypes.byref(opts), _ptr(out["ws"]), out["ws"].numel(),
+          _ptr(prep.proj_off), _ptr(out["G"]), _ptr(out["rho"]), _ptr(out["iters"]), _ptr(out["status"]),
+          _ptr(out["resid"]), _ptr(out.get("nk")), _stream(stream))
+    G = None if out["G"] is None else out["G"][:prep.n_rows]
+    res = Result(prep.proj_off, prep.proj_row, G, out["rho"][:prep.n_rows], out["iters"][:n], out["status"][:n],
+                 out["resid"][:n])
+    res.shift_iters = None if out.get("nk") is None else out["nk"][:n]
+    res._out = out  # keep buffers alive with the result
+    return res
+
+
+def solve_profile():
+    """(seed_ms, shift_ms, batches) of the last solve run with profile=True on this thread."""
+    a, b, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+    _call("sgf_solve_profile", ctypes.byref(a), ctypes.byref(b), ctypes.byref(n))
+    return a.value, b.value, n.value
+
+
+def shifted_solve(system: System, columns, z, w=None, tol=1e-10, radius=0.0, radius_per_col=None, prune=True,
+                  precision="fp64", max_iter=0, seed_index=-1, g_out=True, order=None, batch_cols=0, stage_lds=-1,
+                  grid=0, max_loc_atoms=2048, stream=None) -> Result:
+    """Green's-function elements and density-matrix entries for many columns.
+
+    columns: global orbital indices j; each is solved on the local subspace of
+    its atom (radius in nm; <= 0 means the whole system), pruned to the
+    connected component when ``prune``.  z, w: complex shifts and weights.
+    """
+    prep = prepare(system, columns, radius, radius_per_col, prune, max_loc_atoms, stream)
+    return solve_prepared(prep, z, w, tol, precision, max_iter, seed_index, g_out, order, batch_cols, stage_lds,
+                          grid, stream=stream)
+
+
+def solve_workload(wl, system: Optional[System] = None, cols=None, prune=True, **kw) -> Result:
+    """GPU solve of a workload from ``workloads`` (optionally a column subset)."""
+    system = system_for(wl) if system is None else system
+    rpc = wl.radius_per_col
+    if cols is None:
+        cols = wl.columns
+    else:
+        cols = np.asarray(cols, np.int64)
+        if rpc is not None:
+            pos = {int(j): i for i, j in enumerate(wl.columns)}
+            rpc = rpc[[pos[int(j)] for j in cols]]
+    kw.setdefault("tol", wl.tol)
+    return shifted_solve(system, cols, wl.z, wl.w, radius=wl.radius, radius_per_col=rpc, prune=prune, **kw)

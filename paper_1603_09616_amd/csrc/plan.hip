@@ -1,0 +1,446 @@
+// plan.hip -- local subspaces of the order-N solve.
+//
+// Each plan is the subspace of one centre atom c: the atoms within radius R
+// of c (Euclidean, FP64, no fused multiply-add in the distance), optionally
+// pruned to those connected to c through stored blocks inside that ball.  One
+// wavefront builds one plan in LDS: ball search through the spatial hash,
+// bitonic sort, frontier BFS for the pruning, then the local block-row
+// structure (local column atom + global block index) and the projection atoms.
+#include "build.hpp"
+
+namespace sgf {
+
+constexpr int PLAN_T = 64;
+
+enum : int64_t { PLAN_ERR_NONE = 0, PLAN_ERR_OVERFLOW = 1, PLAN_ERR_NOGEOM = 2, PLAN_ERR_CENTER = 3 };
+
+struct PlanMeta {
+    int64_t err;        // PLAN_ERR_*
+    int64_t err_plan;   // first failing plan (smallest index)
+    int64_t max_loc_atoms, max_loc_blocks, max_proj_atoms;
+};
+
+struct PlanLayout {
+    PlanMeta *meta;
+    char *scan;
+    size_t bytes;
+};
+
+static PlanLayout plan_layout(int64_t n_plans, void *base, size_t cap) {
+    PlanLayout L;
+    Carve c(base, cap);
+    L.meta = c.take<PlanMeta>(1);
+    L.scan = c.take<char>(prefix_scratch_bytes(n_plans + 1));
+    L.bytes = c.used;
+    return L;
+}
+
+__device__ __forceinline__ int bsearch_lds(const int32_t *v, int n, int32_t key) {
+    int lo = 0, hi = n - 1;
+    while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int32_t x = v[mid];
+        if (x == key) return mid;
+        if (x < key) lo = mid + 1; else hi = mid - 1;
+    }
+    return -1;
+}
+
+__device__ __forceinline__ void plan_fail(PlanMeta *m, int64_t code, int64_t p) {
+    atomicMax(reinterpret_cast<unsigned long long *>(&m->err), (unsigned long long)code);
+    atomicMin(reinterpret_cast<long long *>(&m->err_plan), (long long)p);
+}
+
+// Inclusive wavefront scan of an int (64 lanes).
+__device__ __forceinline__ int wave_scan_incl(int v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int u = __shfl_up(v, off, 64);
+        if (lane >= off) v += u;
+    }
+    return v;
+}
+
+struct PlanArgs {
+    int64_t n_plans, n_atoms;
+    const int32_t *center;
+    const double *radius;
+    int32_t prune;
+    const int32_t *row_ptr, *col;
+    const double *xyz;
+    BuildLayout B;  // spatial hash (valid when has_hash)
+    int has_hash;
+    int maxl;       // LDS capacity in atoms (power of two)
+    int64_t *atom_off, *blk_off, *pa_off;
+    int32_t *loc_atom, *lrow, *lblk, *pa_loc, *center_loc;
+    PlanMeta *meta;
+};
+
+template <bool FILL>
+__global__ __launch_bounds__(PLAN_T) void k_plan(PlanArgs a) {
+    extern __shared__ int32_t lds[];
+    int32_t *cand = lds;                 // [maxl]
+    int32_t *visit = lds + a.maxl;       // [maxl]
+    int32_t *queue = lds + 2 * a.maxl;   // [maxl]
+    int32_t *list = lds + 3 * a.maxl;    // [maxl]
+    __shared__ int s_n, s_tail, s_bad;
+    const int lane = threadIdx.x;
+    const int64_t p = blockIdx.x;
+    if (p >= a.n_plans) return;
+    const int32_t c = a.center[p];
+    const double R = a.radius[p];
+    if (c < 0 || c >= a.n_atoms) {
+        if (lane == 0) plan_fail(a.meta, PLAN_ERR_CENTER, p);
+        return;
+    }
+    if (lane == 0) { s_n = 0; s_bad = 0; }
+    __syncthreads();
+
+    // 1. Candidates: the ball around c, or every atom.
+    if (R <= 0.0) {
+        if (a.n_atoms > a.maxl) {
+            if (lane == 0) plan_fail(a.meta, PLAN_ERR_OVERFLOW, p);
+            return;
+        }
+        for (int i = lane; i < a.n_atoms; i += PLAN_T) cand[i] = i;
+        if (lane == 0) s_n = (int)a.n_atoms;
+        __syncthreads();
+    } else {
+        if (!a.has_hash || !a.xyz) {
+            if (lane == 0) plan_fail(a.meta, PLAN_ERR_NOGEOM, p);
+            return;
+        }
+        const double cell = a.B.hdr->cell;
+        const double *rc = &a.xyz[3 * (int64_t)c];
+        const int4 cc = cell_of(rc, cell);
+        const int m = (int)ceil(R / cell);
+        const int w = 2 * m + 1;
+        const int ncell = w * w * w;
+        const double R2 = R * R;
+        const uint32_t mask = (uint32_t)(a.B.nbuck - 1);
+        for (int ci = lane; ci < ncell; ci += PLAN_T) {
+            const int4 t = make_int4(cc.x + ci / (w * w) - m, cc.y + (ci / w) % w - m, cc.z + ci % w - m, 0);
+            const uint32_t b = hash_cell(t, mask);
+            for (int64_t i = a.B.bucket[b]; i < a.B.bucket[b + 1]; ++i) {
+                const int4 qc = a.B.sorted_cell[i];
+                if (qc.x != t.x || qc.y != t.y || qc.z != t.z) continue;
+                const int32_t q = a.B.sorted_atom[i];
+                if (dist2_exact(rc, &a.xyz[3 * (int64_t)q]) <= R2) {
+                    const int pos = atomicAdd(&s_n, 1);
+                    if (pos < a.maxl) cand[pos] = q;
+                }
+            }
+        }
+        __syncthreads();
+        if (s_n > a.maxl) {
+            if (lane == 0) plan_fail(a.meta, PLAN_ERR_OVERFLOW, p);
+            return;
+        }
+        // bitonic sort of cand[0..np) with INT_MAX padding
+        int np = 1;
+        while (np < s_n) np <<= 1;
+        for (int i = s_n + lane; i < np; i += PLAN_T) cand[i] = 0x7fffffff;
+        __syncthreads();
+        for (int k = 2; k <= np; k <<= 1)
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int i = lane; i < np; i += PLAN_T) {
+                    const int l = i ^ j;
+                    if (l > i) {
+                        const int32_t x = cand[i], y = cand[l];
+                        const bool up = (i & k) == 0;
+                        if ((x > y) == up) { cand[i] = y; cand[l] = x; }
+                    }
+                }
+                __syncthreads();
+            }
+    }
+    const int ncand = s_n;
+
+    // 2. Optional pruning to the connected component of c (frontier BFS).
+    int nloc;
+    if (a.prune) {
+        for (int i = lane; i < ncand; i += PLAN_T) visit[i] = 0;
+        __syncthreads();
+        if (lane == 0) {
+            const int ic = bsearch_lds(cand, ncand, c);
+            visit[ic] = 1;
+            queue[0] = ic;
+            s_tail = 1;
+        }
+        __syncthreads();
+        int head = 0;
+        while (true) {
+            const int tail = s_tail;
+            __syncthreads();
+            if (head == tail) break;
+            for (int e = head + lane; e < tail; e += PLAN_T) {
+                const int32_t at = cand[queue[e]];
+                for (int32_t t = a.row_ptr[at]; t < a.row_ptr[at + 1]; ++t) {
+                    const int jb = bsearch_lds(cand, ncand, a.col[t]);
+                    if (jb >= 0 && atomicCAS(&visit[jb], 0, 1) == 0) queue[atomicAdd(&s_tail, 1)] = jb;
+                }
+            }
+            head = tail;
+            __syncthreads();
+        }
+        // ordered compaction of the visited candidates
+        int base = 0;
+        for (int start = 0; start < ncand; start += PLAN_T) {
+            const int i = start + lane;
+            const int f = (i < ncand && visit[i]) ? 1 : 0;
+            const int incl = wave_scan_incl(f);
+            if (f) list[base + incl - 1] = cand[i];
+            base += __shfl(incl, 63, 64);
+        }
+        nloc = base;
+    } else {
+        for (int i = lane; i < ncand; i += PLAN_T) list[i] = cand[i];
+        nloc = ncand;
+    }
+    __syncthreads();
+
+    // 3. Local block rows and projection atoms.
+    const int64_t abase = FILL ? a.atom_off[p] : 0;
+    const int64_t bbase = FILL ? a.blk_off[p] : 0;
+    int carry = 0;
+    for (int start = 0; start < nloc; start += PLAN_T) {
+        const int A = start + lane;
+        int cnt = 0;
+        int32_t r0 = 0, r1 = 0;
+        if (A < nloc) {
+            r0 = a.row_ptr[list[A]];
+            r1 = a.row_ptr[list[A] + 1];
+            for (int32_t t = r0; t < r1; ++t) cnt += bsearch_lds(list, nloc, a.col[t]) >= 0;
+        }
+        const int incl = wave_scan_incl(cnt);
+        if (FILL && A < nloc) {
+            int pos = carry + incl - cnt;
+            a.loc_atom[abase + A] = list[A];
+            a.lrow[abase + A] = pos;
+            for (int32_t t = r0; t < r1; ++t) {
+                const int B = bsearch_lds(list, nloc, a.col[t]);
+                if (B >= 0) {
+                    a.lblk[2 * (bbase + pos)] = B;
+                    a.lblk[2 * (bbase + pos) + 1] = t;
+                    ++pos;
+                }
+            }
+        }
+        carry += __shfl(incl, 63, 64);
+    }
+    const int nblk = carry;
+    if (lane == 0) {
+        int npa = 0;
+        for (int32_t t = a.row_ptr[c]; t < a.row_ptr[c + 1]; ++t) {
+            const int B = bsearch_lds(list, nloc, a.col[t]);
+            if (B >= 0) {
+                if (FILL) a.pa_loc[a.pa_off[p] + npa] = B;
+                ++npa;
+            }
+        }
+        if (FILL) {
+            a.center_loc[p] = bsearch_lds(list, nloc, c);
+        } else {
+            a.atom_off[p + 1] = nloc;
+            a.blk_off[p + 1] = nblk;
+            a.pa_off[p + 1] = npa;
+            atomicMax(reinterpret_cast<unsigned long long *>(&a.meta->max_loc_atoms), (unsigned long long)nloc);
+            atomicMax(reinterpret_cast<unsigned long long *>(&a.meta->max_loc_blocks), (unsigned long long)nblk);
+            atomicMax(reinterpret_cast<unsigned long long *>(&a.meta->max_proj_atoms), (unsigned long long)npa);
+        }
+    }
+}
+
+__global__ void k_plan_init(PlanMeta *m, int64_t *atom_off, int64_t *blk_off, int64_t *pa_off) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        m->err = PLAN_ERR_NONE;
+        m->err_plan = INT64_MAX;
+        m->max_loc_atoms = m->max_loc_blocks = m->max_proj_atoms = 0;
+        atom_off[0] = blk_off[0] = pa_off[0] = 0;
+    }
+}
+
+static int maxl_pow2(int32_t max_loc_atoms) {
+    int m = 64;
+    while (m < max_loc_atoms) m <<= 1;
+    return m;
+}
+
+static sgf_status plan_args(const char *who, const sgf_system *sys, sgf_plan *plan, int32_t max_loc_atoms,
+                            const void *d_build_ws, size_t build_ws_bytes, void *d_ws, size_t ws_bytes, PlanArgs &a,
+                            PlanLayout &L) {
+    SGF_REQUIRE(sys && plan, "%s: NULL system or plan", who);
+    SGF_REQUIRE(sys->n_atoms > 0 && sys->row_ptr && sys->col, "%s: system has no block pattern", who);
+    SGF_REQUIRE(plan->n_plans >= 0 && (plan->n_plans == 0 || (plan->center && plan->radius)),
+                "%s: plan centres/radii missing", who);
+    SGF_REQUIRE(plan->atom_off && plan->blk_off && plan->pa_off, "%s: plan offsets are NULL", who);
+    SGF_REQUIRE(max_loc_atoms >= 1 && max_loc_atoms <= 8192, "%s: max_loc_atoms must be in [1, 8192]", who);
+    SGF_REQUIRE(d_ws, "%s: workspace is NULL", who);
+    L = plan_layout(plan->n_plans, d_ws, ws_bytes);
+    SGF_REQUIRE(L.bytes <= ws_bytes, "%s: workspace %zu bytes < %zu", who, ws_bytes, L.bytes);
+    a = PlanArgs{};
+    a.n_plans = plan->n_plans;
+    a.n_atoms = sys->n_atoms;
+    a.center = plan->center;
+    a.radius = plan->radius;
+    a.prune = plan->prune;
+    a.row_ptr = sys->row_ptr;
+    a.col = sys->col;
+    a.xyz = sys->xyz;
+    a.has_hash = d_build_ws != nullptr;
+    if (d_build_ws) {
+        a.B = build_layout(sys->n_atoms, const_cast<void *>(d_build_ws), build_ws_bytes);
+        SGF_REQUIRE(a.B.bytes <= build_ws_bytes, "%s: build workspace too small", who);
+    }
+    a.maxl = maxl_pow2(max_loc_atoms);
+    a.atom_off = plan->atom_off;
+    a.blk_off = plan->blk_off;
+    a.pa_off = plan->pa_off;
+    a.loc_atom = plan->loc_atom;
+    a.lrow = plan->lrow;
+    a.lblk = plan->lblk;
+    a.pa_loc = plan->pa_loc;
+    a.center_loc = plan->center_loc;
+    a.meta = L.meta;
+    return SGF_OK;
+}
+
+__global__ void k_proj_count(int64_t n_cols, int64_t n_plans, const int32_t *col_plan, const int64_t *pa_off,
+                             int64_t *proj_off) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c <= n_cols; c += (int64_t)gridDim.x * blockDim.x) {
+        if (c == 0) proj_off[0] = 0;
+        else {
+            const int32_t pl = col_plan[c - 1];
+            proj_off[c] = (pl >= 0 && pl < n_plans) ? 4 * (pa_off[pl + 1] - pa_off[pl]) : 0;
+        }
+    }
+}
+
+__global__ void k_proj_rows(int64_t n_cols, int64_t n_plans, const int32_t *col_plan, const int64_t *atom_off, const int64_t *pa_off,
+                            const int32_t *loc_atom, const int32_t *pa_loc, const int64_t *proj_off, int32_t *proj_row) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_cols; c += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t pl = col_plan[c];
+        if (pl < 0 || pl >= n_plans) continue;
+        const int64_t npa = pa_off[pl + 1] - pa_off[pl];
+        for (int64_t q = 0; q < npa; ++q) {
+            const int32_t atom = loc_atom[atom_off[pl] + pa_loc[pa_off[pl] + q]];
+            for (int o = 0; o < 4; ++o) proj_row[proj_off[c] + 4 * q + o] = 4 * atom + o;
+        }
+    }
+}
+
+}  // namespace sgf
+
+using namespace sgf;
+
+extern "C" sgf_status sgf_plan_workspace(const sgf_system *sys, int64_t n_plans, int32_t max_loc_atoms,
+                                         size_t *ws_bytes) {
+    SGF_REQUIRE(sys && ws_bytes && n_plans >= 0, "sgf_plan_workspace: bad arguments");
+    SGF_REQUIRE(max_loc_atoms >= 1 && max_loc_atoms <= 8192, "sgf_plan_workspace: max_loc_atoms out of range");
+    *ws_bytes = plan_layout(n_plans, nullptr, 0).bytes;
+    return SGF_OK;
+}
+
+extern "C" sgf_status sgf_plan_count(const sgf_system *sys, sgf_plan *plan, int32_t max_loc_atoms,
+                                     const void *d_build_ws, size_t build_ws_bytes, void *d_ws, size_t ws_bytes,
+                                     sgf_plan_totals *totals, void *stream) {
+    PlanArgs a;
+    PlanLayout L;
+    sgf_status rc = plan_args("sgf_plan_count", sys, plan, max_loc_atoms, d_build_ws, build_ws_bytes, d_ws, ws_bytes,
+                              a, L);
+    if (rc) return rc;
+    SGF_REQUIRE(totals, "sgf_plan_count: totals is NULL");
+    hipStream_t st = as_stream(stream);
+    k_plan_init<<<1, 64, 0, st>>>(L.meta, plan->atom_off, plan->blk_off, plan->pa_off);
+    SGF_LAUNCHED();
+    if (plan->n_plans > 0) {
+        const size_t lds = 4 * (size_t)a.maxl * sizeof(int32_t);
+        SGF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_plan<false>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        k_plan<false><<<dim3((unsigned)plan->n_plans), dim3(PLAN_T), lds, st>>>(a);
+        SGF_LAUNCHED();
+        for (int64_t *off : {plan->atom_off, plan->blk_off, plan->pa_off}) {
+            rc = inclusive_scan_i64(off + 1, plan->n_plans, L.scan, st);
+            if (rc) return rc;
+        }
+    }
+    PlanMeta m;
+    int64_t t3[3] = {0, 0, 0};
+    SGF_HIP(hipMemcpyAsync(&m, L.meta, sizeof(m), hipMemcpyDeviceToHost, st));
+    SGF_HIP(hipMemcpyAsync(&t3[0], plan->atom_off + plan->n_plans, 8, hipMemcpyDeviceToHost, st));
+    SGF_HIP(hipMemcpyAsync(&t3[1], plan->blk_off + plan->n_plans, 8, hipMemcpyDeviceToHost, st));
+    SGF_HIP(hipMemcpyAsync(&t3[2], plan->pa_off + plan->n_plans, 8, hipMemcpyDeviceToHost, st));
+    SGF_HIP(hipStreamSynchronize(st));
+    if (m.err == PLAN_ERR_OVERFLOW) {
+        set_error("sgf_plan_count: plan %lld holds more than max_loc_atoms=%d atoms", (long long)m.err_plan,
+                  max_loc_atoms);
+        return SGF_EUNSUPPORTED;
+    }
+    if (m.err == PLAN_ERR_CENTER) {
+        set_error("sgf_plan_count: plan %lld has a centre atom outside [0, n_atoms)", (long long)m.err_plan);
+        return SGF_EINVAL;
+    }
+    if (m.err == PLAN_ERR_NOGEOM) {
+        set_error("sgf_plan_count: plan %lld has a positive radius but no xyz / build workspace was given",
+                  (long long)m.err_plan);
+        return SGF_EINVAL;
+    }
+    if (t3[1] >= ((int64_t)1 << 31)) {
+        set_error("sgf_plan_count: %lld local blocks exceed int32 indexing; plan fewer centres per batch",
+                  (long long)t3[1]);
+        return SGF_EUNSUPPORTED;
+    }
+    totals->n_loc_atoms = t3[0];
+    totals->n_loc_blocks = t3[1];
+    totals->n_proj_atoms = t3[2];
+    totals->max_loc_atoms = (int32_t)m.max_loc_atoms;
+    totals->max_loc_blocks = (int32_t)m.max_loc_blocks;
+    totals->max_proj_atoms = (int32_t)m.max_proj_atoms;
+    totals->pad = 0;
+    return SGF_OK;
+}
+
+extern "C" sgf_status sgf_plan_build(const sgf_system *sys, sgf_plan *plan, int32_t max_loc_atoms,
+                                     const void *d_build_ws, size_t build_ws_bytes, void *d_ws, size_t ws_bytes,
+                                     void *stream) {
+    PlanArgs a;
+    PlanLayout L;
+    sgf_status rc = plan_args("sgf_plan_build", sys, plan, max_loc_atoms, d_build_ws, build_ws_bytes, d_ws, ws_bytes,
+                              a, L);
+    if (rc) return rc;
+    SGF_REQUIRE(plan->n_plans == 0 || (plan->loc_atom && plan->lrow && plan->lblk && plan->pa_loc && plan->center_loc),
+                "sgf_plan_build: plan output arrays are NULL");
+    if (plan->n_plans == 0) return SGF_OK;
+    const size_t lds = 4 * (size_t)a.maxl * sizeof(int32_t);
+    SGF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_plan<true>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds));
+    k_plan<true><<<dim3((unsigned)plan->n_plans), dim3(PLAN_T), lds, as_stream(stream)>>>(a);
+    SGF_LAUNCHED();
+    return SGF_OK;
+}
+
+extern "C" sgf_status sgf_proj_layout(const sgf_plan *plan, int64_t n_cols, const int64_t *d_cols,
+                                      const int32_t *d_col_plan, int64_t *d_proj_off, int32_t *d_proj_row,
+                                      int64_t *total_rows, void *stream) {
+    SGF_REQUIRE(plan && plan->pa_off && plan->atom_off, "sgf_proj_layout: plan offsets are NULL");
+    SGF_REQUIRE(n_cols >= 0 && (n_cols == 0 || (d_cols && d_col_plan)), "sgf_proj_layout: columns missing");
+    SGF_REQUIRE(d_proj_off && total_rows, "sgf_proj_layout: NULL output");
+    hipStream_t st = as_stream(stream);
+    const unsigned g = (unsigned)((n_cols + 256) / 256);
+    k_proj_count<<<g, 256, 0, st>>>(n_cols, plan->n_plans, d_col_plan, plan->pa_off, d_proj_off);
+    SGF_LAUNCHED();
+    if (n_cols > 0) {
+        sgf_status rc = inclusive_scan_one_block(d_proj_off + 1, n_cols, st);
+        if (rc) return rc;
+    }
+    if (d_proj_row && n_cols > 0) {
+        SGF_REQUIRE(plan->loc_atom && plan->pa_loc, "sgf_proj_layout: plan has not been built");
+        k_proj_rows<<<g, 256, 0, st>>>(n_cols, plan->n_plans, d_col_plan, plan->atom_off, plan->pa_off, plan->loc_atom, plan->pa_loc,
+                                       d_proj_off, d_proj_row);
+        SGF_LAUNCHED();
+    }
+    SGF_HIP(hipMemcpyAsync(total_rows, d_proj_off + n_cols, 8, hipMemcpyDeviceToHost, st));
+    SGF_HIP(hipStreamSynchronize(st));
+    return SGF_OK;
+}

@@ -1,0 +1,596 @@
+// scocg.hip -- shifted COCG for many columns in two passes.
+//
+// Seed pass (k_seed): one wavefront per column, pulling columns from a work
+// queue.  It runs COCG on the seed system z_s - H inside the column's local
+// subspace (vectors in LDS, wavefront DPP reductions, no workgroup barrier),
+// steps the collinearity factors pi^k of every shift only to decide when each
+// shift k has converged, and records per iteration 1/alpha_n and
+// beta_n/alpha_n together with the residual r_n restricted to the projection
+// rows P.
+//
+// Shift pass (k_shift): one workgroup per column, one lane per shift.  The
+// seed recurrences say (z_s - H) R = R T - r_N e^T / alpha_{N-1} with the
+// tridiagonal T (diagonal 1/alpha_n + beta_{n-1}/alpha_{n-1}, superdiagonal
+// -beta_n/alpha_n, subdiagonal -1/alpha_n), so the shifted Galerkin solution
+// after N_k steps is x^k = R y^k with (T_{N_k} + sigma_k) y^k = e_0.  Each lane
+// factors that tridiagonal from the bottom up (UL, no pivoting: T + sigma_k is
+// similar to z_k - T_L with T_L the real Lanczos matrix of H, whose trailing
+// minors cannot vanish for Im z_k > 0) and accumulates the rows of P by
+// Horner's rule on the way:  G^k_P = y_0 S_0,  S_m = r_{m,P} + g_{m+1} S_{m+1}.
+// Mathematically this is the x^k of the shifted recurrences of Frommer (2003)
+// / Takayama et al. (2006); it costs 8 flops per row and step instead of 22
+// and has no barriers, so the shift work streams at FP64 ALU rate.
+#include "scocg.hpp"
+
+#include <vector>
+
+namespace sgf {
+
+constexpr double INV_PI = 0.318309886183790671537767526745;
+constexpr int SEED_T = 64;   // seed pass: one wavefront per workgroup
+
+// ---------------------------------------------------------------------------
+// Seed pass
+// ---------------------------------------------------------------------------
+template <bool STAGE, int M>
+__global__ __launch_bounds__(SEED_T) void k_seed(SolveArgs a) {
+    extern __shared__ double4 lds4[];
+    char *lds = reinterpret_cast<char *>(lds4);
+    double2 *vp = reinterpret_cast<double2 *>(lds + a.off_p);
+    double2 *vs = reinterpret_cast<double2 *>(lds + a.off_s);
+    double2 *vw = reinterpret_cast<double2 *>(lds + a.off_w);
+    double *hs = reinterpret_cast<double *>(lds + a.off_hs);
+    int32_t *cs = reinterpret_cast<int32_t *>(lds + a.off_cs);
+    int32_t *rs = reinterpret_cast<int32_t *>(lds + a.off_rs);
+    const int lane = threadIdx.x;
+    const double2 zs = a.z[a.seed];
+    double2 sigma[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int k = lane + 64 * m;
+        sigma[m] = k < a.ns ? csub(a.z[k], zs) : make_double2(0.0, 0.0);
+    }
+    const double tol2 = a.tol * a.tol;
+
+    for (;;) {
+        int64_t ticket = 0;
+        if (lane == 0) ticket = (int64_t)atomicAdd(reinterpret_cast<unsigned long long *>(a.ticket), 1ull);
+        ticket = __shfl(ticket, 0, 64);
+        if (ticket >= a.batch_end - a.batch_begin) break;
+        const int64_t slot = ticket;
+        ticket += a.batch_begin;
+        const int64_t c = a.order ? (int64_t)a.order[ticket] : ticket;
+        ColMeta *meta = &a.meta[slot];
+        if (c < 0 || c >= a.n_cols) {
+            if (lane == 0) *meta = ColMeta{-1, 0, 0, SGF_BADCOLUMN};
+            continue;
+        }
+        const int64_t j = a.cols[c];
+        const int32_t pl = a.col_plan[c];
+        bool bad = pl < 0 || pl >= a.n_plans || j < 0;
+        int64_t a0 = 0, b0 = 0, p0 = 0;
+        int n_loc = 0, nblk = 0, npa = 0, cl = 0;
+        if (!bad) {
+            a0 = a.atom_off[pl];
+            n_loc = (int)(a.atom_off[pl + 1] - a0);
+            b0 = a.blk_off[pl];
+            nblk = (int)(a.blk_off[pl + 1] - b0);
+            p0 = a.pa_off[pl];
+            npa = (int)(a.pa_off[pl + 1] - p0);
+            cl = a.center_loc[pl];
+            bad = n_loc < 1 || n_loc > a.max_loc_atoms || npa < 1 || 4 * npa > a.rmax ||
+                  (STAGE && nblk > a.max_loc_blocks) || cl < 0 || cl >= n_loc ||
+                  a.loc_atom[a0 + cl] != (int32_t)(j >> 2);
+        }
+        if (bad) {
+            if (lane == 0) {
+                *meta = ColMeta{-1, 0, 0, SGF_BADCOLUMN};
+                a.iters[c] = 0;
+                a.status[c] = SGF_BADCOLUMN;
+            }
+            continue;
+        }
+        const int nl = 4 * n_loc;
+        const int jl = 4 * cl + (int)(j & 3);
+        const int nprow = 4 * npa;  // <= 32 (checked on the host)
+        const int prow = lane < nprow ? 4 * a.pa_loc[p0 + (lane >> 2)] + (lane & 3) : 0;
+        double2 *hab = a.hab + (size_t)slot * a.cap * 2;
+        double2 *hr = a.hr + (size_t)slot * (a.cap + 1) * a.rmax;
+
+        // start: x = 0, s_0 = p_0 = e_jl (S = I: r = s, q = p)
+        for (int i = lane; i < nl; i += SEED_T) {
+            const double2 v = make_double2(i == jl ? 1.0 : 0.0, 0.0);
+            vp[i] = v;
+            vs[i] = v;
+        }
+        if (STAGE) {
+            for (int e = lane; e < nblk * 16; e += SEED_T)
+                hs[e] = a.h[16 * (int64_t)a.lblk[2 * (b0 + (e >> 4)) + 1] + (e & 15)];
+            for (int t = lane; t < nblk; t += SEED_T) cs[t] = a.lblk[2 * (b0 + t)];
+            for (int A = lane; A <= n_loc; A += SEED_T) rs[A] = A < n_loc ? a.lrow[a0 + A] : nblk;
+        }
+        if (lane < nprow) hr[lane] = make_double2(prow == jl ? 1.0 : 0.0, 0.0);
+        __syncthreads();
+
+        double2 pc[M], po[M];
+        bool act[M];
+        int nkm[M];
+        double res[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            pc[m] = po[m] = make_double2(1.0, 0.0);
+            act[m] = lane + 64 * m < a.ns;
+            nkm[m] = 0;
+            res[m] = 1.0;
+        }
+        double2 rho = make_double2(1.0, 0.0);
+        double2 alpha_old = make_double2(1.0, 0.0), beta_old = make_double2(0.0, 0.0);
+        int status = SGF_MAXITER, iters = 0, applied = 0;
+        double snorm2 = 1.0;
+        const int max_iter = a.max_iter > 0 ? a.max_iter : 10 * nl;  // <= cap by construction
+
+        for (int it = 0; it < max_iter; ++it) {
+            // w = z_s p - H p ; mu = p^T w
+            double m0 = 0.0, m1 = 0.0;
+            for (int i = lane; i < nl; i += SEED_T) {
+                const int A = i >> 2, o = i & 3;
+                double ax = 0.0, ay = 0.0;
+                int t0, t1;
+                if (STAGE) { t0 = rs[A]; t1 = rs[A + 1]; }
+                else { t0 = a.lrow[a0 + A]; t1 = A + 1 < n_loc ? a.lrow[a0 + A + 1] : nblk; }
+                for (int t = t0; t < t1; ++t) {
+                    const double *hrow;
+                    int B;
+                    if (STAGE) { hrow = &hs[16 * t + 4 * o]; B = cs[t]; }
+                    else {
+                        B = a.lblk[2 * (b0 + t)];
+                        hrow = &a.h[16 * (int64_t)a.lblk[2 * (b0 + t) + 1] + 4 * o];
+                    }
+                    const double2 *pb = &vp[4 * B];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const double hv = hrow[q];
+                        const double2 pv = pb[q];
+                        ax = fma(hv, pv.x, ax);
+                        ay = fma(hv, pv.y, ay);
+                    }
+                }
+                const double2 pi_ = vp[i];
+                const double2 wi = make_double2(zs.x * pi_.x - zs.y * pi_.y - ax, zs.x * pi_.y + zs.y * pi_.x - ay);
+                vw[i] = wi;
+                m0 = fma(pi_.x, wi.x, fma(-pi_.y, wi.y, m0));
+                m1 = fma(pi_.x, wi.y, fma(pi_.y, wi.x, m1));
+            }
+            const double2 mu = make_double2(wave_reduce(m0), wave_reduce(m1));
+            iters = it + 1;
+            if (!cfinite(mu) || !cfinite(rho)) { status = SGF_NONFINITE; break; }
+            if (mu.x == 0.0 && mu.y == 0.0) { status = SGF_BREAKDOWN; break; }
+            const double2 alpha = cdiv(rho, mu);
+
+            // s -= alpha w ; rho' = s^T s ; ||s||^2
+            double r0 = 0.0, r1 = 0.0, r2 = 0.0;
+            for (int i = lane; i < nl; i += SEED_T) {
+                const double2 si = csub(vs[i], cmul(alpha, vw[i]));
+                vs[i] = si;
+                r0 = fma(si.x, si.x, fma(-si.y, si.y, r0));
+                r1 = fma(2.0 * si.x, si.y, r1);
+                r2 = fma(si.x, si.x, fma(si.y, si.y, r2));
+            }
+            const double2 rho_new = make_double2(wave_reduce(r0), wave_reduce(r1));
+            snorm2 = wave_reduce(r2);
+            const double2 ia = crcp(alpha);
+            const double2 beta = cmul(rho_new, crcp(rho));
+            for (int i = lane; i < nl; i += SEED_T) vp[i] = cfma(beta, vp[i], vs[i]);
+
+            // history of this step: 1/alpha_n, beta_n/alpha_n and r_{n+1} on P
+            if (lane == 0) {
+                hab[2 * it] = ia;
+                hab[2 * it + 1] = cmul(beta, ia);
+            }
+            __syncthreads();  // s and p of this step are in LDS for every lane
+            if (lane < nprow) hr[(size_t)(it + 1) * a.rmax + lane] = vs[prow];
+
+            // collinearity factors of the shifts; freeze test ||s|| <= tol |pi^k|
+            const double2 coup = cmul(cmul(alpha, beta_old), crcp(alpha_old));
+            int alive = 0;
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                if (!act[m]) continue;
+                const double2 pn = cadd(cmul(cfma(alpha, sigma[m], make_double2(1.0, 0.0)), pc[m]),
+                                        cmul(coup, csub(pc[m], po[m])));
+                po[m] = pc[m];
+                pc[m] = pn;
+                const double pn2 = fma(pn.x, pn.x, pn.y * pn.y);
+                if (snorm2 <= tol2 * pn2) {
+                    act[m] = false;
+                    nkm[m] = it + 1;
+                    res[m] = sqrt(snorm2 / pn2);
+                } else {
+                    alive = 1;
+                }
+            }
+            applied = it + 1;
+            alpha_old = alpha;
+            beta_old = beta;
+            rho = rho_new;
+            const bool any_alive = __any(alive);
+            if (!any_alive || snorm2 == 0.0) { status = SGF_CONVERGED; break; }
+            if (rho_new.x == 0.0 && rho_new.y == 0.0) { status = SGF_BREAKDOWN; break; }
+            if (!cfinite(rho_new) || !isfinite(snorm2)) { status = SGF_NONFINITE; break; }
+        }
+
+        // shifts still running took every applied update
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int k = lane + 64 * m;
+            if (k >= a.ns) continue;
+            if (act[m]) {
+                nkm[m] = applied;
+                const double pn2 = fma(pc[m].x, pc[m].x, pc[m].y * pc[m].y);
+                res[m] = applied > 0 ? sqrt(snorm2 / pn2) : 1.0;
+            }
+            a.nk[(size_t)slot * a.ns_pad + k] = nkm[m];
+            if (a.resid) a.resid[c * a.ns + k] = res[m];
+            if (a.shift_iters) a.shift_iters[c * a.ns + k] = nkm[m];
+        }
+        if (lane == 0) {
+            *meta = ColMeta{(int32_t)c, iters, npa, status};
+            a.iters[c] = iters;
+            a.status[c] = status;
+        }
+        __syncthreads();  // LDS reuse by the next column
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Shift pass
+// ---------------------------------------------------------------------------
+template <int NPA>
+__global__ __launch_bounds__(512) void k_shift(SolveArgs a) {
+    __shared__ double rpart[32 * 8];  // [row][wave] partial rho sums (rows <= 32, waves <= 8)
+    const int64_t slot = blockIdx.x;
+    const ColMeta meta = a.meta[slot];
+    if (meta.col < 0) return;  // uniform over the workgroup
+    const int64_t c = meta.col;
+    const int npa = meta.npa;
+    const int nrow = 4 * npa;
+    const int k = threadIdx.x;
+    const int wv = k >> 6, lane = k & 63, nwv = blockDim.x >> 6;
+    const bool live = k < a.ns;
+    const int nk = live ? a.nk[(size_t)slot * a.ns_pad + k] : 0;
+    const double2 sigma = live ? csub(a.z[k], a.z[a.seed]) : make_double2(0.0, 0.0);
+    const double2 *hab = a.hab + (size_t)slot * a.cap * 2;
+    const double2 *hr = a.hr + (size_t)slot * (a.cap + 1) * a.rmax;
+
+    // longest sweep in this wavefront
+    int top = nk;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) top = max(top, __shfl_xor(top, off, 64));
+
+    double2 S[4 * NPA];
+#pragma unroll
+    for (int r = 0; r < 4 * NPA; ++r) S[r] = make_double2(0.0, 0.0);
+    double2 g = make_double2(0.0, 0.0), y0 = make_double2(0.0, 0.0);
+    double2 ia_m = make_double2(0.0, 0.0), ba_m = make_double2(0.0, 0.0);
+    if (top > 0) {
+        ia_m = hab[2 * (top - 1)];
+        ba_m = hab[2 * (top - 1) + 1];
+    }
+    for (int m = top - 1; m >= 0; --m) {
+        // 1/alpha_{m-1}, beta_{m-1}/alpha_{m-1}
+        double2 ia_p = make_double2(0.0, 0.0), ba_p = make_double2(0.0, 0.0);
+        if (m > 0) {
+            ia_p = hab[2 * (m - 1)];
+            ba_p = hab[2 * (m - 1) + 1];
+        }
+        if (m < nk) {
+            const double2 diag = cadd(cadd(ia_m, ba_p), sigma);
+            const double2 d = (m == nk - 1) ? diag : csub(diag, cmul(ba_m, g));
+            const double2 *rm = hr + (size_t)m * a.rmax;
+#pragma unroll
+            for (int r = 0; r < 4 * NPA; ++r)
+                if (r < nrow) S[r] = cfma(g, S[r], rm[r]);
+            const double2 inv = crcp(d);
+            if (m > 0) g = cmul(ia_p, inv);
+            else y0 = inv;
+        }
+        ia_m = ia_p;
+        ba_m = ba_p;
+    }
+
+    // G rows and the density matrix rho_i = -(1/pi) sum_k Im(w_k G_i(z_k))
+    const double2 wk = (live && a.w) ? a.w[k] : make_double2(0.0, 0.0);
+    const int64_t out0 = a.proj_off[c];
+#pragma unroll
+    for (int r = 0; r < 4 * NPA; ++r) {
+        if (r >= nrow) continue;  // uniform
+        const double2 Gr = nk > 0 ? cmul(y0, S[r]) : make_double2(0.0, 0.0);
+        if (a.G && live) {
+            a.G[2 * ((out0 + r) * a.ns + k)] = Gr.x;
+            a.G[2 * ((out0 + r) * a.ns + k) + 1] = Gr.y;
+        }
+        const double t = wave_reduce(live ? fma(wk.x, Gr.y, wk.y * Gr.x) : 0.0);
+        if (lane == 0) rpart[r * 8 + wv] = t;
+    }
+    __syncthreads();
+    for (int r = k; r < nrow; r += blockDim.x) {
+        double acc = 0.0;
+        for (int v = 0; v < nwv; ++v) acc += rpart[r * 8 + v];
+        a.rho[out0 + r] = -acc * INV_PI;
+    }
+}
+
+__global__ void k_zero_ticket(int64_t *t) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *t = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------
+HistoryShape history_shape(const sgf_plan_totals &tot, int ns, const sgf_solve_opts &o) {
+    HistoryShape h;
+    h.ns_pad = (ns + 63) / 64 * 64;
+    const int nl_max = 4 * (tot.max_loc_atoms > 0 ? tot.max_loc_atoms : 1);
+    h.cap = o.max_iter > 0 ? o.max_iter : 10 * nl_max;
+    h.rmax = 4 * (tot.max_proj_atoms > 0 ? tot.max_proj_atoms : 1);
+    h.per_col = align_up(sizeof(ColMeta), 16) + align_up((size_t)h.ns_pad * 4, 16) + (size_t)h.cap * 32 +
+                (size_t)(h.cap + 1) * h.rmax * 16;
+    h.fixed = 4096 + 2 * align_up((size_t)ns * 16);
+    return h;
+}
+
+SolveLayout solve_layout(const HistoryShape &hs, int ns, int64_t slots, void *base, size_t cap) {
+    SolveLayout L;
+    Carve c(base, cap);
+    L.ticket = c.take<int64_t>(1);
+    L.z = c.take<double2>(ns);
+    L.w = c.take<double2>(ns);
+    L.meta = c.take<ColMeta>(slots);
+    L.nk = c.take<int32_t>((size_t)slots * hs.ns_pad);
+    L.hab = c.take<double2>((size_t)slots * hs.cap * 2);
+    L.hr = c.take<double2>((size_t)slots * (hs.cap + 1) * hs.rmax);
+    L.slots = slots;
+    L.bytes = c.used;
+    return L;
+}
+
+using KernelFn = void (*)(SolveArgs);
+
+// Events of the last profiled solve on this thread (seed start, seed end =
+// shift start, shift end per batch).
+struct Profile {
+    std::vector<hipEvent_t> events;
+    hipError_t add(hipEvent_t &e) {
+        hipError_t r = hipEventCreate(&e);
+        if (r == hipSuccess) events.push_back(e);
+        return r;
+    }
+    void release() {
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        events.clear();
+    }
+    ~Profile() { release(); }
+};
+static thread_local Profile g_profile;
+
+template <bool STAGE>
+static KernelFn pick_seed_m(int M) {
+    switch (M) {
+        case 1: return k_seed<STAGE, 1>;
+        case 2: return k_seed<STAGE, 2>;
+        case 3:
+        case 4: return k_seed<STAGE, 4>;
+        default: return k_seed<STAGE, 8>;
+    }
+}
+
+static KernelFn pick_seed(bool stage, int M) { return stage ? pick_seed_m<true>(M) : pick_seed_m<false>(M); }
+
+static KernelFn pick_shift(int npa) {
+    switch (npa) {
+        case 1: return k_shift<1>;
+        case 2: return k_shift<2>;
+        case 3: return k_shift<3>;
+        case 4: return k_shift<4>;
+        case 5: return k_shift<5>;
+        case 6: return k_shift<6>;
+        case 7: return k_shift<7>;
+        default: return k_shift<8>;
+    }
+}
+
+}  // namespace sgf
+
+using namespace sgf;
+
+extern "C" sgf_status sgf_solve_workspace(const sgf_system *sys, const sgf_plan_totals *totals, int64_t n_cols,
+                                          int32_t n_shifts, const sgf_solve_opts *opts, size_t *ws_bytes) {
+    SGF_REQUIRE(sys && totals && opts && ws_bytes, "sgf_solve_workspace: NULL argument");
+    SGF_REQUIRE(n_cols >= 0 && n_shifts >= 1, "sgf_solve_workspace: bad sizes");
+    const HistoryShape hs = history_shape(*totals, n_shifts, *opts);
+    int64_t slots = opts->batch_cols > 0 ? opts->batch_cols : n_cols;
+    if (slots > n_cols) slots = n_cols;
+    if (slots < 1) slots = 1;
+    *ws_bytes = solve_layout(hs, n_shifts, slots, nullptr, 0).bytes;
+    return SGF_OK;
+}
+
+extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *plan, const sgf_plan_totals *totals,
+                                        int64_t n_cols, const int64_t *d_cols, const int32_t *d_col_plan,
+                                        const int32_t *d_order, int32_t n_shifts, const double *z, const double *w,
+                                        const sgf_solve_opts *opts, void *d_ws, size_t ws_bytes,
+                                        const int64_t *d_proj_off, double *d_G, double *d_rho, int32_t *d_iters,
+                                        int32_t *d_status, double *d_resid, int32_t *d_shift_iters,
+                                        void *stream) {
+    SGF_REQUIRE(sys && plan && totals && opts, "sgf_shifted_solve: NULL system, plan, totals or options");
+    SGF_REQUIRE(sys->row_ptr && sys->col && sys->h && sys->n_atoms > 0, "sgf_shifted_solve: system incomplete");
+    SGF_REQUIRE(plan->atom_off && plan->blk_off && plan->pa_off && plan->loc_atom && plan->lrow && plan->lblk &&
+                    plan->pa_loc && plan->center_loc,
+                "sgf_shifted_solve: plan has not been built");
+    SGF_REQUIRE(n_cols >= 0, "sgf_shifted_solve: n_cols < 0");
+    SGF_REQUIRE(n_cols == 0 || (d_cols && d_col_plan && d_proj_off && d_rho && d_iters && d_status),
+                "sgf_shifted_solve: NULL column or output array");
+    SGF_REQUIRE(n_shifts >= 1, "sgf_shifted_solve: n_shifts must be >= 1");
+    SGF_REQUIRE(z, "sgf_shifted_solve: z is NULL");
+    SGF_REQUIRE(opts->tol > 0, "sgf_shifted_solve: tol must be positive");
+    SGF_REQUIRE(opts->precision == 0 || opts->precision == 1, "sgf_shifted_solve: precision must be 0 or 1");
+    SGF_REQUIRE(opts->max_iter >= 0, "sgf_shifted_solve: max_iter must be >= 0");
+    const int seed = opts->seed_index < 0 ? n_shifts / 2 : opts->seed_index;
+    SGF_REQUIRE(seed < n_shifts, "sgf_shifted_solve: seed_index %d >= n_shifts %d", seed, n_shifts);
+    for (int kk = 0; kk < n_shifts; ++kk)
+        SGF_REQUIRE(z[2 * kk + 1] > 0, "sgf_shifted_solve: Im z[%d] = %g is not positive", kk, z[2 * kk + 1]);
+    if (n_shifts > 512) {
+        set_error("sgf_shifted_solve: %d shifts (limit 512)", n_shifts);
+        return SGF_EUNSUPPORTED;
+    }
+    if (totals->max_proj_atoms > 8) {
+        set_error("sgf_shifted_solve: a column has %d projection atoms (limit 8)", totals->max_proj_atoms);
+        return SGF_EUNSUPPORTED;
+    }
+    if (sys->s) {
+        set_error("sgf_shifted_solve: the generalized (S != I) path is not built into this library");
+        return SGF_EUNSUPPORTED;
+    }
+    if (opts->precision == 1) {
+        set_error("sgf_shifted_solve: the mixed-precision path is not built into this library");
+        return SGF_EUNSUPPORTED;
+    }
+    SGF_REQUIRE(d_ws, "sgf_shifted_solve: workspace is NULL");
+    const HistoryShape hs = history_shape(*totals, n_shifts, *opts);
+    const SolveLayout L1 = solve_layout(hs, n_shifts, 1, nullptr, 0);
+    SGF_REQUIRE(L1.bytes <= ws_bytes, "sgf_shifted_solve: workspace %zu bytes < %zu (one column)", ws_bytes, L1.bytes);
+    if (n_cols == 0) return SGF_OK;
+    // as many history slots as the workspace holds
+    int64_t slots = (int64_t)((ws_bytes - L1.bytes) / (hs.per_col + 1024)) + 1;
+    if (slots > n_cols) slots = n_cols;
+    SolveLayout L = solve_layout(hs, n_shifts, slots, d_ws, ws_bytes);
+    while (L.bytes > ws_bytes && slots > 1) L = solve_layout(hs, n_shifts, --slots, d_ws, ws_bytes);
+    hipStream_t st = as_stream(stream);
+    SGF_HIP(hipMemcpyAsync(L.z, z, 16 * (size_t)n_shifts, hipMemcpyHostToDevice, st));
+    if (w) SGF_HIP(hipMemcpyAsync(L.w, w, 16 * (size_t)n_shifts, hipMemcpyHostToDevice, st));
+
+    SolveArgs a{};
+    a.row_ptr = sys->row_ptr;
+    a.col = sys->col;
+    a.h = sys->h;
+    a.atom_off = plan->atom_off;
+    a.blk_off = plan->blk_off;
+    a.pa_off = plan->pa_off;
+    a.loc_atom = plan->loc_atom;
+    a.lrow = plan->lrow;
+    a.lblk = plan->lblk;
+    a.pa_loc = plan->pa_loc;
+    a.center_loc = plan->center_loc;
+    a.n_plans = plan->n_plans;
+    a.max_loc_atoms = totals->max_loc_atoms;
+    a.max_loc_blocks = totals->max_loc_blocks;
+    a.npa_max = totals->max_proj_atoms;
+    a.n_cols = n_cols;
+    a.cols = d_cols;
+    a.col_plan = d_col_plan;
+    a.order = d_order;
+    a.ns = n_shifts;
+    a.ns_pad = hs.ns_pad;
+    a.seed = seed;
+    a.z = L.z;
+    a.w = w ? L.w : nullptr;
+    a.tol = opts->tol;
+    a.max_iter = opts->max_iter;
+    a.proj_off = d_proj_off;
+    a.G = d_G;
+    a.rho = d_rho;
+    a.resid = d_resid;
+    a.iters = d_iters;
+    a.status = d_status;
+    a.shift_iters = d_shift_iters;
+    a.cap = hs.cap;
+    a.rmax = hs.rmax;
+    a.meta = L.meta;
+    a.nk = L.nk;
+    a.hab = L.hab;
+    a.hr = L.hr;
+    a.ticket = L.ticket;
+
+    // seed-pass LDS: p, s, w vectors and (optionally) the staged local operator
+    const int nl = 4 * (totals->max_loc_atoms > 0 ? totals->max_loc_atoms : 1);
+    const int blk = totals->max_loc_blocks > 0 ? totals->max_loc_blocks : 1;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t r = off; off = align_up(off + bytes, 16); return r; };
+    a.off_p = take((size_t)nl * 16);
+    a.off_s = take((size_t)nl * 16);
+    a.off_w = take((size_t)nl * 16);
+    const size_t lds_plain = off;
+    a.off_hs = take((size_t)blk * 128);
+    a.off_cs = take((size_t)blk * 4);
+    a.off_rs = take((size_t)(totals->max_loc_atoms + 1) * 4);
+    const size_t lds_staged = off;
+    const bool stage = opts->stage_lds == 1 || (opts->stage_lds < 0 && lds_staged <= 16 * 1024);
+    const size_t lds = stage ? lds_staged : lds_plain;
+    if (lds > 160 * 1024) {
+        set_error("sgf_shifted_solve: a local subspace of %d atoms needs %zu bytes of LDS (limit 163840)",
+                  totals->max_loc_atoms, lds);
+        return SGF_EUNSUPPORTED;
+    }
+    const int M = hs.ns_pad / 64;
+    KernelFn seed_fn = pick_seed(stage, M);
+    KernelFn shift_fn = pick_shift(totals->max_proj_atoms);
+    SGF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(seed_fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds));
+    int per_cu = 0;
+    SGF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(seed_fn), SEED_T,
+                                                         lds));
+    if (per_cu < 1) {
+        set_error("sgf_shifted_solve: seed kernel does not fit a compute unit (LDS %zu)", lds);
+        return SGF_EUNSUPPORTED;
+    }
+    int dev = 0, n_cu = 0;
+    SGF_HIP(hipGetDevice(&dev));
+    SGF_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    const int64_t seed_grid_max = opts->grid > 0 ? opts->grid : (int64_t)per_cu * n_cu;
+
+    Profile &prof = g_profile;
+    prof.release();
+    const bool timed = opts->profile != 0;
+    for (int64_t b0 = 0; b0 < n_cols; b0 += slots) {
+        const int64_t b1 = b0 + slots < n_cols ? b0 + slots : n_cols;
+        a.batch_begin = b0;
+        a.batch_end = b1;
+        const int64_t grid = seed_grid_max < b1 - b0 ? seed_grid_max : b1 - b0;
+        k_zero_ticket<<<1, 64, 0, st>>>(L.ticket);
+        SGF_LAUNCHED();
+        hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+        if (timed) {
+            SGF_HIP(prof.add(e0));
+            SGF_HIP(prof.add(e1));
+            SGF_HIP(prof.add(e2));
+            SGF_HIP(hipEventRecord(e0, st));
+        }
+        hipLaunchKernelGGL(seed_fn, dim3((unsigned)grid), dim3(SEED_T), lds, st, a);
+        SGF_LAUNCHED();
+        if (timed) SGF_HIP(hipEventRecord(e1, st));
+        hipLaunchKernelGGL(shift_fn, dim3((unsigned)(b1 - b0)), dim3(hs.ns_pad), 0, st, a);
+        SGF_LAUNCHED();
+        if (timed) SGF_HIP(hipEventRecord(e2, st));
+    }
+    return SGF_OK;
+}
+
+extern "C" sgf_status sgf_solve_profile(double *seed_ms, double *shift_ms, int32_t *batches) {
+    SGF_REQUIRE(seed_ms && shift_ms && batches, "sgf_solve_profile: NULL argument");
+    Profile &prof = g_profile;
+    SGF_REQUIRE(!prof.events.empty(), "sgf_solve_profile: no profiled solve is pending on this thread");
+    double t_seed = 0.0, t_shift = 0.0;
+    for (size_t i = 0; i + 2 < prof.events.size(); i += 3) {
+        float a = 0.f, b = 0.f;
+        SGF_HIP(hipEventSynchronize(prof.events[i + 2]));
+        SGF_HIP(hipEventElapsedTime(&a, prof.events[i], prof.events[i + 1]));
+        SGF_HIP(hipEventElapsedTime(&b, prof.events[i + 1], prof.events[i + 2]));
+        t_seed += a;
+        t_shift += b;
+    }
+    *seed_ms = t_seed;
+    *shift_ms = t_shift;
+    *batches = (int32_t)(prof.events.size() / 3);
+    prof.release();
+    return SGF_OK;
+}

@@ -1,0 +1,72 @@
+// scocg.hpp -- argument blocks, workspace layout and launch configuration of
+// the two-pass shifted-COCG solver.
+#pragma once
+
+#include "common.hpp"
+
+namespace sgf {
+
+// Column metadata written by the seed pass for the shift pass.
+struct ColMeta {
+    int32_t col;     // column index (-1: slot unused or rejected)
+    int32_t iters;   // seed iterations performed
+    int32_t npa;     // projection atoms
+    int32_t status;  // sgf_col_status
+};
+
+struct SolveArgs {
+    // system (device)
+    const int32_t *row_ptr, *col;
+    const double *h;
+    // plan (device)
+    const int64_t *atom_off, *blk_off, *pa_off;
+    const int32_t *loc_atom, *lrow, *lblk, *pa_loc, *center_loc;
+    int64_t n_plans;
+    int max_loc_atoms, max_loc_blocks, npa_max;
+    // columns
+    int64_t n_cols;
+    const int64_t *cols;
+    const int32_t *col_plan;
+    const int32_t *order;
+    int64_t batch_begin, batch_end;  // ticket range of this batch
+    // shifts
+    int ns, ns_pad, seed;
+    const double2 *z, *w;
+    double tol;
+    int max_iter;       // per column; <= 0: 10 * (local orbitals)
+    // outputs
+    const int64_t *proj_off;
+    double *G, *rho, *resid;
+    int32_t *iters, *status, *shift_iters;
+    // history (per batch slot)
+    int cap;            // recorded iterations per slot (max_iter of the batch)
+    int rmax;           // projection rows per slot (4 * npa_max)
+    ColMeta *meta;      // [slots]
+    int32_t *nk;        // [slots][ns_pad] freeze iteration of every shift
+    double2 *hab;       // [slots][cap][2]: 1/alpha_n, beta_n/alpha_n
+    double2 *hr;        // [slots][cap+1][rmax]: projected residuals r_n on P
+    int64_t *ticket;
+    // seed-pass LDS carve (bytes)
+    size_t off_p, off_s, off_w, off_hs, off_cs, off_rs;
+};
+
+struct SolveLayout {
+    int64_t *ticket;
+    double2 *z, *w;
+    ColMeta *meta;
+    int32_t *nk;
+    double2 *hab, *hr;
+    int64_t slots;
+    size_t bytes;
+};
+
+// History capacity and per-column bytes for a solve.
+struct HistoryShape {
+    int cap, rmax, ns_pad;
+    size_t per_col, fixed;
+};
+
+HistoryShape history_shape(const sgf_plan_totals &tot, int ns, const sgf_solve_opts &o);
+SolveLayout solve_layout(const HistoryShape &hs, int ns, int64_t slots, void *base, size_t cap);
+
+}  // namespace sgf

@@ -210,13 +210,18 @@ def chain_workload(n_sites: int = 2000, n_columns: int = 16, n_shifts: int = 64,
 def bundle_workload(n_grid_x: int = 13, n_grid_y: int = 13, atoms_per_chain: int = 700, *,
                     n_chains: Optional[int] = None, n_shifts: int = 128, radius: float = 1.0,
                     overlap: bool = False, radius_range=None, columns: Optional[np.ndarray] = None,
-                    n_columns: Optional[int] = None, config_no: int = 2, tol: float = 1e-10,
+                    n_columns: Optional[int] = None, config_no: int = 2, tol: float = 1e-12,
                     e_window=BUNDLE_WINDOW, eta: float = ETA) -> Workload:
     """Polymer-bundle-like sp tight binding (4 orbitals per atom).
 
     columns: explicit global orbital indices; otherwise ``n_columns`` drawn
     without replacement (stream 1), otherwise every orbital.
     radius_range: (lo, hi) draws a per-column radius U[lo, hi] (stream 2).
+    tol defaults to 1e-12: a shift frozen at relative residual tol carries an
+    error up to tol/eta in G, and the density matrix sums G over ~N_s/2 shifts
+    near resonances, so a 1e-10 relative accuracy on every G_ij and rho_ij
+    needs the tolerance two decades below it (measured against the dense
+    restricted solve: rho error 2e-10 at tol 1e-11, 4e-11 at 1e-12).
     """
     xyz = bundle_xyz(n_grid_x, n_grid_y, atoms_per_chain, n_chains=n_chains, config_no=config_no)
     n_orb = 4 * xyz.shape[0]
