@@ -60,6 +60,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-g", action="store_true", help="skip writing G (rho only)")
+    ap.add_argument("--shifts-per-lane", type=int, default=0)
     args = ap.parse_args(argv)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: every run of this path uses a single MI355X; columns are "
@@ -92,7 +93,8 @@ def main(argv=None):
         s = sgf.build_hamiltonian(d_xyz, wl.tb, device=dev)
         prep = sgf.prepare_planned(s, d_cols, d_cp, d_centers, d_radii, prune=True)
         res = sgf.solve_prepared(prep, wl.z, wl.w, tol=wl.tol, g_out=not args.no_g, batch_cols=args.batch,
-                                 out=out_buf.get("out"), profile=profile, shift_iters=True)
+                                 out=out_buf.get("out"), profile=profile, shift_iters=True,
+                                 shifts_per_lane=args.shifts_per_lane)
         out_buf["out"] = res._out
         return s, prep, res
 

@@ -179,7 +179,8 @@ typedef struct {
     int64_t n_loc_atoms;   /* atom_off[n_plans] */
     int64_t n_loc_blocks;  /* blk_off[n_plans] */
     int64_t n_proj_atoms;  /* pa_off[n_plans] */
-    int32_t max_loc_atoms, max_loc_blocks, max_proj_atoms, pad;
+    int32_t max_loc_atoms, max_loc_blocks, max_proj_atoms;
+    int32_t max_row_blocks; /* most local blocks in one local block row */
 } sgf_plan_totals;
 
 /* Scratch bytes for planning n_plans centres with at most max_loc_atoms
@@ -211,10 +212,14 @@ typedef struct {
     int32_t max_iter;      /* <= 0: 10 * (local orbitals) per column */
     int32_t seed_index;    /* < 0: n_shifts / 2 */
     int32_t monitor_every; /* mixed: FP64 true residual every K iterations (0: only at the end) */
-    int32_t stage_lds;     /* 1: copy each local operator to LDS; 0: read it from global; -1: auto */
+    int32_t stage_lds;     /* seed pass: -1 auto (register rows for subspaces of <= 64 orbitals and
+                              <= 8 blocks per row, else an LDS-staged operator when it fits);
+                              1 LDS-staged operator; 0 operator read from global */
     int32_t grid;          /* seed-pass persistent workgroups; 0: fill the device */
     int32_t profile;       /* 1: record HIP events around each pass (read with sgf_solve_profile) */
     int64_t batch_cols;    /* columns per history batch for sgf_solve_workspace (0: all) */
+    int32_t shifts_per_lane; /* shift pass: 1 or 2 shifts per lane; 0: chosen from the projection size */
+    int32_t reserved;
 } sgf_solve_opts;
 
 /* Output offsets: d_proj_off[c+1] - d_proj_off[c] = 4 * |P(plan of column c)|

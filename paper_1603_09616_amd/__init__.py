@@ -56,12 +56,13 @@ class PlanC(ctypes.Structure):
 
 class PlanTotalsC(ctypes.Structure):
     _fields_ = [("n_loc_atoms", i64), ("n_loc_blocks", i64), ("n_proj_atoms", i64), ("max_loc_atoms", i32),
-                ("max_loc_blocks", i32), ("max_proj_atoms", i32), ("pad", i32)]
+                ("max_loc_blocks", i32), ("max_proj_atoms", i32), ("max_row_blocks", i32)]
 
 
 class SolveOptsC(ctypes.Structure):
     _fields_ = [("precision", i32), ("tol", dbl), ("max_iter", i32), ("seed_index", i32), ("monitor_every", i32),
-                ("stage_lds", i32), ("grid", i32), ("profile", i32), ("batch_cols", i64)]
+                ("stage_lds", i32), ("grid", i32), ("profile", i32), ("batch_cols", i64),
+                ("shifts_per_lane", i32), ("reserved", i32)]
 
 
 _lib = None
@@ -353,7 +354,7 @@ def _cplx_host(a) -> Optional[np.ndarray]:
 
 def solve_prepared(prep: Prepared, z, w=None, tol=1e-10, precision="fp64", max_iter=0, seed_index=-1,
                    g_out=True, order=None, batch_cols=0, stage_lds=-1, grid=0, monitor_every=50, out=None,
-                   profile=False, shift_iters=False, stream=None) -> Result:
+                   profile=False, shift_iters=False, shifts_per_lane=0, stream=None) -> Result:
     """Shifted COCG on every prepared column (asynchronous on the stream)."""
     torch = _torch()
     dev = prep.cols.device
@@ -362,7 +363,8 @@ def solve_prepared(prep: Prepared, z, w=None, tol=1e-10, precision="fp64", max_i
     wh = _cplx_host(w)
     ns = zh.size // 2
     opts = SolveOptsC({"fp64": 0, "mixed": 1}[precision], float(tol), int(max_iter), int(seed_index),
-                      int(monitor_every), int(stage_lds), int(grid), int(bool(profile)), int(batch_cols))
+                      int(monitor_every), int(stage_lds), int(grid), int(bool(profile)), int(batch_cols),
+                      int(shifts_per_lane), 0)
     sc = prep.system.c()
     pc = prep.plan.c()
     ws = ctypes.c_size_t()
@@ -402,7 +404,7 @@ def solve_profile():
 
 def shifted_solve(system: System, columns, z, w=None, tol=1e-10, radius=0.0, radius_per_col=None, prune=True,
                   precision="fp64", max_iter=0, seed_index=-1, g_out=True, order=None, batch_cols=0, stage_lds=-1,
-                  grid=0, max_loc_atoms=2048, stream=None) -> Result:
+                  grid=0, max_loc_atoms=2048, shifts_per_lane=0, stream=None) -> Result:
     """Green's-function elements and density-matrix entries for many columns.
 
     columns: global orbital indices j; each is solved on the local subspace of
@@ -411,7 +413,7 @@ def shifted_solve(system: System, columns, z, w=None, tol=1e-10, radius=0.0, rad
     """
     prep = prepare(system, columns, radius, radius_per_col, prune, max_loc_atoms, stream)
     return solve_prepared(prep, z, w, tol, precision, max_iter, seed_index, g_out, order, batch_cols, stage_lds,
-                          grid, stream=stream)
+                          grid, shifts_per_lane=shifts_per_lane, stream=stream)
 
 
 def solve_workload(wl, system: Optional[System] = None, cols=None, prune=True, **kw) -> Result:

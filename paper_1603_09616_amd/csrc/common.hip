@@ -98,23 +98,34 @@ sgf_status inclusive_scan_i64(int64_t *d_data, int64_t n, void *d_scratch, hipSt
     return SGF_OK;
 }
 
-// One workgroup, in place, chunk by chunk with a running carry.
+// One workgroup, in place, tile by tile (SCAN_TILE items, SCAN_ITEMS
+// consecutive items per thread) with a running carry.
 __global__ __launch_bounds__(SCAN_T) void k_scan_one_block(int64_t *data, int64_t n) {
     __shared__ int64_t part[SCAN_T];
     __shared__ int64_t carry;
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
-    for (int64_t start = 0; start < n; start += SCAN_T) {
-        const int64_t i = start + threadIdx.x;
-        part[threadIdx.x] = i < n ? data[i] : 0;
+    for (int64_t start = 0; start < n; start += SCAN_TILE) {
+        const int64_t base = start + (int64_t)threadIdx.x * SCAN_ITEMS;
+        int64_t v[SCAN_ITEMS];
+        int64_t run = 0;
+#pragma unroll
+        for (int i = 0; i < SCAN_ITEMS; ++i) {
+            run += (base + i < n) ? data[base + i] : 0;
+            v[i] = run;
+        }
+        part[threadIdx.x] = run;
         __syncthreads();
         for (int off = 1; off < SCAN_T; off <<= 1) {
-            int64_t add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+            const int64_t add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
             __syncthreads();
             part[threadIdx.x] += add;
             __syncthreads();
         }
-        if (i < n) data[i] = carry + part[threadIdx.x];
+        const int64_t prefix = carry + (threadIdx.x > 0 ? part[threadIdx.x - 1] : 0);
+#pragma unroll
+        for (int i = 0; i < SCAN_ITEMS; ++i)
+            if (base + i < n) data[base + i] = v[i] + prefix;
         __syncthreads();
         if (threadIdx.x == SCAN_T - 1) carry += part[SCAN_T - 1];
         __syncthreads();

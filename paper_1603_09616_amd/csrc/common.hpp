@@ -100,6 +100,18 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // ---------------------------------------------------------------------------
+// LDS ordering inside one wavefront: every LDS access issued before this point
+// has completed (lgkmcnt(0)) and the compiler keeps memory accesses on their
+// side of it.  Unlike __syncthreads() it does not wait for outstanding global
+// loads or stores (vmcnt) and it involves no other wavefront.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_lds_fence() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // gfx9 encoding: vmcnt=63, expcnt=7, lgkmcnt=0
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// ---------------------------------------------------------------------------
 // DPP wavefront reduction (CDNA row operations).  The partial sums climb to
 // the last lane of each 16-lane row (row_shr 1, 2, 4, 8), rows 1 and 3 add
 // row 0 / row 2 (row_bcast15), rows 2 and 3 add lane 31 (row_bcast31); lane 63

@@ -17,7 +17,7 @@ enum : int64_t { PLAN_ERR_NONE = 0, PLAN_ERR_OVERFLOW = 1, PLAN_ERR_NOGEOM = 2, 
 struct PlanMeta {
     int64_t err;        // PLAN_ERR_*
     int64_t err_plan;   // first failing plan (smallest index)
-    int64_t max_loc_atoms, max_loc_blocks, max_proj_atoms;
+    int64_t max_loc_atoms, max_loc_blocks, max_proj_atoms, max_row_blocks;
 };
 
 struct PlanLayout {
@@ -97,75 +97,25 @@ __global__ __launch_bounds__(PLAN_T) void k_plan(PlanArgs a) {
     if (lane == 0) { s_n = 0; s_bad = 0; }
     __syncthreads();
 
-    // 1. Candidates: the ball around c, or every atom.
-    if (R <= 0.0) {
-        if (a.n_atoms > a.maxl) {
-            if (lane == 0) plan_fail(a.meta, PLAN_ERR_OVERFLOW, p);
-            return;
-        }
-        for (int i = lane; i < a.n_atoms; i += PLAN_T) cand[i] = i;
-        if (lane == 0) s_n = (int)a.n_atoms;
-        __syncthreads();
-    } else {
-        if (!a.has_hash || !a.xyz) {
+    int nloc;
+    if (a.prune && R > 0.0) {
+        // Connected component of c inside the ball, found by a breadth-first
+        // search along stored blocks that admits only atoms within R of c; the
+        // ball itself is never enumerated.  Visited atoms go to an open-addressing
+        // hash set in LDS (2 * maxl slots, i.e. cand and visit together).
+        if (!a.xyz) {
             if (lane == 0) plan_fail(a.meta, PLAN_ERR_NOGEOM, p);
             return;
         }
-        const double cell = a.B.hdr->cell;
+        int32_t *hset = cand;  // 2 * maxl slots (cand and visit are adjacent)
+        const uint32_t hmask = (uint32_t)(2 * a.maxl - 1);
+        for (int i = lane; i < 2 * a.maxl; i += PLAN_T) hset[i] = -1;
+        __syncthreads();
         const double *rc = &a.xyz[3 * (int64_t)c];
-        const int4 cc = cell_of(rc, cell);
-        const int m = (int)ceil(R / cell);
-        const int w = 2 * m + 1;
-        const int ncell = w * w * w;
         const double R2 = R * R;
-        const uint32_t mask = (uint32_t)(a.B.nbuck - 1);
-        for (int ci = lane; ci < ncell; ci += PLAN_T) {
-            const int4 t = make_int4(cc.x + ci / (w * w) - m, cc.y + (ci / w) % w - m, cc.z + ci % w - m, 0);
-            const uint32_t b = hash_cell(t, mask);
-            for (int64_t i = a.B.bucket[b]; i < a.B.bucket[b + 1]; ++i) {
-                const int4 qc = a.B.sorted_cell[i];
-                if (qc.x != t.x || qc.y != t.y || qc.z != t.z) continue;
-                const int32_t q = a.B.sorted_atom[i];
-                if (dist2_exact(rc, &a.xyz[3 * (int64_t)q]) <= R2) {
-                    const int pos = atomicAdd(&s_n, 1);
-                    if (pos < a.maxl) cand[pos] = q;
-                }
-            }
-        }
-        __syncthreads();
-        if (s_n > a.maxl) {
-            if (lane == 0) plan_fail(a.meta, PLAN_ERR_OVERFLOW, p);
-            return;
-        }
-        // bitonic sort of cand[0..np) with INT_MAX padding
-        int np = 1;
-        while (np < s_n) np <<= 1;
-        for (int i = s_n + lane; i < np; i += PLAN_T) cand[i] = 0x7fffffff;
-        __syncthreads();
-        for (int k = 2; k <= np; k <<= 1)
-            for (int j = k >> 1; j > 0; j >>= 1) {
-                for (int i = lane; i < np; i += PLAN_T) {
-                    const int l = i ^ j;
-                    if (l > i) {
-                        const int32_t x = cand[i], y = cand[l];
-                        const bool up = (i & k) == 0;
-                        if ((x > y) == up) { cand[i] = y; cand[l] = x; }
-                    }
-                }
-                __syncthreads();
-            }
-    }
-    const int ncand = s_n;
-
-    // 2. Optional pruning to the connected component of c (frontier BFS).
-    int nloc;
-    if (a.prune) {
-        for (int i = lane; i < ncand; i += PLAN_T) visit[i] = 0;
-        __syncthreads();
         if (lane == 0) {
-            const int ic = bsearch_lds(cand, ncand, c);
-            visit[ic] = 1;
-            queue[0] = ic;
+            hset[((uint32_t)c * 2654435761u) & hmask] = c;
+            queue[0] = c;
             s_tail = 1;
         }
         __syncthreads();
@@ -173,30 +123,154 @@ __global__ __launch_bounds__(PLAN_T) void k_plan(PlanArgs a) {
         while (true) {
             const int tail = s_tail;
             __syncthreads();
-            if (head == tail) break;
+            if (head == tail || tail > a.maxl) break;
             for (int e = head + lane; e < tail; e += PLAN_T) {
-                const int32_t at = cand[queue[e]];
+                const int32_t at = queue[e];
                 for (int32_t t = a.row_ptr[at]; t < a.row_ptr[at + 1]; ++t) {
-                    const int jb = bsearch_lds(cand, ncand, a.col[t]);
-                    if (jb >= 0 && atomicCAS(&visit[jb], 0, 1) == 0) queue[atomicAdd(&s_tail, 1)] = jb;
+                    const int32_t b = a.col[t];
+                    if (dist2_exact(rc, &a.xyz[3 * (int64_t)b]) > R2) continue;
+                    // Stop inserting once maxl atoms are in: with at most 63 concurrent
+                    // inserts after this check the set holds < maxl + 64 <= 2 * maxl atoms,
+                    // so the probe below always finds an empty slot.
+                    if (atomicAdd(&s_tail, 0) >= a.maxl) break;
+                    uint32_t h = ((uint32_t)b * 2654435761u) & hmask;
+                    while (true) {
+                        const int32_t prev = atomicCAS(&hset[h], -1, b);
+                        if (prev == -1) {
+                            const int pos = atomicAdd(&s_tail, 1);
+                            if (pos < a.maxl) queue[pos] = b;
+                            break;
+                        }
+                        if (prev == b) break;
+                        h = (h + 1) & hmask;
+                    }
                 }
             }
             head = tail;
             __syncthreads();
         }
-        // ordered compaction of the visited candidates
-        int base = 0;
-        for (int start = 0; start < ncand; start += PLAN_T) {
-            const int i = start + lane;
-            const int f = (i < ncand && visit[i]) ? 1 : 0;
-            const int incl = wave_scan_incl(f);
-            if (f) list[base + incl - 1] = cand[i];
-            base += __shfl(incl, 63, 64);
+        if (s_tail > a.maxl) {
+            if (lane == 0) plan_fail(a.meta, PLAN_ERR_OVERFLOW, p);
+            return;
         }
-        nloc = base;
+        nloc = s_tail;
+        // sort the component (bitonic, INT_MAX padding) into list
+        int np = 1;
+        while (np < nloc) np <<= 1;
+        for (int i = lane; i < np; i += PLAN_T) list[i] = i < nloc ? queue[i] : 0x7fffffff;
+        __syncthreads();
+        for (int k = 2; k <= np; k <<= 1)
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int i = lane; i < np; i += PLAN_T) {
+                    const int l = i ^ j;
+                    if (l > i) {
+                        const int32_t x = list[i], y = list[l];
+                        if ((x > y) == ((i & k) == 0)) { list[i] = y; list[l] = x; }
+                    }
+                }
+                __syncthreads();
+            }
     } else {
-        for (int i = lane; i < ncand; i += PLAN_T) list[i] = cand[i];
-        nloc = ncand;
+        // 1. Candidates: the ball around c, or every atom.
+        if (R <= 0.0) {
+            if (a.n_atoms > a.maxl) {
+                if (lane == 0) plan_fail(a.meta, PLAN_ERR_OVERFLOW, p);
+                return;
+            }
+            for (int i = lane; i < a.n_atoms; i += PLAN_T) cand[i] = i;
+            if (lane == 0) s_n = (int)a.n_atoms;
+            __syncthreads();
+        } else {
+            if (!a.has_hash || !a.xyz) {
+                if (lane == 0) plan_fail(a.meta, PLAN_ERR_NOGEOM, p);
+                return;
+            }
+            const double cell = a.B.hdr->cell;
+            const double *rc = &a.xyz[3 * (int64_t)c];
+            const int4 cc = cell_of(rc, cell);
+            const int m = (int)ceil(R / cell);
+            const int w = 2 * m + 1;
+            const int ncell = w * w * w;
+            const double R2 = R * R;
+            const uint32_t mask = (uint32_t)(a.B.nbuck - 1);
+            for (int ci = lane; ci < ncell; ci += PLAN_T) {
+                const int4 t = make_int4(cc.x + ci / (w * w) - m, cc.y + (ci / w) % w - m, cc.z + ci % w - m, 0);
+                const uint32_t b = hash_cell(t, mask);
+                for (int64_t i = a.B.bucket[b]; i < a.B.bucket[b + 1]; ++i) {
+                    const int4 qc = a.B.sorted_cell[i];
+                    if (qc.x != t.x || qc.y != t.y || qc.z != t.z) continue;
+                    const int32_t q = a.B.sorted_atom[i];
+                    if (dist2_exact(rc, &a.xyz[3 * (int64_t)q]) <= R2) {
+                        const int pos = atomicAdd(&s_n, 1);
+                        if (pos < a.maxl) cand[pos] = q;
+                    }
+                }
+            }
+            __syncthreads();
+            if (s_n > a.maxl) {
+                if (lane == 0) plan_fail(a.meta, PLAN_ERR_OVERFLOW, p);
+                return;
+            }
+            // bitonic sort of cand[0..np) with INT_MAX padding
+            int np = 1;
+            while (np < s_n) np <<= 1;
+            for (int i = s_n + lane; i < np; i += PLAN_T) cand[i] = 0x7fffffff;
+            __syncthreads();
+            for (int k = 2; k <= np; k <<= 1)
+                for (int j = k >> 1; j > 0; j >>= 1) {
+                    for (int i = lane; i < np; i += PLAN_T) {
+                        const int l = i ^ j;
+                        if (l > i) {
+                            const int32_t x = cand[i], y = cand[l];
+                            const bool up = (i & k) == 0;
+                            if ((x > y) == up) { cand[i] = y; cand[l] = x; }
+                        }
+                    }
+                    __syncthreads();
+                }
+        }
+        const int ncand = s_n;
+
+        // 2. Optional pruning to the connected component of c (frontier BFS).
+        if (a.prune) {
+            for (int i = lane; i < ncand; i += PLAN_T) visit[i] = 0;
+            __syncthreads();
+            if (lane == 0) {
+                const int ic = bsearch_lds(cand, ncand, c);
+                visit[ic] = 1;
+                queue[0] = ic;
+                s_tail = 1;
+            }
+            __syncthreads();
+            int head = 0;
+            while (true) {
+                const int tail = s_tail;
+                __syncthreads();
+                if (head == tail) break;
+                for (int e = head + lane; e < tail; e += PLAN_T) {
+                    const int32_t at = cand[queue[e]];
+                    for (int32_t t = a.row_ptr[at]; t < a.row_ptr[at + 1]; ++t) {
+                        const int jb = bsearch_lds(cand, ncand, a.col[t]);
+                        if (jb >= 0 && atomicCAS(&visit[jb], 0, 1) == 0) queue[atomicAdd(&s_tail, 1)] = jb;
+                    }
+                }
+                head = tail;
+                __syncthreads();
+            }
+            // ordered compaction of the visited candidates
+            int base = 0;
+            for (int start = 0; start < ncand; start += PLAN_T) {
+                const int i = start + lane;
+                const int f = (i < ncand && visit[i]) ? 1 : 0;
+                const int incl = wave_scan_incl(f);
+                if (f) list[base + incl - 1] = cand[i];
+                base += __shfl(incl, 63, 64);
+            }
+            nloc = base;
+        } else {
+            for (int i = lane; i < ncand; i += PLAN_T) list[i] = cand[i];
+            nloc = ncand;
+        }
     }
     __syncthreads();
 
@@ -214,6 +288,8 @@ __global__ __launch_bounds__(PLAN_T) void k_plan(PlanArgs a) {
             for (int32_t t = r0; t < r1; ++t) cnt += bsearch_lds(list, nloc, a.col[t]) >= 0;
         }
         const int incl = wave_scan_incl(cnt);
+        if (!FILL && cnt > 0)
+            atomicMax(reinterpret_cast<unsigned long long *>(&a.meta->max_row_blocks), (unsigned long long)cnt);
         if (FILL && A < nloc) {
             int pos = carry + incl - cnt;
             a.loc_atom[abase + A] = list[A];
@@ -256,7 +332,7 @@ __global__ void k_plan_init(PlanMeta *m, int64_t *atom_off, int64_t *blk_off, in
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         m->err = PLAN_ERR_NONE;
         m->err_plan = INT64_MAX;
-        m->max_loc_atoms = m->max_loc_blocks = m->max_proj_atoms = 0;
+        m->max_loc_atoms = m->max_loc_blocks = m->max_proj_atoms = m->max_row_blocks = 0;
         atom_off[0] = blk_off[0] = pa_off[0] = 0;
     }
 }
@@ -397,7 +473,7 @@ extern "C" sgf_status sgf_plan_count(const sgf_system *sys, sgf_plan *plan, int3
     totals->max_loc_atoms = (int32_t)m.max_loc_atoms;
     totals->max_loc_blocks = (int32_t)m.max_loc_blocks;
     totals->max_proj_atoms = (int32_t)m.max_proj_atoms;
-    totals->pad = 0;
+    totals->max_row_blocks = (int32_t)m.max_row_blocks;
     return SGF_OK;
 }
 

@@ -110,7 +110,7 @@ __global__ __launch_bounds__(SEED_T) void k_seed(SolveArgs a) {
             for (int A = lane; A <= n_loc; A += SEED_T) rs[A] = A < n_loc ? a.lrow[a0 + A] : nblk;
         }
         if (lane < nprow) hr[lane] = make_double2(prow == jl ? 1.0 : 0.0, 0.0);
-        __syncthreads();
+        wave_lds_fence();
 
         double2 pc[M], po[M];
         bool act[M];
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(SEED_T) void k_seed(SolveArgs a) {
                 hab[2 * it] = ia;
                 hab[2 * it + 1] = cmul(beta, ia);
             }
-            __syncthreads();  // s and p of this step are in LDS for every lane
+            wave_lds_fence();  // s and p of this step are in LDS for every lane
             if (lane < nprow) hr[(size_t)(it + 1) * a.rmax + lane] = vs[prow];
 
             // collinearity factors of the shifts; freeze test ||s|| <= tol |pi^k|
@@ -238,82 +238,347 @@ __global__ __launch_bounds__(SEED_T) void k_seed(SolveArgs a) {
             a.iters[c] = iters;
             a.status[c] = status;
         }
-        __syncthreads();  // LDS reuse by the next column
+        wave_lds_fence();  // LDS reuse by the next column
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Seed pass, register variant for local subspaces of at most 64 orbitals:
+// lane i owns row i; s, w, p and the row's blocks of H (with their local
+// columns) stay in registers for the whole column, p is mirrored in LDS for
+// the neighbour reads of the block product, and each iteration needs two
+// complex reciprocals (1/mu and 1/rho') instead of four divisions.
+// ---------------------------------------------------------------------------
+template <int M, int BMAX>
+__global__ __launch_bounds__(SEED_T) void k_seed_r1(SolveArgs a) {
+    __shared__ double2 vp[64];
+    const int lane = threadIdx.x;
+    const double2 zs = a.z[a.seed];
+    double2 sigma[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int k = lane + 64 * m;
+        sigma[m] = k < a.ns ? csub(a.z[k], zs) : make_double2(0.0, 0.0);
+    }
+    const double tol2 = a.tol * a.tol;
+    const double2 zero = make_double2(0.0, 0.0), one = make_double2(1.0, 0.0);
+
+    for (;;) {
+        int64_t ticket = 0;
+        if (lane == 0) ticket = (int64_t)atomicAdd(reinterpret_cast<unsigned long long *>(a.ticket), 1ull);
+        ticket = __shfl(ticket, 0, 64);
+        if (ticket >= a.batch_end - a.batch_begin) break;
+        const int64_t slot = ticket;
+        ticket += a.batch_begin;
+        const int64_t c = a.order ? (int64_t)a.order[ticket] : ticket;
+        ColMeta *meta = &a.meta[slot];
+        if (c < 0 || c >= a.n_cols) {
+            if (lane == 0) *meta = ColMeta{-1, 0, 0, SGF_BADCOLUMN};
+            continue;
+        }
+        const int64_t j = a.cols[c];
+        const int32_t pl = a.col_plan[c];
+        bool bad = pl < 0 || pl >= a.n_plans || j < 0;
+        int64_t a0 = 0, b0 = 0, p0 = 0;
+        int n_loc = 0, nblk = 0, npa = 0, cl = 0;
+        if (!bad) {
+            a0 = a.atom_off[pl];
+            n_loc = (int)(a.atom_off[pl + 1] - a0);
+            b0 = a.blk_off[pl];
+            nblk = (int)(a.blk_off[pl + 1] - b0);
+            p0 = a.pa_off[pl];
+            npa = (int)(a.pa_off[pl + 1] - p0);
+            cl = a.center_loc[pl];
+            bad = n_loc < 1 || n_loc > 16 || npa < 1 || 4 * npa > a.rmax || cl < 0 || cl >= n_loc ||
+                  a.loc_atom[a0 + cl] != (int32_t)(j >> 2);
+        }
+        // this lane's row: its blocks and local columns
+        const int nl = 4 * n_loc;
+        const int A = lane >> 2, o = lane & 3;
+        const bool row = !bad && lane < nl;
+        int nb = 0, t0 = 0;
+        if (row) {
+            t0 = a.lrow[a0 + A];
+            nb = (A + 1 < n_loc ? a.lrow[a0 + A + 1] : nblk) - t0;
+        }
+        bad = bad || __any(nb > BMAX);
+        if (bad) {
+            if (lane == 0) {
+                *meta = ColMeta{-1, 0, 0, SGF_BADCOLUMN};
+                a.iters[c] = 0;
+                a.status[c] = SGF_BADCOLUMN;
+            }
+            continue;
+        }
+        int bcol[BMAX];
+        double hrow[BMAX][4];
+#pragma unroll
+        for (int b = 0; b < BMAX; ++b) {
+            bcol[b] = 0;
+            hrow[b][0] = hrow[b][1] = hrow[b][2] = hrow[b][3] = 0.0;
+            if (b < nb) {
+                const int32_t *lb = &a.lblk[2 * (b0 + t0 + b)];
+                bcol[b] = 4 * lb[0];
+                const double *hb = &a.h[16 * (int64_t)lb[1] + 4 * o];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) hrow[b][q] = hb[q];
+            }
+        }
+        const int jl = 4 * cl + (int)(j & 3);
+        int pidx = -1;  // position of this lane's row among the projection rows
+        for (int q = 0; q < npa; ++q)
+            if (row && a.pa_loc[p0 + q] == A) pidx = 4 * q + o;
+        double2 *hab = a.hab + (size_t)slot * a.cap * 2;
+        double2 *hr = a.hr + (size_t)slot * (a.cap + 1) * a.rmax;
+
+        // start: x = 0, s_0 = p_0 = e_jl
+        double2 s = (row && lane == jl) ? one : zero, p = s;
+        vp[lane] = p;
+        if (pidx >= 0) hr[pidx] = s;
+        wave_lds_fence();
+
+        double2 pc[M], po[M];
+        bool act[M];
+        int nkm[M];
+        double res[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            pc[m] = po[m] = one;
+            act[m] = lane + 64 * m < a.ns;
+            nkm[m] = 0;
+            res[m] = 1.0;
+        }
+        double2 rho = one, inv_rho = one;
+        double2 alpha_old = one, beta_old = zero, ia_old = one;
+        int status = SGF_MAXITER, iters = 0, applied = 0;
+        double snorm2 = 1.0;
+        const int max_iter = a.max_iter > 0 ? a.max_iter : 10 * nl;
+
+        for (int it = 0; it < max_iter; ++it) {
+            // w = z_s p - H p ; mu = p^T w
+            double ax = 0.0, ay = 0.0;
+#pragma unroll
+            for (int b = 0; b < BMAX; ++b) {
+                if (b < nb) {
+                    const double2 *pb = &vp[bcol[b]];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const double2 pv = pb[q];
+                        ax = fma(hrow[b][q], pv.x, ax);
+                        ay = fma(hrow[b][q], pv.y, ay);
+                    }
+                }
+            }
+            const double2 w = make_double2(zs.x * p.x - zs.y * p.y - ax, zs.x * p.y + zs.y * p.x - ay);
+            const double2 mu = make_double2(wave_reduce(fma(p.x, w.x, -p.y * w.y)),
+                                            wave_reduce(fma(p.x, w.y, p.y * w.x)));
+            iters = it + 1;
+            if (!cfinite(mu) || !cfinite(rho)) { status = SGF_NONFINITE; break; }
+            if (mu.x == 0.0 && mu.y == 0.0) { status = SGF_BREAKDOWN; break; }
+            const double2 alpha = cmul(rho, crcp(mu));
+            const double2 ia = cmul(mu, inv_rho);  // 1/alpha
+
+            // s -= alpha w ; rho' = s^T s ; ||s||^2
+            s = csub(s, cmul(alpha, w));
+            const double2 rho_new = make_double2(wave_reduce(fma(s.x, s.x, -s.y * s.y)),
+                                                 wave_reduce(2.0 * s.x * s.y));
+            snorm2 = wave_reduce(fma(s.x, s.x, s.y * s.y));
+            const double2 beta = cmul(rho_new, inv_rho);
+            p = cfma(beta, p, s);
+            vp[lane] = p;
+
+            // history: 1/alpha_n, beta_n/alpha_n, r_{n+1} on P
+            if (lane == 0) {
+                hab[2 * it] = ia;
+                hab[2 * it + 1] = cmul(beta, ia);
+            }
+            if (pidx >= 0) hr[(size_t)(it + 1) * a.rmax + pidx] = s;
+
+            // collinearity factors; freeze test ||s|| <= tol |pi^k|
+            const double2 coup = cmul(cmul(alpha, beta_old), ia_old);
+            int alive = 0;
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                if (!act[m]) continue;
+                const double2 pn = cadd(cmul(cfma(alpha, sigma[m], one), pc[m]), cmul(coup, csub(pc[m], po[m])));
+                po[m] = pc[m];
+                pc[m] = pn;
+                const double pn2 = fma(pn.x, pn.x, pn.y * pn.y);
+                if (snorm2 <= tol2 * pn2) {
+                    act[m] = false;
+                    nkm[m] = it + 1;
+                    res[m] = sqrt(snorm2 / pn2);
+                } else {
+                    alive = 1;
+                }
+            }
+            applied = it + 1;
+            alpha_old = alpha;
+            beta_old = beta;
+            ia_old = ia;
+            rho = rho_new;
+            wave_lds_fence();  // p is in LDS for the next block product
+            const bool any_alive = __any(alive);
+            if (!any_alive || snorm2 == 0.0) { status = SGF_CONVERGED; break; }
+            if (rho_new.x == 0.0 && rho_new.y == 0.0) { status = SGF_BREAKDOWN; break; }
+            if (!cfinite(rho_new) || !isfinite(snorm2)) { status = SGF_NONFINITE; break; }
+            inv_rho = crcp(rho_new);
+        }
+
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int k = lane + 64 * m;
+            if (k >= a.ns) continue;
+            if (act[m]) {
+                nkm[m] = applied;
+                const double pn2 = fma(pc[m].x, pc[m].x, pc[m].y * pc[m].y);
+                res[m] = applied > 0 ? sqrt(snorm2 / pn2) : 1.0;
+            }
+            a.nk[(size_t)slot * a.ns_pad + k] = nkm[m];
+            if (a.resid) a.resid[c * a.ns + k] = res[m];
+            if (a.shift_iters) a.shift_iters[c * a.ns + k] = nkm[m];
+        }
+        if (lane == 0) {
+            *meta = ColMeta{(int32_t)c, iters, npa, status};
+            a.iters[c] = iters;
+            a.status[c] = status;
+        }
+        wave_lds_fence();  // vp reuse by the next column
     }
 }
 
 // ---------------------------------------------------------------------------
 // Shift pass
 // ---------------------------------------------------------------------------
-template <int NPA>
+constexpr int SHIFT_CH = 16;  // backward steps staged in LDS at a time
+
+// One workgroup per column; each lane carries MS shifts.  The shifts are
+// first sorted by their step count N_k so that the lanes of a wavefront (and
+// the MS shifts of a lane) end their sweeps together.
+template <int NPA, int MS>
 __global__ __launch_bounds__(512) void k_shift(SolveArgs a) {
-    __shared__ double rpart[32 * 8];  // [row][wave] partial rho sums (rows <= 32, waves <= 8)
+    __shared__ double2 sab[SHIFT_CH + 1][2];       // 1/alpha, beta/alpha of steps lo-1 .. hi
+    __shared__ double2 srow[SHIFT_CH][4 * NPA];    // r_m on P for steps lo .. hi
+    __shared__ int skey[512];                      // (N_k << 10) | k, sorted ascending
+    __shared__ double rpart[32 * 8];               // [row][wave] partial rho sums
     const int64_t slot = blockIdx.x;
     const ColMeta meta = a.meta[slot];
     if (meta.col < 0) return;  // uniform over the workgroup
     const int64_t c = meta.col;
     const int npa = meta.npa;
     const int nrow = 4 * npa;
-    const int k = threadIdx.x;
-    const int wv = k >> 6, lane = k & 63, nwv = blockDim.x >> 6;
-    const bool live = k < a.ns;
-    const int nk = live ? a.nk[(size_t)slot * a.ns_pad + k] : 0;
-    const double2 sigma = live ? csub(a.z[k], a.z[a.seed]) : make_double2(0.0, 0.0);
+    const int tid = threadIdx.x, T = blockDim.x;
+    const int wv = tid >> 6, lane = tid & 63, nwv = T >> 6;
     const double2 *hab = a.hab + (size_t)slot * a.cap * 2;
     const double2 *hr = a.hr + (size_t)slot * (a.cap + 1) * a.rmax;
+    const double2 zero = make_double2(0.0, 0.0);
 
-    // longest sweep in this wavefront
-    int top = nk;
+    // sort the shifts of this column by step count (bitonic, power-of-two length)
+    int nsort = 64;
+    while (nsort < a.ns_pad) nsort <<= 1;
+    constexpr int SENT = 0x7fffffff;
+    for (int i = tid; i < 512; i += T)
+        skey[i] = i < a.ns ? (a.nk[(size_t)slot * a.ns_pad + i] << 10) | i : (i < a.ns_pad ? i : SENT);
+    __syncthreads();
+    for (int kk = 2; kk <= nsort; kk <<= 1)
+        for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+            for (int i = tid; i < nsort; i += T) {
+                const int l = i ^ jj;
+                if (l > i) {
+                    const int x = skey[i], y = skey[l];
+                    if ((x > y) == ((i & kk) == 0)) { skey[i] = y; skey[l] = x; }
+                }
+            }
+            __syncthreads();
+        }
+    int kof[MS], nk[MS];
+    double2 sigma[MS];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) top = max(top, __shfl_xor(top, off, 64));
-
-    double2 S[4 * NPA];
-#pragma unroll
-    for (int r = 0; r < 4 * NPA; ++r) S[r] = make_double2(0.0, 0.0);
-    double2 g = make_double2(0.0, 0.0), y0 = make_double2(0.0, 0.0);
-    double2 ia_m = make_double2(0.0, 0.0), ba_m = make_double2(0.0, 0.0);
-    if (top > 0) {
-        ia_m = hab[2 * (top - 1)];
-        ba_m = hab[2 * (top - 1) + 1];
+    for (int u = 0; u < MS; ++u) {
+        const int key = skey[tid * MS + u];
+        const bool live = key != SENT && (key & 1023) < a.ns;
+        kof[u] = live ? (key & 1023) : -1;
+        nk[u] = live ? (key >> 10) : 0;
+        sigma[u] = live ? csub(a.z[kof[u]], a.z[a.seed]) : zero;
     }
-    for (int m = top - 1; m >= 0; --m) {
-        // 1/alpha_{m-1}, beta_{m-1}/alpha_{m-1}
-        double2 ia_p = make_double2(0.0, 0.0), ba_p = make_double2(0.0, 0.0);
-        if (m > 0) {
-            ia_p = hab[2 * (m - 1)];
-            ba_p = hab[2 * (m - 1) + 1];
-        }
-        if (m < nk) {
-            const double2 diag = cadd(cadd(ia_m, ba_p), sigma);
-            const double2 d = (m == nk - 1) ? diag : csub(diag, cmul(ba_m, g));
-            const double2 *rm = hr + (size_t)m * a.rmax;
+    const int top = skey[a.ns_pad - 1] >> 10;  // largest N_k (ns_pad - ns padding keys sort first)
+    int wtop = 0;  // largest N_k in this wavefront
 #pragma unroll
-            for (int r = 0; r < 4 * NPA; ++r)
-                if (r < nrow) S[r] = cfma(g, S[r], rm[r]);
-            const double2 inv = crcp(d);
-            if (m > 0) g = cmul(ia_p, inv);
-            else y0 = inv;
+    for (int u = 0; u < MS; ++u) wtop = max(wtop, nk[u]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) wtop = max(wtop, __shfl_xor(wtop, off, 64));
+
+    double2 S[MS][4 * NPA];
+    double2 g[MS], y0[MS];
+#pragma unroll
+    for (int u = 0; u < MS; ++u) {
+        g[u] = y0[u] = zero;
+#pragma unroll
+        for (int r = 0; r < 4 * NPA; ++r) S[u][r] = zero;
+    }
+    for (int hi = top - 1; hi >= 0; hi -= SHIFT_CH) {
+        const int lo = hi - SHIFT_CH + 1 > 0 ? hi - SHIFT_CH + 1 : 0;
+        const int nstep = hi - lo + 1;
+        __syncthreads();  // the previous chunk has been consumed
+        for (int idx = tid; idx < (nstep + 1) * 2; idx += T) {
+            const int m = lo - 1 + (idx >> 1);
+            sab[idx >> 1][idx & 1] = m >= 0 ? hab[2 * m + (idx & 1)] : zero;
         }
-        ia_m = ia_p;
-        ba_m = ba_p;
+        for (int idx = tid; idx < nstep * nrow; idx += T) {
+            const int sm = idx / nrow, r = idx - sm * nrow;
+            srow[sm][r] = hr[(size_t)(lo + sm) * a.rmax + r];
+        }
+        __syncthreads();
+        if (lo >= wtop) continue;  // nothing for this wavefront in this chunk
+        double2 ia_m = sab[hi - lo + 1][0], ba_m = sab[hi - lo + 1][1];
+        for (int m = hi; m >= lo; --m) {
+            const double2 ia_p = sab[m - lo][0], ba_p = sab[m - lo][1];
+            const double2 *rm = srow[m - lo];
+#pragma unroll
+            for (int u = 0; u < MS; ++u) {
+                if (m >= nk[u]) continue;
+                const double2 diag = cadd(cadd(ia_m, ba_p), sigma[u]);
+                const double2 d = (m == nk[u] - 1) ? diag : csub(diag, cmul(ba_m, g[u]));
+#pragma unroll
+                for (int q = 0; q < NPA; ++q) {
+                    if (q < npa) {
+#pragma unroll
+                        for (int o = 0; o < 4; ++o) S[u][4 * q + o] = cfma(g[u], S[u][4 * q + o], rm[4 * q + o]);
+                    }
+                }
+                const double2 inv = crcp(d);
+                if (m > 0) g[u] = cmul(ia_p, inv);
+                else y0[u] = inv;
+            }
+            ia_m = ia_p;
+            ba_m = ba_p;
+        }
     }
 
     // G rows and the density matrix rho_i = -(1/pi) sum_k Im(w_k G_i(z_k))
-    const double2 wk = (live && a.w) ? a.w[k] : make_double2(0.0, 0.0);
+    double2 wk[MS];
+#pragma unroll
+    for (int u = 0; u < MS; ++u) wk[u] = (kof[u] >= 0 && a.w) ? a.w[kof[u]] : zero;
     const int64_t out0 = a.proj_off[c];
 #pragma unroll
     for (int r = 0; r < 4 * NPA; ++r) {
         if (r >= nrow) continue;  // uniform
-        const double2 Gr = nk > 0 ? cmul(y0, S[r]) : make_double2(0.0, 0.0);
-        if (a.G && live) {
-            a.G[2 * ((out0 + r) * a.ns + k)] = Gr.x;
-            a.G[2 * ((out0 + r) * a.ns + k) + 1] = Gr.y;
+        double t = 0.0;
+#pragma unroll
+        for (int u = 0; u < MS; ++u) {
+            if (kof[u] < 0) continue;
+            const double2 Gr = nk[u] > 0 ? cmul(y0[u], S[u][r]) : zero;
+            if (a.G) {
+                a.G[2 * ((out0 + r) * a.ns + kof[u])] = Gr.x;
+                a.G[2 * ((out0 + r) * a.ns + kof[u]) + 1] = Gr.y;
+            }
+            t = fma(wk[u].x, Gr.y, fma(wk[u].y, Gr.x, t));
         }
-        const double t = wave_reduce(live ? fma(wk.x, Gr.y, wk.y * Gr.x) : 0.0);
+        t = wave_reduce(t);
         if (lane == 0) rpart[r * 8 + wv] = t;
     }
     __syncthreads();
-    for (int r = k; r < nrow; r += blockDim.x) {
+    for (int r = tid; r < nrow; r += T) {
         double acc = 0.0;
         for (int v = 0; v < nwv; ++v) acc += rpart[r * 8 + v];
         a.rho[out0 + r] = -acc * INV_PI;
@@ -386,18 +651,39 @@ static KernelFn pick_seed_m(int M) {
 
 static KernelFn pick_seed(bool stage, int M) { return stage ? pick_seed_m<true>(M) : pick_seed_m<false>(M); }
 
-static KernelFn pick_shift(int npa) {
-    switch (npa) {
-        case 1: return k_shift<1>;
-        case 2: return k_shift<2>;
-        case 3: return k_shift<3>;
-        case 4: return k_shift<4>;
-        case 5: return k_shift<5>;
-        case 6: return k_shift<6>;
-        case 7: return k_shift<7>;
-        default: return k_shift<8>;
+template <int BMAX>
+static KernelFn pick_seed_r1_m(int M) {
+    switch (M) {
+        case 1: return k_seed_r1<1, BMAX>;
+        case 2: return k_seed_r1<2, BMAX>;
+        case 3:
+        case 4: return k_seed_r1<4, BMAX>;
+        default: return k_seed_r1<8, BMAX>;
     }
 }
+
+static KernelFn pick_seed_r1(int M, int bmax) { return bmax <= 6 ? pick_seed_r1_m<6>(M) : pick_seed_r1_m<8>(M); }
+
+template <int MS>
+static KernelFn pick_shift_ms(int npa) {
+    switch (npa) {
+        case 1: return k_shift<1, MS>;
+        case 2: return k_shift<2, MS>;
+        case 3: return k_shift<3, MS>;
+        case 4: return k_shift<4, MS>;
+        case 5: return k_shift<5, MS>;
+        case 6: return k_shift<6, MS>;
+        case 7: return k_shift<7, MS>;
+        default: return k_shift<8, MS>;
+    }
+}
+
+// Shifts per lane: one by default (measured faster on the bundle: the extra
+// registers of a second shift halve the occupancy); two on request when the
+// projection rows leave room in registers.
+static int shift_ms(int npa, int requested) { return requested == 2 && npa <= 5 ? 2 : 1; }
+
+static KernelFn pick_shift(int npa, int ms) { return ms == 2 ? pick_shift_ms<2>(npa) : pick_shift_ms<1>(npa); }
 
 }  // namespace sgf
 
@@ -532,13 +818,19 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
         return SGF_EUNSUPPORTED;
     }
     const int M = hs.ns_pad / 64;
-    KernelFn seed_fn = pick_seed(stage, M);
-    KernelFn shift_fn = pick_shift(totals->max_proj_atoms);
+    // register variant when every subspace has <= 64 orbitals and <= 8 blocks per row
+    const bool r1 = opts->stage_lds < 0 && totals->max_loc_atoms <= 16 && totals->max_row_blocks <= 8;
+    KernelFn seed_fn = r1 ? pick_seed_r1(M, totals->max_row_blocks) : pick_seed(stage, M);
+    const size_t seed_lds = r1 ? 0 : lds;
+    const int ms = shift_ms(totals->max_proj_atoms, opts->shifts_per_lane);
+    KernelFn shift_fn = pick_shift(totals->max_proj_atoms, ms);
+    // shift-pass workgroup: ns_pad / ms lanes rounded up to whole wavefronts (<= 512)
+    const int shift_threads = ((hs.ns_pad / ms + 63) / 64) * 64;
     SGF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(seed_fn), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds));
+                                (int)seed_lds));
     int per_cu = 0;
     SGF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(seed_fn), SEED_T,
-                                                         lds));
+                                                         seed_lds));
     if (per_cu < 1) {
         set_error("sgf_shifted_solve: seed kernel does not fit a compute unit (LDS %zu)", lds);
         return SGF_EUNSUPPORTED;
@@ -565,10 +857,10 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
             SGF_HIP(prof.add(e2));
             SGF_HIP(hipEventRecord(e0, st));
         }
-        hipLaunchKernelGGL(seed_fn, dim3((unsigned)grid), dim3(SEED_T), lds, st, a);
+        hipLaunchKernelGGL(seed_fn, dim3((unsigned)grid), dim3(SEED_T), seed_lds, st, a);
         SGF_LAUNCHED();
         if (timed) SGF_HIP(hipEventRecord(e1, st));
-        hipLaunchKernelGGL(shift_fn, dim3((unsigned)(b1 - b0)), dim3(hs.ns_pad), 0, st, a);
+        hipLaunchKernelGGL(shift_fn, dim3((unsigned)(b1 - b0)), dim3(shift_threads), 0, st, a);
         SGF_LAUNCHED();
         if (timed) SGF_HIP(hipEventRecord(e2, st));
     }

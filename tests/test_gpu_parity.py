@@ -165,19 +165,30 @@ def test_bundle_at_looser_tol(sgf, O):
     compare(got, ref, rtol=1e-8, tol=wl.tol)
 
 
-@pytest.mark.parametrize("stage", [0, 1])
+@pytest.mark.parametrize("stage", [-1, 0, 1])
 @pytest.mark.parametrize("batch", [0, 7])
 def test_launch_shapes_agree(sgf, O, stage, batch):
-    """Operator staging and history batching (a ragged last batch) give the
-    oracle's result, and every shape gives the same bits."""
+    """Each seed-pass variant (register rows, LDS-staged operator, operator
+    from global memory) gives the oracle's result, and history batching (with
+    a ragged last batch) does not change a single bit."""
     wl = W.bundle_workload(2, 2, 50, n_shifts=128, config_no=74)
     cols = wl.columns[::2]
     got = sgf.solve_workload(wl, cols=cols, batch_cols=batch, stage_lds=stage).numpy()
     ref = O.solve_workload(wl, cols=cols, threads=8)
     compare(got, ref)
-    base = sgf.solve_workload(wl, cols=cols).numpy()
+    base = sgf.solve_workload(wl, cols=cols, stage_lds=stage).numpy()
     np.testing.assert_array_equal(got.G, base.G)
     np.testing.assert_array_equal(got.rho, base.rho)
+
+
+@pytest.mark.parametrize("spl", [1, 2])
+def test_shift_lanes_agree(sgf, O, spl):
+    """One or two shifts per lane in the shift pass: oracle parity."""
+    wl = W.bundle_workload(3, 2, 60, n_shifts=128, config_no=79)
+    cols = wl.columns[::3]
+    got = sgf.solve_workload(wl, cols=cols, shifts_per_lane=spl).numpy()
+    ref = O.solve_workload(wl, cols=cols, threads=8)
+    compare(got, ref)
 
 
 def test_order_and_repeat_are_bitwise(sgf):
