@@ -448,6 +448,254 @@ __global__ __launch_bounds__(SEED_T) void k_seed_r1(SolveArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Seed pass for S != I.  COCG on A = S^{-1}(z_s S - H) with the S-bilinear
+// form [u, v] = u^T S v (A is symmetric in it since H and S are real
+// symmetric): s is the true-space residual, r = S^{-1} s, q = S p and
+// w = (z_s S - H) p = z_s q - H p, so mu = p^T w and rho = r^T s.  The inverse
+// of the local overlap S_L is formed once per column in LDS by in-place
+// Gauss-Jordan elimination (S_L is symmetric positive definite, so no
+// pivoting) and applied as a dense product each iteration.  The recorded
+// history holds r on P: the shifted iterates are combinations of the r_n.
+// ---------------------------------------------------------------------------
+template <int M>
+__global__ __launch_bounds__(SEED_T) void k_seed_gen(SolveArgs a) {
+    extern __shared__ double4 lds4[];
+    char *lds = reinterpret_cast<char *>(lds4);
+    double2 *vp = reinterpret_cast<double2 *>(lds + a.off_p);
+    double2 *vs = reinterpret_cast<double2 *>(lds + a.off_s);
+    double2 *vw = reinterpret_cast<double2 *>(lds + a.off_w);
+    double2 *vq = reinterpret_cast<double2 *>(lds + a.off_q);
+    double2 *vr = reinterpret_cast<double2 *>(lds + a.off_r);
+    double *Si = reinterpret_cast<double *>(lds + a.off_sinv);  // [nl][nl]
+    const int lane = threadIdx.x;
+    const double2 zs = a.z[a.seed];
+    double2 sigma[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int k = lane + 64 * m;
+        sigma[m] = k < a.ns ? csub(a.z[k], zs) : make_double2(0.0, 0.0);
+    }
+    const double tol2 = a.tol * a.tol;
+    const double2 zero = make_double2(0.0, 0.0);
+
+    for (;;) {
+        int64_t ticket = 0;
+        if (lane == 0) ticket = (int64_t)atomicAdd(reinterpret_cast<unsigned long long *>(a.ticket), 1ull);
+        ticket = __shfl(ticket, 0, 64);
+        if (ticket >= a.batch_end - a.batch_begin) break;
+        const int64_t slot = ticket;
+        ticket += a.batch_begin;
+        const int64_t c = a.order ? (int64_t)a.order[ticket] : ticket;
+        ColMeta *meta = &a.meta[slot];
+        if (c < 0 || c >= a.n_cols) {
+            if (lane == 0) *meta = ColMeta{-1, 0, 0, SGF_BADCOLUMN};
+            continue;
+        }
+        const int64_t j = a.cols[c];
+        const int32_t pl = a.col_plan[c];
+        bool bad = pl < 0 || pl >= a.n_plans || j < 0;
+        int64_t a0 = 0, b0 = 0, p0 = 0;
+        int n_loc = 0, nblk = 0, npa = 0, cl = 0;
+        if (!bad) {
+            a0 = a.atom_off[pl];
+            n_loc = (int)(a.atom_off[pl + 1] - a0);
+            b0 = a.blk_off[pl];
+            nblk = (int)(a.blk_off[pl + 1] - b0);
+            p0 = a.pa_off[pl];
+            npa = (int)(a.pa_off[pl + 1] - p0);
+            cl = a.center_loc[pl];
+            bad = n_loc < 1 || n_loc > a.max_loc_atoms || npa < 1 || 4 * npa > a.rmax || cl < 0 || cl >= n_loc ||
+                  a.loc_atom[a0 + cl] != (int32_t)(j >> 2);
+        }
+        if (bad) {
+            if (lane == 0) {
+                *meta = ColMeta{-1, 0, 0, SGF_BADCOLUMN};
+                a.iters[c] = 0;
+                a.status[c] = SGF_BADCOLUMN;
+            }
+            continue;
+        }
+        const int nl = 4 * n_loc;
+        const int jl = 4 * cl + (int)(j & 3);
+        const int nprow = 4 * npa;
+        const int prow = lane < nprow ? 4 * a.pa_loc[p0 + (lane >> 2)] + (lane & 3) : 0;
+        double2 *hab = a.hab + (size_t)slot * a.cap * 2;
+        double2 *hr = a.hr + (size_t)slot * (a.cap + 1) * a.rmax;
+
+        // dense S_L, then its inverse in place
+        for (int e = lane; e < nl * nl; e += SEED_T) Si[e] = 0.0;
+        wave_lds_fence();
+        for (int A = lane; A < n_loc; A += SEED_T) {
+            const int t0 = a.lrow[a0 + A], t1 = A + 1 < n_loc ? a.lrow[a0 + A + 1] : nblk;
+            for (int t = t0; t < t1; ++t) {
+                const int B = a.lblk[2 * (b0 + t)];
+                const double *sb = &a.s[16 * (int64_t)a.lblk[2 * (b0 + t) + 1]];
+                for (int o = 0; o < 4; ++o)
+                    for (int q = 0; q < 4; ++q) Si[(4 * A + o) * nl + 4 * B + q] = sb[4 * o + q];
+            }
+        }
+        wave_lds_fence();
+        for (int kk = 0; kk < nl; ++kk) {
+            const double piv = 1.0 / Si[kk * nl + kk];
+            wave_lds_fence();
+            for (int jj = lane; jj < nl; jj += SEED_T) Si[kk * nl + jj] = (jj == kk) ? piv : Si[kk * nl + jj] * piv;
+            wave_lds_fence();
+            for (int i = lane; i < nl; i += SEED_T) {
+                if (i == kk) continue;
+                const double f = Si[i * nl + kk];
+                for (int jj = 0; jj < nl; ++jj)
+                    Si[i * nl + jj] = (jj == kk) ? -f * Si[kk * nl + jj] : fma(-f, Si[kk * nl + jj], Si[i * nl + jj]);
+            }
+            wave_lds_fence();
+        }
+
+        // start: s_0 = q_0 = e_jl, r_0 = p_0 = S^{-1} e_jl, rho_0 = r_0^T s_0
+        for (int i = lane; i < nl; i += SEED_T) {
+            const double2 sv = make_double2(i == jl ? 1.0 : 0.0, 0.0);
+            const double2 rv = make_double2(Si[i * nl + jl], 0.0);
+            vs[i] = sv;
+            vq[i] = sv;
+            vr[i] = rv;
+            vp[i] = rv;
+        }
+        wave_lds_fence();
+        if (lane < nprow) hr[lane] = vr[prow];
+
+        double2 pc[M], po[M];
+        bool act[M];
+        int nkm[M];
+        double res[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            pc[m] = po[m] = make_double2(1.0, 0.0);
+            act[m] = lane + 64 * m < a.ns;
+            nkm[m] = 0;
+            res[m] = 1.0;
+        }
+        double2 rho = make_double2(Si[jl * nl + jl], 0.0);
+        double2 alpha_old = make_double2(1.0, 0.0), beta_old = zero;
+        int status = SGF_MAXITER, iters = 0, applied = 0;
+        double snorm2 = 1.0;
+        const int max_iter = a.max_iter > 0 ? a.max_iter : 10 * nl;
+
+        for (int it = 0; it < max_iter; ++it) {
+            // w = z_s q - H p ; mu = p^T w
+            double m0 = 0.0, m1 = 0.0;
+            for (int i = lane; i < nl; i += SEED_T) {
+                const int A = i >> 2, o = i & 3;
+                double ax = 0.0, ay = 0.0;
+                const int t0 = a.lrow[a0 + A], t1 = A + 1 < n_loc ? a.lrow[a0 + A + 1] : nblk;
+                for (int t = t0; t < t1; ++t) {
+                    const int B = a.lblk[2 * (b0 + t)];
+                    const double *hrow = &a.h[16 * (int64_t)a.lblk[2 * (b0 + t) + 1] + 4 * o];
+                    const double2 *pb = &vp[4 * B];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        ax = fma(hrow[q], pb[q].x, ax);
+                        ay = fma(hrow[q], pb[q].y, ay);
+                    }
+                }
+                const double2 pi_ = vp[i], qi = vq[i];
+                const double2 wi = make_double2(zs.x * qi.x - zs.y * qi.y - ax, zs.x * qi.y + zs.y * qi.x - ay);
+                vw[i] = wi;
+                m0 = fma(pi_.x, wi.x, fma(-pi_.y, wi.y, m0));
+                m1 = fma(pi_.x, wi.y, fma(pi_.y, wi.x, m1));
+            }
+            const double2 mu = make_double2(wave_reduce(m0), wave_reduce(m1));
+            iters = it + 1;
+            if (!cfinite(mu) || !cfinite(rho)) { status = SGF_NONFINITE; break; }
+            if (mu.x == 0.0 && mu.y == 0.0) { status = SGF_BREAKDOWN; break; }
+            const double2 alpha = cdiv(rho, mu);
+
+            // s -= alpha w ; ||s||^2
+            double r2 = 0.0;
+            for (int i = lane; i < nl; i += SEED_T) {
+                const double2 si = csub(vs[i], cmul(alpha, vw[i]));
+                vs[i] = si;
+                r2 = fma(si.x, si.x, fma(si.y, si.y, r2));
+            }
+            snorm2 = wave_reduce(r2);
+            wave_lds_fence();
+            // r = S^{-1} s ; rho' = r^T s
+            double r0 = 0.0, r1 = 0.0;
+            for (int i = lane; i < nl; i += SEED_T) {
+                double rx = 0.0, ry = 0.0;
+                const double *srow = &Si[i * nl];
+                for (int jj = 0; jj < nl; ++jj) {
+                    const double2 sj = vs[jj];
+                    rx = fma(srow[jj], sj.x, rx);
+                    ry = fma(srow[jj], sj.y, ry);
+                }
+                vr[i] = make_double2(rx, ry);
+                const double2 si = vs[i];
+                r0 = fma(rx, si.x, fma(-ry, si.y, r0));
+                r1 = fma(rx, si.y, fma(ry, si.x, r1));
+            }
+            const double2 rho_new = make_double2(wave_reduce(r0), wave_reduce(r1));
+            const double2 ia = crcp(alpha);
+            const double2 beta = cmul(rho_new, crcp(rho));
+            for (int i = lane; i < nl; i += SEED_T) {
+                vp[i] = cfma(beta, vp[i], vr[i]);
+                vq[i] = cfma(beta, vq[i], vs[i]);
+            }
+            if (lane == 0) {
+                hab[2 * it] = ia;
+                hab[2 * it + 1] = cmul(beta, ia);
+            }
+            wave_lds_fence();
+            if (lane < nprow) hr[(size_t)(it + 1) * a.rmax + lane] = vr[prow];
+
+            const double2 coup = cmul(cmul(alpha, beta_old), crcp(alpha_old));
+            int alive = 0;
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                if (!act[m]) continue;
+                const double2 pn = cadd(cmul(cfma(alpha, sigma[m], make_double2(1.0, 0.0)), pc[m]),
+                                        cmul(coup, csub(pc[m], po[m])));
+                po[m] = pc[m];
+                pc[m] = pn;
+                const double pn2 = fma(pn.x, pn.x, pn.y * pn.y);
+                if (snorm2 <= tol2 * pn2) {
+                    act[m] = false;
+                    nkm[m] = it + 1;
+                    res[m] = sqrt(snorm2 / pn2);
+                } else {
+                    alive = 1;
+                }
+            }
+            applied = it + 1;
+            alpha_old = alpha;
+            beta_old = beta;
+            rho = rho_new;
+            const bool any_alive = __any(alive);
+            if (!any_alive || snorm2 == 0.0) { status = SGF_CONVERGED; break; }
+            if (rho_new.x == 0.0 && rho_new.y == 0.0) { status = SGF_BREAKDOWN; break; }
+            if (!cfinite(rho_new) || !isfinite(snorm2)) { status = SGF_NONFINITE; break; }
+        }
+
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int k = lane + 64 * m;
+            if (k >= a.ns) continue;
+            if (act[m]) {
+                nkm[m] = applied;
+                const double pn2 = fma(pc[m].x, pc[m].x, pc[m].y * pc[m].y);
+                res[m] = applied > 0 ? sqrt(snorm2 / pn2) : 1.0;
+            }
+            a.nk[(size_t)slot * a.ns_pad + k] = nkm[m];
+            if (a.resid) a.resid[c * a.ns + k] = res[m];
+            if (a.shift_iters) a.shift_iters[c * a.ns + k] = nkm[m];
+        }
+        if (lane == 0) {
+            *meta = ColMeta{(int32_t)c, iters, npa, status};
+            a.iters[c] = iters;
+            a.status[c] = status;
+        }
+        wave_lds_fence();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Shift pass
 // ---------------------------------------------------------------------------
 constexpr int SHIFT_CH = 16;  // backward steps staged in LDS at a time
@@ -664,6 +912,16 @@ static KernelFn pick_seed_r1_m(int M) {
 
 static KernelFn pick_seed_r1(int M, int bmax) { return bmax <= 6 ? pick_seed_r1_m<6>(M) : pick_seed_r1_m<8>(M); }
 
+static KernelFn pick_seed_gen(int M) {
+    switch (M) {
+        case 1: return k_seed_gen<1>;
+        case 2: return k_seed_gen<2>;
+        case 3:
+        case 4: return k_seed_gen<4>;
+        default: return k_seed_gen<8>;
+    }
+}
+
 template <int MS>
 static KernelFn pick_shift_ms(int npa) {
     switch (npa) {
@@ -733,10 +991,6 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
         set_error("sgf_shifted_solve: a column has %d projection atoms (limit 8)", totals->max_proj_atoms);
         return SGF_EUNSUPPORTED;
     }
-    if (sys->s) {
-        set_error("sgf_shifted_solve: the generalized (S != I) path is not built into this library");
-        return SGF_EUNSUPPORTED;
-    }
     if (opts->precision == 1) {
         set_error("sgf_shifted_solve: the mixed-precision path is not built into this library");
         return SGF_EUNSUPPORTED;
@@ -759,6 +1013,7 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
     a.row_ptr = sys->row_ptr;
     a.col = sys->col;
     a.h = sys->h;
+    a.s = sys->s;
     a.atom_off = plan->atom_off;
     a.blk_off = plan->blk_off;
     a.pa_off = plan->pa_off;
@@ -812,16 +1067,35 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
     const size_t lds_staged = off;
     const bool stage = opts->stage_lds == 1 || (opts->stage_lds < 0 && lds_staged <= 16 * 1024);
     const size_t lds = stage ? lds_staged : lds_plain;
-    if (lds > 160 * 1024) {
+    if (lds > 160 * 1024 && !sys->s) {
         set_error("sgf_shifted_solve: a local subspace of %d atoms needs %zu bytes of LDS (limit 163840)",
                   totals->max_loc_atoms, lds);
         return SGF_EUNSUPPORTED;
     }
     const int M = hs.ns_pad / 64;
     // register variant when every subspace has <= 64 orbitals and <= 8 blocks per row
-    const bool r1 = opts->stage_lds < 0 && totals->max_loc_atoms <= 16 && totals->max_row_blocks <= 8;
-    KernelFn seed_fn = r1 ? pick_seed_r1(M, totals->max_row_blocks) : pick_seed(stage, M);
-    const size_t seed_lds = r1 ? 0 : lds;
+    const bool gen = sys->s != nullptr;
+    const bool r1 = !gen && opts->stage_lds < 0 && totals->max_loc_atoms <= 16 && totals->max_row_blocks <= 8;
+    KernelFn seed_fn = gen ? pick_seed_gen(M) : (r1 ? pick_seed_r1(M, totals->max_row_blocks) : pick_seed(stage, M));
+    size_t seed_lds = r1 ? 0 : lds;
+    if (gen) {
+        // p, s, w, q, r and the dense inverse of the local overlap
+        size_t goff = 0;
+        auto gtake = [&](size_t bytes) { size_t r = goff; goff = align_up(goff + bytes, 16); return r; };
+        a.off_p = gtake((size_t)nl * 16);
+        a.off_s = gtake((size_t)nl * 16);
+        a.off_w = gtake((size_t)nl * 16);
+        a.off_q = gtake((size_t)nl * 16);
+        a.off_r = gtake((size_t)nl * 16);
+        a.off_sinv = gtake((size_t)nl * nl * 8);
+        seed_lds = goff;
+        if (seed_lds > 160 * 1024) {
+            set_error("sgf_shifted_solve: S != I with a local subspace of %d orbitals needs %zu bytes of LDS "
+                      "for the dense local overlap inverse (limit 163840); prune the subspaces or reduce the radius",
+                      nl, seed_lds);
+            return SGF_EUNSUPPORTED;
+        }
+    }
     const int ms = shift_ms(totals->max_proj_atoms, opts->shifts_per_lane);
     KernelFn shift_fn = pick_shift(totals->max_proj_atoms, ms);
     // shift-pass workgroup: ns_pad / ms lanes rounded up to whole wavefronts (<= 512)

@@ -17,7 +17,7 @@ struct ColMeta {
 struct SolveArgs {
     // system (device)
     const int32_t *row_ptr, *col;
-    const double *h;
+    const double *h, *s;
     // plan (device)
     const int64_t *atom_off, *blk_off, *pa_off;
     const int32_t *loc_atom, *lrow, *lblk, *pa_loc, *center_loc;
@@ -47,7 +47,7 @@ struct SolveArgs {
     double2 *hr;        // [slots][cap+1][rmax]: projected residuals r_n on P
     int64_t *ticket;
     // seed-pass LDS carve (bytes)
-    size_t off_p, off_s, off_w, off_hs, off_cs, off_rs;
+    size_t off_p, off_s, off_w, off_hs, off_cs, off_rs, off_q, off_r, off_sinv;
 };
 
 struct SolveLayout {

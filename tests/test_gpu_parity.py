@@ -280,3 +280,36 @@ def test_bundle_full_size_sampled(sgf, O):
     got.status = st[sample]
     got.iters = res.iters.cpu().numpy()[sample]
     compare(got, ref)
+
+
+# ---------------------------------------------------------------------------
+# Generalized equation (S != I)
+# ---------------------------------------------------------------------------
+
+def test_overlap_small(sgf, O):
+    """(zS - H)x = e_j with the non-orthogonal overlap: GPU vs oracle."""
+    wl = W.bundle_workload(2, 2, 40, overlap=True, n_shifts=64, config_no=83)
+    cols = wl.columns[::3]
+    got = sgf.solve_workload(wl, cols=cols).numpy()
+    ref = O.solve_workload(wl, cols=cols, threads=8)
+    compare(got, ref)
+
+
+def test_overlap_workload_sampled(sgf, O):
+    """The overlap workload (full bundle geometry, per-column radius drawn from
+    U[0.6, 1.4] nm, 256 shifts): 2048 seeded columns on the GPU, 48 of them
+    recomputed by the oracle."""
+    wl = W.config_bundle_overlap(n_columns=2048)
+    got = sgf.solve_workload(wl).numpy()
+    assert np.all(got.status == sgf.CONVERGED)
+    pick = np.sort(np.random.default_rng(3).choice(wl.columns.size, 48, replace=False))
+    ref = O.solve_workload(wl, cols=wl.columns[pick], threads=8)
+
+    class Sub:
+        pass
+    sub = Sub()
+    rows = np.concatenate([np.arange(got.proj_off[c], got.proj_off[c + 1]) for c in pick])
+    sub.proj_off = np.concatenate([[0], np.cumsum(got.proj_off[pick + 1] - got.proj_off[pick])])
+    sub.proj_row, sub.G, sub.rho = got.proj_row[rows], got.G[rows], got.rho[rows]
+    sub.status, sub.iters = got.status[pick], got.iters[pick]
+    compare(sub, ref)
