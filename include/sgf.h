@@ -288,6 +288,61 @@ sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *plan, const 
  * profiled solve is pending; the events are released by this call. */
 sgf_status sgf_solve_profile(double *seed_ms, double *shift_ms, int32_t *batches);
 
+/* ------------------------------------------------------------------------ */
+/* Learned scheduling                                                         */
+/* ------------------------------------------------------------------------ */
+/* A small network predicts how many Krylov iterations a column needs from
+ * its local environment, so that columns can be queued longest-first and
+ * grouped into balanced batches.  Convergence is still decided by the
+ * residual in sgf_shifted_solve, so the order never changes a result; the
+ * natural order is the fallback.  (This scheduler is not part of the paper;
+ * it sits on top of the method.)
+ *
+ * Features of column j (atom c, orbital o) on its local subspace, float[5]:
+ *   f0 off-diagonal blocks of c's local block row;
+ *   f1, f2 mean and max of ||H_cb[o, :]||_2 over those blocks;
+ *   f3 |H_jj - mean of H_ii over the local orbitals of type o|;
+ *   f4 local orbitals.
+ * Network (FP32): x' = (x - mean) * inv_std; h1 = relu(W1 x' + b1);
+ * h2 = relu(W2 h1 + b2); y = W3 . h2 + b3, trained on y = log(iterations)
+ * by mean-squared error with Adam (beta1 0.9, beta2 0.999, eps 1e-8).
+ * Parameters: float[SGF_MLP_NPARAM] = [0:5] mean, [5:10] inv_std,
+ * W1 (64x5 row-major), b1 (64), W2 (64x64), b2 (64), W3 (64), b3 (1). */
+#define SGF_MLP_NFEAT 5
+#define SGF_MLP_HIDDEN 64
+#define SGF_MLP_NPARAM 4619
+
+/* d_feat float[n_cols][5] for the columns of a built plan. */
+sgf_status sgf_features(const sgf_system *sys, const sgf_plan *plan, int64_t n_cols, const int64_t *d_cols,
+                        const int32_t *d_col_plan, float *d_feat, void *stream);
+
+/* Set the normalisation entries [0:10] of d_params to the mean and 1/std of
+ * n feature rows (a constant feature keeps inv_std = 1). */
+sgf_status sgf_mlp_normalize(float *d_params, const float *d_feat, int64_t n, void *stream);
+
+/* d_y[i] = network(d_feat[i]) for n rows. */
+sgf_status sgf_mlp_forward(const float *d_params, const float *d_feat, int64_t n, float *d_y, void *stream);
+
+/* One Adam step (step counts from 1) on a minibatch of n <= 128 rows with
+ * targets d_target; d_adam_m / d_adam_v are float[SGF_MLP_NPARAM] moment
+ * buffers (zero before step 1).  d_loss (nullable) receives the minibatch
+ * MSE before the update.  One workgroup; gradients are summed in a fixed
+ * order, so a step is bitwise reproducible. */
+sgf_status sgf_mlp_train_step(float *d_params, float *d_adam_m, float *d_adam_v, int32_t step, float lr,
+                              const float *d_feat, const float *d_target, int32_t n, float *d_loss, void *stream);
+
+/* Gradient of the minibatch MSE with respect to every parameter (zero for
+ * the normalisation entries), n <= 128, into d_grad float[SGF_MLP_NPARAM]. */
+sgf_status sgf_mlp_gradient(const float *d_params, const float *d_feat, const float *d_target, int32_t n,
+                            float *d_grad, float *d_loss, void *stream);
+
+/* Work-queue order, largest prediction first: a counting sort of d_pred into
+ * 4096 buckets over [y_lo, y_hi] (values outside are clamped); the order
+ * inside a bucket is unspecified.  Writes a permutation of 0..n-1. */
+sgf_status sgf_order_workspace(size_t *ws_bytes);
+sgf_status sgf_order_by_prediction(const float *d_pred, int64_t n, float y_lo, float y_hi, int32_t *d_order,
+                                   void *d_ws, size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

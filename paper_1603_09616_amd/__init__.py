@@ -24,8 +24,10 @@ CONVERGED, MAXITER, BREAKDOWN, NONFINITE, DRIFT, BADCOLUMN = 0, 1, 2, 3, 4, 5
 EXPORTED = (
     "sgf_last_error", "sgf_version", "sgf_build_workspace", "sgf_build_pattern", "sgf_build_hamiltonian",
     "sgf_build_chain", "sgf_to_f32", "sgf_plan_workspace", "sgf_plan_count", "sgf_plan_build", "sgf_proj_layout",
-    "sgf_solve_workspace", "sgf_shifted_solve", "sgf_solve_profile",
+    "sgf_solve_workspace", "sgf_shifted_solve", "sgf_solve_profile", "sgf_features", "sgf_mlp_normalize",
+    "sgf_mlp_forward", "sgf_mlp_train_step", "sgf_mlp_gradient", "sgf_order_workspace", "sgf_order_by_prediction",
 )
+MLP_NFEAT, MLP_NPARAM, MLP_BATCH = 5, 4619, 128
 
 
 class SgfError(RuntimeError):
@@ -91,6 +93,13 @@ def lib():
             "sgf_solve_workspace": [P, P, i64, i32, P, P],
             "sgf_shifted_solve": [P, P, P, i64, P, P, P, i32, P, P, P, P, szt, P, P, P, P, P, P, P, P],
             "sgf_solve_profile": [P, P, P],
+            "sgf_features": [P, P, i64, P, P, P, P],
+            "sgf_mlp_normalize": [P, P, i64, P],
+            "sgf_mlp_forward": [P, P, i64, P, P],
+            "sgf_mlp_train_step": [P, P, P, i32, ctypes.c_float, P, P, i32, P, P],
+            "sgf_mlp_gradient": [P, P, P, i32, P, P, P],
+            "sgf_order_workspace": [P],
+            "sgf_order_by_prediction": [P, i64, ctypes.c_float, ctypes.c_float, P, P, szt, P],
         }
         for name, args in sigs.items():
             f = getattr(L, name)
@@ -429,3 +438,91 @@ def solve_workload(wl, system: Optional[System] = None, cols=None, prune=True, *
             rpc = rpc[[pos[int(j)] for j in cols]]
     kw.setdefault("tol", wl.tol)
     return shifted_solve(system, cols, wl.z, wl.w, radius=wl.radius, radius_per_col=rpc, prune=prune, **kw)
+
+
+# --- learned scheduling ---------------------------------------------------------
+
+def features(prep: Prepared, stream=None):
+    """float32 [n_cols, 5] features of the prepared columns (see include/sgf.h)."""
+    torch = _torch()
+    n = prep.cols.numel()
+    out = torch.empty((max(n, 1), MLP_NFEAT), dtype=torch.float32, device=prep.cols.device)
+    sc, pc = prep.system.c(), prep.plan.c()
+    _call("sgf_features", ctypes.byref(sc), ctypes.byref(pc), n, _ptr(prep.cols), _ptr(prep.col_plan), _ptr(out),
+          _stream(stream))
+    return out[:n]
+
+
+class IterationModel:
+    """The iteration-count network; params is its flat FP32 parameter vector
+    (initial weights are an input, e.g. workloads.mlp_init)."""
+
+    def __init__(self, params, device="cuda"):
+        torch = _torch()
+        self.params = _dev(np.asarray(params, np.float32) if not isinstance(params, torch.Tensor) else params,
+                           torch.float32, device)
+        assert self.params.numel() == MLP_NPARAM
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.step = 0
+
+    def normalize(self, feat, stream=None):
+        _call("sgf_mlp_normalize", _ptr(self.params), _ptr(feat.contiguous()), feat.shape[0], _stream(stream))
+
+    def predict(self, feat, stream=None):
+        torch = _torch()
+        y = torch.empty(max(feat.shape[0], 1), dtype=torch.float32, device=feat.device)
+        _call("sgf_mlp_forward", _ptr(self.params), _ptr(feat.contiguous()), feat.shape[0], _ptr(y), _stream(stream))
+        return y[:feat.shape[0]]
+
+    def gradient(self, feat, target, stream=None):
+        torch = _torch()
+        g = torch.empty_like(self.params)
+        loss = torch.empty(1, dtype=torch.float32, device=feat.device)
+        _call("sgf_mlp_gradient", _ptr(self.params), _ptr(feat.contiguous()), _ptr(target.contiguous()),
+              feat.shape[0], _ptr(g), _ptr(loss), _stream(stream))
+        return g, loss
+
+    def train_step(self, feat, target, lr=1e-3, stream=None):
+        torch = _torch()
+        self.step += 1
+        loss = torch.empty(1, dtype=torch.float32, device=feat.device)
+        _call("sgf_mlp_train_step", _ptr(self.params), _ptr(self.m), _ptr(self.v), self.step, float(lr),
+              _ptr(feat.contiguous()), _ptr(target.contiguous()), feat.shape[0], _ptr(loss), _stream(stream))
+        return loss
+
+    def fit(self, feat, target, epochs=20, lr=1e-3, seed=0, holdout=0.2, stream=None):
+        """Minibatch Adam on (feat, target) with a seeded shuffle; returns the
+        per-epoch mean training loss and the held-out MSE."""
+        torch = _torch()
+        n = feat.shape[0]
+        perm = np.random.default_rng(seed).permutation(n)
+        n_test = int(holdout * n)
+        test = torch.as_tensor(perm[:n_test], device=feat.device)
+        train = perm[n_test:]
+        self.normalize(feat[torch.as_tensor(train, device=feat.device)])
+        rng = np.random.default_rng(seed + 1)
+        hist = []
+        for _ in range(epochs):
+            order = torch.as_tensor(rng.permutation(train), device=feat.device)
+            losses = []
+            for b in range(0, order.numel() - MLP_BATCH + 1, MLP_BATCH):
+                idx = order[b:b + MLP_BATCH]
+                losses.append(self.train_step(feat[idx], target[idx], lr, stream))
+            hist.append(float(torch.cat(losses).mean()))
+        test_mse = float(((self.predict(feat[test]) - target[test]) ** 2).mean()) if n_test else float("nan")
+        return hist, test_mse
+
+
+def order_by_prediction(pred, y_lo, y_hi, stream=None):
+    """Permutation of the columns, largest predicted work first."""
+    torch = _torch()
+    n = pred.numel()
+    ws = ctypes.c_size_t()
+    _call("sgf_order_workspace", ctypes.byref(ws))
+    d_ws = _bytes(ws.value, pred.device)
+    order = torch.empty(max(n, 1), dtype=torch.int32, device=pred.device)
+    _call("sgf_order_by_prediction", _ptr(pred.contiguous()), n, float(y_lo), float(y_hi), _ptr(order), _ptr(d_ws),
+          ws.value, _stream(stream))
+    return order[:n]
+

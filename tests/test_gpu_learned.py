@@ -1,0 +1,135 @@
+"""GPU tests of the learned scheduler: features, the network's forward pass,
+gradient and Adam step against the FP64 oracle, training on logged solves,
+and the order it produces leaving every result unchanged."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sgf():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1603_09616_amd as sgf
+    sgf.lib()
+    return sgf
+
+
+@pytest.fixture(scope="module")
+def O():
+    import oracle
+    oracle.build(force=False)
+    return oracle
+
+
+def synthetic_batch(n, seed):
+    """Seeded feature rows shaped like the bundle's and smooth targets."""
+    g = np.random.default_rng(seed)
+    x = np.column_stack([g.integers(1, 5, n), g.uniform(1, 20, n), g.uniform(1.5, 50, n), g.uniform(0, 0.5, n),
+                         4 * g.integers(7, 16, n)]).astype(np.float64)
+    t = np.log(60 + 8 * x[:, 0] + 2 * x[:, 1] + g.normal(0, 3, n))
+    p = W.mlp_init(seed)
+    p[0:5] = x.mean(0)
+    p[5:10] = 1 / x.std(0)
+    return x, t, p
+
+
+@pytest.mark.parametrize("kind", ["bundle", "chain"])
+def test_features_vs_oracle(sgf, O, kind):
+    import oracle.mlp as M
+    if kind == "bundle":
+        wl = W.bundle_workload(3, 2, 40, n_shifts=16, config_no=84)
+        cols = wl.columns[::5]
+    else:
+        wl = W.chain_workload(200, 12, 16, config_no=85)
+        cols = wl.columns
+    b = O.system_for(wl)
+    prep = sgf.prepare(sgf.system_for(wl), cols, radius=wl.radius, prune=True)
+    got = sgf.features(prep).cpu().numpy()
+    for i, j in enumerate(cols):
+        full = O.solve_full(b, wl.xyz, int(j), wl.z[:1], radius=wl.radius, prune=True, max_iter=1)
+        ref = M.features(b, full.loc_atoms, int(j))
+        np.testing.assert_allclose(got[i], ref, rtol=2e-6, atol=1e-6)
+
+
+def test_forward_gradient_adam_vs_oracle(sgf):
+    import torch
+    import oracle.mlp as M
+    x, t, p = synthetic_batch(128, 11)
+    model = sgf.IterationModel(p)
+    dx = torch.as_tensor(x, dtype=torch.float32, device="cuda")
+    dt = torch.as_tensor(t, dtype=torch.float32, device="cuda")
+    # FP32 GPU vs FP64 oracle on the FP32-rounded inputs
+    p32 = p.astype(np.float32).astype(np.float64)
+    x32 = x.astype(np.float32).astype(np.float64)
+    t32 = t.astype(np.float32).astype(np.float64)
+    y = model.predict(dx).cpu().numpy()
+    yr = M.forward(p32, x32)
+    assert np.abs(y - yr).max() / np.abs(yr).max() < 1e-5
+    g, loss = model.gradient(dx, dt)
+    lr_, gr = M.loss_and_grad(p32, x32, t32)
+    g = g.cpu().numpy()
+    err = np.linalg.norm(g - gr) / np.linalg.norm(gr)
+    print(f"  gradient normwise rel err {err:.2e}")
+    assert err < 1e-4
+    assert abs(float(loss.cpu()) - lr_) / lr_ < 1e-5
+    model.train_step(dx, dt, lr=1e-3)
+    # the Adam arithmetic is checked on the GPU's own gradient: a first step
+    # moves each weight by lr * g / (|g| + eps), so entries whose gradient is
+    # rounding noise would otherwise flip sign between FP32 and FP64
+    q, _, _ = M.adam_step(p32, np.zeros_like(p32), np.zeros_like(p32), g.astype(np.float64), 1, 1e-3)
+    got = model.params.cpu().numpy()
+    assert np.abs(got - q).max() < 1e-6
+
+
+def test_training_step_is_bitwise_reproducible(sgf):
+    import torch
+    x, t, p = synthetic_batch(100, 12)
+    dx = torch.as_tensor(x, dtype=torch.float32, device="cuda")
+    dt = torch.as_tensor(t, dtype=torch.float32, device="cuda")
+    runs = []
+    for _ in range(2):
+        m = sgf.IterationModel(p)
+        for _ in range(5):
+            m.train_step(dx, dt)
+        runs.append(m.params.cpu().numpy())
+    np.testing.assert_array_equal(runs[0], runs[1])
+
+
+def test_train_on_logged_solves_and_schedule(sgf):
+    """Train on iteration counts logged by GPU solves of one bundle, predict
+    another (different seed), and check that the learned order is a
+    permutation that leaves G and rho bit for bit unchanged."""
+    import torch
+    train_wl = W.bundle_workload(4, 4, 300, n_shifts=128, config_no=20)
+    s_tr = sgf.system_for(train_wl)
+    prep = sgf.prepare(s_tr, train_wl.columns, radius=train_wl.radius, prune=True)
+    res = sgf.solve_prepared(prep, train_wl.z, train_wl.w, tol=train_wl.tol, g_out=False)
+    feat = sgf.features(prep)
+    target = torch.log(res.iters.to(torch.float32))
+    model = sgf.IterationModel(W.mlp_init(3))
+    hist, test_mse = model.fit(feat, target, epochs=15, lr=1e-3, seed=4)
+    var = float(target.var())
+    print(f"  train loss {hist[0]:.4f} -> {hist[-1]:.4f}; held-out MSE {test_mse:.4f} vs variance {var:.4f}")
+    assert hist[-1] < hist[0]
+    assert test_mse < 0.8 * var
+
+    wl = W.bundle_workload(4, 4, 300, n_shifts=128, config_no=21)
+    s = sgf.system_for(wl)
+    prep2 = sgf.prepare(s, wl.columns, radius=wl.radius, prune=True)
+    pred = model.predict(sgf.features(prep2))
+    order = sgf.order_by_prediction(pred, 0.0, float(np.log(10 * 4 * 16)))
+    o = order.cpu().numpy()
+    assert np.array_equal(np.sort(o), np.arange(wl.columns.size))
+    po = pred.cpu().numpy()[o]
+    # longest predicted first, up to the bucket width
+    assert np.all(np.diff(po) <= np.log(640) / 4096 + 1e-6)
+    a = sgf.solve_prepared(prep2, wl.z, wl.w, tol=wl.tol).numpy()
+    b = sgf.solve_prepared(prep2, wl.z, wl.w, tol=wl.tol, order=o).numpy()
+    np.testing.assert_array_equal(a.G, b.G)
+    np.testing.assert_array_equal(a.rho, b.rho)
+    np.testing.assert_array_equal(a.iters, b.iters)

@@ -267,3 +267,28 @@ def config_large(**kw) -> Workload:
     kw.setdefault("config_no", 5)
     kw.setdefault("n_shifts", 256)
     return bundle_workload(38, 38, 700, n_chains=1429, **kw)
+
+
+# ---------------------------------------------------------------------------
+# Initial weights of the iteration-count network (inputs of the training).
+# ---------------------------------------------------------------------------
+
+MLP_NF, MLP_NH = 5, 64
+MLP_NPARAM = 2 * MLP_NF + MLP_NH * MLP_NF + MLP_NH + MLP_NH * MLP_NH + MLP_NH + MLP_NH + 1
+
+
+def mlp_init(seed: int = 0) -> np.ndarray:
+    """He-normal weights and zero biases in the flat layout
+    [mean(5), inv_std(5), W1(64x5), b1, W2(64x64), b2, W3(64), b3];
+    normalisation is the identity until it is set from training data."""
+    g = rng(4, seed)
+    p = np.zeros(MLP_NPARAM)
+    p[MLP_NF:2 * MLP_NF] = 1.0
+    o = 2 * MLP_NF
+    p[o:o + MLP_NH * MLP_NF] = g.normal(0, np.sqrt(2.0 / MLP_NF), MLP_NH * MLP_NF)
+    o += MLP_NH * MLP_NF + MLP_NH
+    p[o:o + MLP_NH * MLP_NH] = g.normal(0, np.sqrt(2.0 / MLP_NH), MLP_NH * MLP_NH)
+    o += MLP_NH * MLP_NH + MLP_NH
+    p[o:o + MLP_NH] = g.normal(0, np.sqrt(1.0 / MLP_NH), MLP_NH)
+    return p
+
