@@ -7,8 +7,11 @@ columns on its R = 1.0 nm local subspace (pruned to the connected component),
 128 shifts E + 0.01i on [-30, 30] eV, tol 1e-12 (FP64 accuracy 1e-10 per
 result).  One step = the whole hot path on that input: neighbour list,
 Hamiltonian assembly, local-subspace plans, projection layout and the
-two-pass shifted solve (Green's function on the projection rows and the
-density matrix).  Inputs (atom positions, the column list and the column ->
+per-column features, the iteration-count network's predictions and the
+longest-predicted-first column order, and the two-pass shifted solve
+(Green's function on the projection rows and the density matrix).  The
+network is trained before the timed region on iteration counts logged by
+solves of a differently seeded bundle.  Inputs (atom positions, the column list and the column ->
 subspace-centre map) are resident in HBM before the timed region.
 
 Prints one JSON line on stdout; progress goes to stderr.
@@ -51,12 +54,40 @@ def pass_flops(nblk, nl, nrow, iters, nk, ns):
     return seed, shift
 
 
+def train_scheduler(sgf, W, dev, n_logged=50000):
+    """The learned scheduler's setup (outside the timed region): log the
+    iteration counts of n_logged solves of a differently seeded bundle of the
+    same shape, then train the iteration-count network on them with the
+    library's own kernels."""
+    import torch
+    tw = W.config_bundle(config_no=20)
+    cols = np.sort(np.random.default_rng(5).choice(tw.columns, n_logged, replace=False))
+    ts = sgf.system_for(tw)
+    tp = sgf.prepare(ts, cols, radius=tw.radius, prune=True)
+    tr = sgf.solve_prepared(tp, tw.z, tw.w, tol=tw.tol, g_out=False,
+                            batch_cols=sgf.batch_limit(tp, tw.z.size, 16 << 30))
+    feat = sgf.features(tp)
+    target = torch.log(tr.iters.to(torch.float32))
+    model = sgf.IterationModel(W.mlp_init(3))
+    t0 = time.perf_counter()
+    hist, test_mse = model.fit(feat, target, epochs=10, lr=1e-3, seed=4)
+    torch.cuda.synchronize()
+    info = {"logged_solves": int(cols.size), "epochs": 10, "train_s": round(time.perf_counter() - t0, 3),
+            "final_train_mse": hist[-1], "heldout_mse": test_mse, "target_var": float(target.var())}
+    del tp, tr, ts
+    torch.cuda.empty_cache()
+    return model, info
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--batch", type=int, default=8192, help="columns per history batch")
+    ap.add_argument("--batch", type=int, default=0, help="columns per launch (0: as many as --ws-gib holds)")
+    ap.add_argument("--ws-gib", type=float, default=112.0, help="solve workspace budget for the automatic batch")
+    ap.add_argument("--plain-batch", type=int, default=8192, help="columns per launch of the plain variant")
+    ap.add_argument("--no-variants", action="store_true", help="time only the full solver")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-g", action="store_true", help="skip writing G (rho only)")
@@ -65,7 +96,7 @@ def main(argv=None):
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: every run of this path uses a single MI355X; columns are "
               "independent, so a multi-GPU run shards columns spatially with no communication in the "
-              "Krylov loop (see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+              "Krylov loop. Run with --gpus 1.", file=sys.stderr)
         return 2
 
     import torch
@@ -84,39 +115,56 @@ def main(argv=None):
     d_cp = torch.as_tensor(col_plan, device=dev)
     d_centers = torch.as_tensor(centers, device=dev)
     d_radii = torch.as_tensor(radii, device=dev)
+
+    model, train_info = train_scheduler(sgf, W, dev)
+    log(f"[bench] scheduler trained on {train_info['logged_solves']} logged solves in {train_info['train_s']} s: "
+        f"held-out MSE {train_info['heldout_mse']:.4f} (target variance {train_info['target_var']:.4f})")
+
+    s0 = sgf.build_hamiltonian(d_xyz, wl.tb, device=dev)
+    p0 = sgf.prepare_planned(s0, d_cols, d_cp, d_centers, d_radii, prune=True)
+    batch = args.batch or sgf.batch_limit(p0, ns, int(args.ws_gib * (1 << 30)))
+    del s0, p0
     log(f"[bench] workload {wl.name}: {wl.n_atoms} atoms, {wl.columns.size} columns, {ns} shifts, "
-        f"batch {args.batch}")
+        f"batch {batch}")
 
-    out_buf = {}
+    def make_step(order_mode, batch_cols):
+        out_buf = {}
 
-    def step(profile):
-        s = sgf.build_hamiltonian(d_xyz, wl.tb, device=dev)
-        prep = sgf.prepare_planned(s, d_cols, d_cp, d_centers, d_radii, prune=True)
-        res = sgf.solve_prepared(prep, wl.z, wl.w, tol=wl.tol, g_out=not args.no_g, batch_cols=args.batch,
-                                 out=out_buf.get("out"), profile=profile, shift_iters=True,
-                                 shifts_per_lane=args.shifts_per_lane)
-        out_buf["out"] = res._out
-        return s, prep, res
+        def step(profile):
+            s = sgf.build_hamiltonian(d_xyz, wl.tb, device=dev)
+            prep = sgf.prepare_planned(s, d_cols, d_cp, d_centers, d_radii, prune=True)
+            order = None
+            if order_mode == "learned":
+                pred = model.predict(sgf.features(prep))
+                order = sgf.order_by_prediction(pred, 0.0, float(np.log(4096.0)))
+            res = sgf.solve_prepared(prep, wl.z, wl.w, tol=wl.tol, g_out=not args.no_g, batch_cols=batch_cols,
+                                     order=order, out=out_buf.get("out"), profile=profile, shift_iters=True,
+                                     shifts_per_lane=args.shifts_per_lane)
+            out_buf["out"] = res._out
+            return s, prep, res
+        return step
 
-    for i in range(args.warmup):
-        step(False)
+    def timed(step, steps, warmup, name):
+        for i in range(warmup):
+            step(False)
+            torch.cuda.synchronize()
+            log(f"[bench] {name}: warmup {i + 1}/{warmup} done")
         torch.cuda.synchronize()
-        log(f"[bench] warmup {i + 1}/{args.warmup} done")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    prof = []
-    for i in range(args.steps):
-        s, prep, res = step(True)
-        prof.append(sgf.solve_profile())   # waits only for this step's solve events
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    seed_ms = float(np.mean([p[0] for p in prof]))
-    shift_ms = float(np.mean([p[1] for p in prof]))
-    launches = prof[-1][2]
-    log(f"[bench] {args.steps} steps: {ms_step:.2f} ms/step; seed pass {seed_ms:.2f} ms, shift pass "
-        f"{shift_ms:.2f} ms ({launches} launches each)")
+        t0 = time.perf_counter()
+        prof = []
+        for _ in range(steps):
+            s, prep, res = step(True)
+            prof.append(sgf.solve_profile())   # waits only for this step's solve events
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        seed_ms = float(np.mean([p[0] for p in prof]))
+        shift_ms = float(np.mean([p[1] for p in prof]))
+        log(f"[bench] {name}: {steps} steps, {ms:.2f} ms/step; seed pass {seed_ms:.2f} ms, shift pass "
+            f"{shift_ms:.2f} ms ({prof[-1][2]} launches each)")
+        return ms, seed_ms, shift_ms, prof[-1][2], (s, prep, res)
 
+    ms_step, seed_ms, shift_ms, launches, (s, prep, res) = timed(make_step("learned", batch), args.steps,
+                                                                 args.warmup, "fp64 batched+learned")
     iters = res.iters.cpu().numpy().astype(np.float64)
     status = res.status.cpu().numpy()
     resid = res.resid.cpu().numpy()
@@ -134,6 +182,22 @@ def main(argv=None):
     dominant = "k_shift" if shift_ms >= seed_ms else "k_seed"
     dom_ms, dom_f = (shift_ms, f_shift) if dominant == "k_shift" else (seed_ms, f_seed)
     achieved = dom_f / (dom_ms * 1e-3) / 1e12
+    variants = {"fp64_batched_learned": {"ms_per_step": ms_step, "solves_per_s": value, "seed_ms": seed_ms,
+                                         "shift_ms": shift_ms, "launches": launches, "batch_cols": batch,
+                                         "order": "learned"}}
+    if not args.no_variants:
+        rho_ref = res.rho.clone()
+        del res, prep, s
+        for name, mode, b in [("fp64_batched", "natural", batch), ("fp64_plain", "natural", args.plain_batch)]:
+            torch.cuda.empty_cache()
+            ms_v, sd_v, sh_v, l_v, (_, _, r_v) = timed(make_step(mode, b), max(2, args.steps // 2), 1, name)
+            same = bool(torch.equal(r_v.rho, rho_ref))
+            variants[name] = {"ms_per_step": ms_v, "solves_per_s": converged / (ms_v * 1e-3), "seed_ms": sd_v,
+                              "shift_ms": sh_v, "launches": l_v, "batch_cols": b, "order": mode,
+                              "rho_bitwise_equal": same}
+            del r_v
+        variants["speedup_vs_fp64_plain"] = variants["fp64_plain"]["ms_per_step"] / ms_step
+        variants["learned_gain_vs_natural_order"] = variants["fp64_batched"]["ms_per_step"] / ms_step
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -155,8 +219,9 @@ def main(argv=None):
         "config": {
             "workload": "polymer bundle 13x13 chains x 700 sp atoms (118,300 atoms), all 473,200 columns, "
                         "128 shifts E+0.01i on [-30,30] eV, R=1.0 nm pruned, tol 1e-12, FP64",
-            "columns": int(wl.columns.size), "shifts": ns, "batch_cols": args.batch,
-            "step": "build_hamiltonian + plan + shifted_solve (seed pass + shift pass)",
+            "columns": int(wl.columns.size), "shifts": ns, "batch_cols": batch,
+            "step": "build_hamiltonian + plan + features + MLP prediction + order + shifted_solve "
+                    "(seed pass + shift pass)",
         },
         "roofline": {
             "kernel": dominant,
@@ -173,6 +238,8 @@ def main(argv=None):
             },
         },
         "cpu_baseline": cpu,
+        "variants": variants,
+        "scheduler": train_info,
         "converged_solves": converged,
         "columns_not_converged": int(np.sum(status != 0)),
         "iters_mean": float(iters.mean()),

@@ -217,7 +217,7 @@ typedef struct {
                               1 LDS-staged operator; 0 operator read from global */
     int32_t grid;          /* seed-pass persistent workgroups; 0: fill the device */
     int32_t profile;       /* 1: record HIP events around each pass (read with sgf_solve_profile) */
-    int64_t batch_cols;    /* columns per history batch for sgf_solve_workspace (0: all) */
+    int64_t batch_cols;    /* columns per launch (0: all); the solve also stops at what the workspace holds */
     int32_t shifts_per_lane; /* shift pass: 1 or 2 shifts per lane; 0: chosen from the projection size */
     int32_t reserved;
 } sgf_solve_opts;
@@ -233,8 +233,8 @@ sgf_status sgf_proj_layout(const sgf_plan *plan, int64_t n_cols, const int64_t *
  * batch (0: every column at once).  Per column the workspace holds the seed
  * history: (max_iter) x 32 bytes of recurrence scalars and (max_iter + 1) x
  * 16 x 4|P|max bytes of projected residuals.  sgf_shifted_solve accepts any
- * workspace of at least one column's worth and processes the columns in as
- * many batches as it needs. */
+ * workspace of at least one column's worth and launches the columns in
+ * batches of min(batch_cols, what the workspace holds) columns. */
 sgf_status sgf_solve_workspace(const sgf_system *sys, const sgf_plan_totals *totals, int64_t n_cols,
                                int32_t n_shifts, const sgf_solve_opts *opts, size_t *ws_bytes);
 

@@ -389,7 +389,7 @@ def solve_prepared(prep: Prepared, z, w=None, tol=1e-10, precision="fp64", max_i
             "resid": torch.empty((max(n, 1), ns), dtype=torch.float64, device=dev),
             "nk": torch.empty((max(n, 1), ns), dtype=torch.int32, device=dev) if shift_iters else None,
         }
-    d_order = None if order is None else _dev(np.asarray(order, np.int32), torch.int32, dev)
+    d_order = None if order is None else _dev(order, torch.int32, dev)
     out["order"] = d_order
     _call("sgf_shifted_solve", ctypes.byref(sc), ctypes.byref(pc), ctypes.byref(prep.plan.totals), n,
           _ptr(prep.cols), _ptr(prep.col_plan), _ptr(d_order), ns, zh.ctypes.data_as(P),
@@ -402,6 +402,26 @@ def solve_prepared(prep: Prepared, z, w=None, tol=1e-10, precision="fp64", max_i
     res.shift_iters = None if out.get("nk") is None else out["nk"][:n]
     res._out = out  # keep buffers alive with the result
     return res
+
+
+def batch_limit(prep: Prepared, n_shifts, budget_bytes, max_iter=0, precision="fp64"):
+    """Largest number of columns per launch whose solve workspace (Krylov
+    history and per-column scalars) fits in budget_bytes."""
+    n = prep.cols.numel()
+    sc = prep.system.c()
+
+    def ws(batch):
+        opts = SolveOptsC({"fp64": 0, "mixed": 1}[precision], 1e-10, int(max_iter), -1, 50, -1, 0, 0, int(batch),
+                          0, 0)
+        out = ctypes.c_size_t()
+        _call("sgf_solve_workspace", ctypes.byref(sc), ctypes.byref(prep.plan.totals), max(n, 2), int(n_shifts),
+              ctypes.byref(opts), ctypes.byref(out))
+        return out.value
+
+    w1, w2 = ws(1), ws(2)
+    per = max(w2 - w1, 1)
+    fixed = w1 - per
+    return int(max(1, min(max(n, 1), (int(budget_bytes) - fixed) // per)))
 
 
 def solve_profile():

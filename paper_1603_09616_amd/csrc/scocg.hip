@@ -1000,11 +1000,18 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
     const SolveLayout L1 = solve_layout(hs, n_shifts, 1, nullptr, 0);
     SGF_REQUIRE(L1.bytes <= ws_bytes, "sgf_shifted_solve: workspace %zu bytes < %zu (one column)", ws_bytes, L1.bytes);
     if (n_cols == 0) return SGF_OK;
-    // as many history slots as the workspace holds
-    int64_t slots = (int64_t)((ws_bytes - L1.bytes) / (hs.per_col + 1024)) + 1;
-    if (slots > n_cols) slots = n_cols;
+    // columns per launch: batch_cols (0: all), at most as many history slots
+    // as the workspace holds (the largest count whose layout fits)
+    int64_t slots = opts->batch_cols > 0 && opts->batch_cols < n_cols ? opts->batch_cols : n_cols;
+    if (solve_layout(hs, n_shifts, slots, nullptr, 0).bytes > ws_bytes) {
+        int64_t lo = 1, hi = slots;  // layout(lo) fits, layout(hi) does not
+        while (hi - lo > 1) {
+            const int64_t mid = lo + (hi - lo) / 2;
+            (solve_layout(hs, n_shifts, mid, nullptr, 0).bytes <= ws_bytes ? lo : hi) = mid;
+        }
+        slots = lo;
+    }
     SolveLayout L = solve_layout(hs, n_shifts, slots, d_ws, ws_bytes);
-    while (L.bytes > ws_bytes && slots > 1) L = solve_layout(hs, n_shifts, --slots, d_ws, ws_bytes);
     hipStream_t st = as_stream(stream);
     SGF_HIP(hipMemcpyAsync(L.z, z, 16 * (size_t)n_shifts, hipMemcpyHostToDevice, st));
     if (w) SGF_HIP(hipMemcpyAsync(L.w, w, 16 * (size_t)n_shifts, hipMemcpyHostToDevice, st));

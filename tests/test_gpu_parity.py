@@ -254,13 +254,17 @@ def test_invalid_arguments(sgf):
 
 def test_bundle_full_size_sampled(sgf, O):
     """The full 118,300-atom bundle (all 473,200 columns, 128 shifts), in the
-    launch configuration the benchmark times; 160 sampled columns are
-    recomputed by the oracle."""
+    launch configuration the benchmark times (one batch of as many columns
+    as a 112 GiB workspace holds, a permuted column order); 160 sampled
+    columns are recomputed by the oracle."""
     import torch
+    torch.cuda.empty_cache()
     wl = W.config_bundle()
     s = sgf.system_for(wl)
     prep = sgf.prepare(s, wl.columns, radius=wl.radius, prune=True)
-    res = sgf.solve_prepared(prep, wl.z, wl.w, tol=wl.tol, batch_cols=8192)
+    batch = sgf.batch_limit(prep, wl.z.size, 112 << 30)
+    order = np.random.default_rng(7).permutation(wl.columns.size).astype(np.int32)
+    res = sgf.solve_prepared(prep, wl.z, wl.w, tol=wl.tol, batch_cols=batch, order=order)
     torch.cuda.synchronize()
     st = res.status.cpu().numpy()
     assert np.all(st == sgf.CONVERGED)
