@@ -209,7 +209,7 @@ typedef struct {
     int32_t precision;     /* 0: FP64 throughout; 1: mixed (complex-FP32 vectors and operator,
                               FP64 recurrence scalars, FP64 true-residual monitor and FP64 epilogue) */
     double tol;            /* shift k stops when ||s_{n+1}||_2 / |pi^k_{n+1}| <= tol ||b||_2 */
-    int32_t max_iter;      /* <= 0: 10 * (local orbitals) per column */
+    int32_t max_iter;      /* <= 0: 10 * (local orbitals) per column (mixed precision: 40 *) */
     int32_t seed_index;    /* < 0: n_shifts / 2 */
     int32_t monitor_every; /* mixed: FP64 true residual every K iterations (0: only at the end) */
     int32_t stage_lds;     /* seed pass: -1 auto (register rows for subspaces of <= 64 orbitals and
@@ -220,6 +220,15 @@ typedef struct {
     int64_t batch_cols;    /* columns per launch (0: all); the solve also stops at what the workspace holds */
     int32_t shifts_per_lane; /* shift pass: 1 or 2 shifts per lane; 0: chosen from the projection size */
     int32_t reserved;
+    double drift_tol;      /* mixed: a column stops with SGF_DRIFT when its FP64 true seed residual
+                              b - (z_s - H) x_s departs from the recursive residual by more than
+                              drift_tol ||b||_2 (checked every monitor_every iterations and at the end);
+                              0: 1e-3 */
+    double g_tol;          /* mixed: a column whose a-posteriori bound max_k ||r_k||^2 / Im z_k on the
+                              error of G_jj (r_k the FP64 true residual of the full iterate of shift
+                              k) exceeds g_tol max_k |G_jj(z_k)| gets SGF_DRIFT; 0: 5e-7 */
+    int64_t queue_len;     /* > 0: take only d_order[0 .. queue_len) from the work queue (the other
+                              columns' outputs are left untouched); 0: every column */
 } sgf_solve_opts;
 
 /* Output offsets: d_proj_off[c+1] - d_proj_off[c] = 4 * |P(plan of column c)|
@@ -232,7 +241,8 @@ sgf_status sgf_proj_layout(const sgf_plan *plan, int64_t n_cols, const int64_t *
 /* Scratch bytes for sgf_shifted_solve with opts->batch_cols columns per
  * batch (0: every column at once).  Per column the workspace holds the seed
  * history: (max_iter) x 32 bytes of recurrence scalars and (max_iter + 1) x
- * 16 x 4|P|max bytes of projected residuals.  sgf_shifted_solve accepts any
+ * 16 x 4|P|max bytes of projected residuals (mixed precision: (max_iter + 1)
+ * x 512 bytes of full residual vectors).  sgf_shifted_solve accepts any
  * workspace of at least one column's worth and launches the columns in
  * batches of min(batch_cols, what the workspace holds) columns. */
 sgf_status sgf_solve_workspace(const sgf_system *sys, const sgf_plan_totals *totals, int64_t n_cols,
@@ -264,15 +274,36 @@ sgf_status sgf_solve_workspace(const sgf_system *sys, const sgf_plan_totals *tot
  * d_iters / d_status int32[n_cols], d_resid double[n_cols][n_shifts]
  * (nullable): ||s|| / |pi^k| when shift k froze (or at the last step).
  * d_shift_iters (nullable) int32[n_cols][n_shifts]: N_k, the steps shift k took.
- * d_order (nullable) int32[n_cols]: the order in which columns are taken
- * from the work queue (a permutation of 0..n_cols-1); results do not depend
- * on it (entries outside [0, n_cols) are skipped).  Device arrays are
+ * d_order (nullable) int32[n_cols] (int32[queue_len] when opts->queue_len >
+ * 0): the order in which columns are taken from the work queue (a
+ * permutation of 0..n_cols-1, or queue_len distinct columns); results do not
+ * depend on it (entries outside [0, n_cols) are skipped).  Device arrays are
  * checked where they are read: a column whose plan index is out of range,
  * whose atom is not its plan's centre, or whose plan exceeds `totals`
  * gets SGF_BADCOLUMN and no output.  EINVAL on bad sizes, Im z_k <= 0, tol <= 0, NULL required
  * pointers or a workspace below one column's worth; EUNSUPPORTED when a plan
  * is larger than the kernels' LDS allows, a column has more than 8
  * projection atoms or n_shifts > 512.
+ *
+ * Mixed precision (opts->precision = 1; S = I, local subspaces of <= 16
+ * atoms with <= 8 blocks per row, n_shifts <= 256, sys->h32 required, else
+ * EUNSUPPORTED / EINVAL): the seed iteration runs on the FP32 shadow of H with
+ * complex-FP32 vectors and FP64 scalars (mu, rho, alpha, beta, pi^k), and
+ * keeps the seed iterate x_s in FP64; its FP64 true residual is compared
+ * with the recursive one every monitor_every iterations and at the end
+ * (SGF_DRIFT beyond drift_tol).  The shift pass rebuilds the full iterate
+ * x~^k on the local subspace (complex FP32) and writes for the diagonal
+ * element the FP64 variational estimate 2 x~_j - x~^T (z_k - H) x~^k, whose
+ * error is quadratic in that of x~ (the stationary property of the
+ * Green's-function functional for the complex symmetric z - H).  The other
+ * projection rows are the FP32-Krylov values.  From the FP64 true residual
+ * r_k of the full iterate (written to d_resid instead of the recursive
+ * residual) the shift pass bounds the error of the estimate rigorously,
+ * |G_jj - G~_jj| <= ||r_k||^2 / Im z_k, and sets SGF_DRIFT on a column
+ * whose bound exceeds opts->g_tol max_k |G~_jj|.  A caller that needs every
+ * column re-solves the non-converged ones in FP64 with queue_len (the Python
+ * binding does so).  The workspace holds the full residual history:
+ * (max_iter + 1) x 512 bytes per column.
  */
 sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *plan, const sgf_plan_totals *totals,
                              int64_t n_cols, const int64_t *d_cols, const int32_t *d_col_plan,

@@ -64,7 +64,8 @@ class PlanTotalsC(ctypes.Structure):
 class SolveOptsC(ctypes.Structure):
     _fields_ = [("precision", i32), ("tol", dbl), ("max_iter", i32), ("seed_index", i32), ("monitor_every", i32),
                 ("stage_lds", i32), ("grid", i32), ("profile", i32), ("batch_cols", i64),
-                ("shifts_per_lane", i32), ("reserved", i32)]
+                ("shifts_per_lane", i32), ("reserved", i32), ("drift_tol", dbl), ("g_tol", dbl),
+                ("queue_len", i64)]
 
 
 _lib = None
@@ -305,8 +306,12 @@ class Result:
     resid: "object"      # float64 [n_cols, n_shifts] or None
 
     def numpy(self):
-        cv = (lambda t: None if t is None else t.cpu().numpy())
-        return Result(*(cv(getattr(self, f.name)) for f in dataclasses.fields(self)))
+        cv = (lambda t: t.cpu().numpy() if hasattr(t, "cpu") else t)
+        r = Result(*(cv(getattr(self, f.name)) for f in dataclasses.fields(self)))
+        for extra in ("n_fallback", "shift_iters"):
+            if hasattr(self, extra):
+                setattr(r, extra, cv(getattr(self, extra)))
+        return r
 
     def column(self, c: int):
         a, b = int(self.proj_off[c]), int(self.proj_off[c + 1])
@@ -363,17 +368,26 @@ def _cplx_host(a) -> Optional[np.ndarray]:
 
 def solve_prepared(prep: Prepared, z, w=None, tol=1e-10, precision="fp64", max_iter=0, seed_index=-1,
                    g_out=True, order=None, batch_cols=0, stage_lds=-1, grid=0, monitor_every=50, out=None,
-                   profile=False, shift_iters=False, shifts_per_lane=0, stream=None) -> Result:
-    """Shifted COCG on every prepared column (asynchronous on the stream)."""
+                   profile=False, shift_iters=False, shifts_per_lane=0, drift_tol=0.0, g_tol=0.0, queue_len=0,
+                   fallback=True, fallback_tol=1e-9, stream=None) -> Result:
+    """Shifted COCG on every prepared column (asynchronous on the stream).
+
+    precision "mixed" builds the FP32 shadow of H first if the system has
+    none; with ``fallback`` the columns the mixed path does not accept
+    (DRIFT, MAXITER, ...) are then re-solved in FP64 at ``fallback_tol`` into
+    the same outputs (this reads the status array, so it synchronises the
+    stream); ``Result.n_fallback`` counts them."""
     torch = _torch()
     dev = prep.cols.device
     n = prep.cols.numel()
     zh = _cplx_host(z)
     wh = _cplx_host(w)
     ns = zh.size // 2
+    if precision == "mixed" and prep.system.h32 is None:
+        prep.system.add_f32(stream)
     opts = SolveOptsC({"fp64": 0, "mixed": 1}[precision], float(tol), int(max_iter), int(seed_index),
                       int(monitor_every), int(stage_lds), int(grid), int(bool(profile)), int(batch_cols),
-                      int(shifts_per_lane), 0)
+                      int(shifts_per_lane), 0, float(drift_tol), float(g_tol), int(queue_len))
     sc = prep.system.c()
     pc = prep.plan.c()
     ws = ctypes.c_size_t()
@@ -396,9 +410,24 @@ def solve_prepared(prep: Prepared, z, w=None, tol=1e-10, precision="fp64", max_i
           None if wh is None else wh.ctypes.data_as(P), ctypes.byref(opts), _ptr(out["ws"]), out["ws"].numel(),
           _ptr(prep.proj_off), _ptr(out["G"]), _ptr(out["rho"]), _ptr(out["iters"]), _ptr(out["status"]),
           _ptr(out["resid"]), _ptr(out.get("nk")), _stream(stream))
+    n_fallback = 0
+    if precision == "mixed" and fallback and n > 0 and queue_len == 0:
+        torch.cuda.current_stream(dev).synchronize() if stream is None else stream.synchronize()
+        bad = torch.nonzero(out["status"][:n] != CONVERGED).flatten().to(torch.int32)
+        n_fallback = int(bad.numel())
+        if n_fallback:
+            out["fallback_order"] = bad
+            opts64 = SolveOptsC(0, float(fallback_tol), 0, int(seed_index), 0, -1, int(grid), 0, 0,
+                                int(shifts_per_lane), 0, 0.0, 0.0, n_fallback)
+            _call("sgf_shifted_solve", ctypes.byref(sc), ctypes.byref(pc), ctypes.byref(prep.plan.totals), n,
+                  _ptr(prep.cols), _ptr(prep.col_plan), _ptr(bad), ns, zh.ctypes.data_as(P),
+                  None if wh is None else wh.ctypes.data_as(P), ctypes.byref(opts64), _ptr(out["ws"]),
+                  out["ws"].numel(), _ptr(prep.proj_off), _ptr(out["G"]), _ptr(out["rho"]), _ptr(out["iters"]),
+                  _ptr(out["status"]), _ptr(out["resid"]), _ptr(out.get("nk")), _stream(stream))
     G = None if out["G"] is None else out["G"][:prep.n_rows]
     res = Result(prep.proj_off, prep.proj_row, G, out["rho"][:prep.n_rows], out["iters"][:n], out["status"][:n],
                  out["resid"][:n])
+    res.n_fallback = n_fallback
     res.shift_iters = None if out.get("nk") is None else out["nk"][:n]
     res._out = out  # keep buffers alive with the result
     return res
@@ -412,7 +441,7 @@ def batch_limit(prep: Prepared, n_shifts, budget_bytes, max_iter=0, precision="f
 
     def ws(batch):
         opts = SolveOptsC({"fp64": 0, "mixed": 1}[precision], 1e-10, int(max_iter), -1, 50, -1, 0, 0, int(batch),
-                          0, 0)
+                          0, 0, 0.0, 0.0, 0)
         out = ctypes.c_size_t()
         _call("sgf_solve_workspace", ctypes.byref(sc), ctypes.byref(prep.plan.totals), max(n, 2), int(n_shifts),
               ctypes.byref(opts), ctypes.byref(out))
@@ -433,7 +462,8 @@ def solve_profile():
 
 def shifted_solve(system: System, columns, z, w=None, tol=1e-10, radius=0.0, radius_per_col=None, prune=True,
                   precision="fp64", max_iter=0, seed_index=-1, g_out=True, order=None, batch_cols=0, stage_lds=-1,
-                  grid=0, max_loc_atoms=2048, shifts_per_lane=0, stream=None) -> Result:
+                  grid=0, max_loc_atoms=2048, shifts_per_lane=0, monitor_every=50, drift_tol=0.0, g_tol=0.0,
+                  fallback=True, stream=None) -> Result:
     """Green's-function elements and density-matrix entries for many columns.
 
     columns: global orbital indices j; each is solved on the local subspace of
@@ -442,7 +472,8 @@ def shifted_solve(system: System, columns, z, w=None, tol=1e-10, radius=0.0, rad
     """
     prep = prepare(system, columns, radius, radius_per_col, prune, max_loc_atoms, stream)
     return solve_prepared(prep, z, w, tol, precision, max_iter, seed_index, g_out, order, batch_cols, stage_lds,
-                          grid, shifts_per_lane=shifts_per_lane, stream=stream)
+                          grid, monitor_every=monitor_every, shifts_per_lane=shifts_per_lane, drift_tol=drift_tol,
+                          g_tol=g_tol, fallback=fallback, stream=stream)
 
 
 def solve_workload(wl, system: Optional[System] = None, cols=None, prune=True, **kw) -> Result:

@@ -26,8 +26,6 @@
 
 namespace sgf {
 
-constexpr double INV_PI = 0.318309886183790671537767526745;
-constexpr int SEED_T = 64;   // seed pass: one wavefront per workgroup
 
 // ---------------------------------------------------------------------------
 // Seed pass
@@ -698,7 +696,6 @@ __global__ __launch_bounds__(SEED_T) void k_seed_gen(SolveArgs a) {
 // ---------------------------------------------------------------------------
 // Shift pass
 // ---------------------------------------------------------------------------
-constexpr int SHIFT_CH = 16;  // backward steps staged in LDS at a time
 
 // One workgroup per column; each lane carries MS shifts.  The shifts are
 // first sorted by their step count N_k so that the lanes of a wavefront (and
@@ -844,8 +841,8 @@ HistoryShape history_shape(const sgf_plan_totals &tot, int ns, const sgf_solve_o
     HistoryShape h;
     h.ns_pad = (ns + 63) / 64 * 64;
     const int nl_max = 4 * (tot.max_loc_atoms > 0 ? tot.max_loc_atoms : 1);
-    h.cap = o.max_iter > 0 ? o.max_iter : 10 * nl_max;
-    h.rmax = 4 * (tot.max_proj_atoms > 0 ? tot.max_proj_atoms : 1);
+    h.cap = o.max_iter > 0 ? o.max_iter : (o.precision == 1 ? 40 : 10) * nl_max;
+    h.rmax = o.precision == 1 ? 32 : 4 * (tot.max_proj_atoms > 0 ? tot.max_proj_atoms : 1);
     h.per_col = align_up(sizeof(ColMeta), 16) + align_up((size_t)h.ns_pad * 4, 16) + (size_t)h.cap * 32 +
                 (size_t)(h.cap + 1) * h.rmax * 16;
     h.fixed = 4096 + 2 * align_up((size_t)ns * 16);
@@ -867,7 +864,6 @@ SolveLayout solve_layout(const HistoryShape &hs, int ns, int64_t slots, void *ba
     return L;
 }
 
-using KernelFn = void (*)(SolveArgs);
 
 // Events of the last profiled solve on this thread (seed start, seed end =
 // shift start, shift end per batch).
@@ -972,6 +968,10 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
                     plan->pa_loc && plan->center_loc,
                 "sgf_shifted_solve: plan has not been built");
     SGF_REQUIRE(n_cols >= 0, "sgf_shifted_solve: n_cols < 0");
+    SGF_REQUIRE(opts->queue_len >= 0 && opts->queue_len <= n_cols && (opts->queue_len == 0 || d_order),
+                "sgf_shifted_solve: queue_len must be in [0, n_cols] and needs d_order");
+    // columns taken from the work queue: d_order[0 .. n_tickets)
+    const int64_t n_tickets = opts->queue_len > 0 ? opts->queue_len : n_cols;
     SGF_REQUIRE(n_cols == 0 || (d_cols && d_col_plan && d_proj_off && d_rho && d_iters && d_status),
                 "sgf_shifted_solve: NULL column or output array");
     SGF_REQUIRE(n_shifts >= 1, "sgf_shifted_solve: n_shifts must be >= 1");
@@ -991,9 +991,25 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
         set_error("sgf_shifted_solve: a column has %d projection atoms (limit 8)", totals->max_proj_atoms);
         return SGF_EUNSUPPORTED;
     }
-    if (opts->precision == 1) {
-        set_error("sgf_shifted_solve: the mixed-precision path is not built into this library");
-        return SGF_EUNSUPPORTED;
+    const bool mixed = opts->precision == 1;
+    if (mixed) {
+        if (sys->s) {
+            set_error("sgf_shifted_solve: the mixed-precision path supports S = I only");
+            return SGF_EUNSUPPORTED;
+        }
+        if (totals->max_loc_atoms > 16 || totals->max_row_blocks > 8) {
+            set_error("sgf_shifted_solve: the mixed-precision path needs local subspaces of <= 16 atoms with "
+                      "<= 8 blocks per row (got %d atoms, %d blocks)", totals->max_loc_atoms,
+                      totals->max_row_blocks);
+            return SGF_EUNSUPPORTED;
+        }
+        if (n_shifts > 256) {
+            set_error("sgf_shifted_solve: the mixed-precision path takes at most 256 shifts (got %d)", n_shifts);
+            return SGF_EUNSUPPORTED;
+        }
+        SGF_REQUIRE(sys->h32, "sgf_shifted_solve: the mixed-precision path needs the FP32 shadow h32 (sgf_to_f32)");
+        SGF_REQUIRE(opts->drift_tol >= 0 && opts->g_tol >= 0, "sgf_shifted_solve: drift_tol and g_tol must be >= 0");
+        SGF_REQUIRE(opts->monitor_every >= 0, "sgf_shifted_solve: monitor_every must be >= 0");
     }
     SGF_REQUIRE(d_ws, "sgf_shifted_solve: workspace is NULL");
     const HistoryShape hs = history_shape(*totals, n_shifts, *opts);
@@ -1002,7 +1018,7 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
     if (n_cols == 0) return SGF_OK;
     // columns per launch: batch_cols (0: all), at most as many history slots
     // as the workspace holds (the largest count whose layout fits)
-    int64_t slots = opts->batch_cols > 0 && opts->batch_cols < n_cols ? opts->batch_cols : n_cols;
+    int64_t slots = opts->batch_cols > 0 && opts->batch_cols < n_tickets ? opts->batch_cols : n_tickets;
     if (solve_layout(hs, n_shifts, slots, nullptr, 0).bytes > ws_bytes) {
         int64_t lo = 1, hi = slots;  // layout(lo) fits, layout(hi) does not
         while (hi - lo > 1) {
@@ -1021,6 +1037,7 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
     a.col = sys->col;
     a.h = sys->h;
     a.s = sys->s;
+    a.h32 = sys->h32;
     a.atom_off = plan->atom_off;
     a.blk_off = plan->blk_off;
     a.pa_off = plan->pa_off;
@@ -1044,6 +1061,9 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
     a.w = w ? L.w : nullptr;
     a.tol = opts->tol;
     a.max_iter = opts->max_iter;
+    a.monitor_every = opts->monitor_every;
+    a.drift_tol = opts->drift_tol > 0 ? opts->drift_tol : 1e-3;
+    a.g_tol = opts->g_tol > 0 ? opts->g_tol : 5e-7;
     a.proj_off = d_proj_off;
     a.G = d_G;
     a.rho = d_rho;
@@ -1083,8 +1103,10 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
     // register variant when every subspace has <= 64 orbitals and <= 8 blocks per row
     const bool gen = sys->s != nullptr;
     const bool r1 = !gen && opts->stage_lds < 0 && totals->max_loc_atoms <= 16 && totals->max_row_blocks <= 8;
-    KernelFn seed_fn = gen ? pick_seed_gen(M) : (r1 ? pick_seed_r1(M, totals->max_row_blocks) : pick_seed(stage, M));
-    size_t seed_lds = r1 ? 0 : lds;
+    KernelFn seed_fn = mixed ? pick_seed_mx(M, totals->max_row_blocks)
+                             : gen ? pick_seed_gen(M)
+                                   : (r1 ? pick_seed_r1(M, totals->max_row_blocks) : pick_seed(stage, M));
+    size_t seed_lds = (r1 || mixed) ? 0 : lds;
     if (gen) {
         // p, s, w, q, r and the dense inverse of the local overlap
         size_t goff = 0;
@@ -1103,10 +1125,15 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
             return SGF_EUNSUPPORTED;
         }
     }
-    const int ms = shift_ms(totals->max_proj_atoms, opts->shifts_per_lane);
-    KernelFn shift_fn = pick_shift(totals->max_proj_atoms, ms);
+    const int ms = mixed ? 1 : shift_ms(totals->max_proj_atoms, opts->shifts_per_lane);
+    KernelFn shift_fn = mixed ? shift_mx_kernel() : pick_shift(totals->max_proj_atoms, ms);
     // shift-pass workgroup: ns_pad / ms lanes rounded up to whole wavefronts (<= 512)
     const int shift_threads = ((hs.ns_pad / ms + 63) / 64) * 64;
+    // mixed: the full iterates of every shift, complex FP32 [64][ns_pad]
+    const size_t shift_lds = mixed ? (size_t)64 * hs.ns_pad * 8 : 0;
+    if (mixed)
+        SGF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(shift_fn),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shift_lds));
     SGF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(seed_fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)seed_lds));
     int per_cu = 0;
@@ -1124,8 +1151,8 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
     Profile &prof = g_profile;
     prof.release();
     const bool timed = opts->profile != 0;
-    for (int64_t b0 = 0; b0 < n_cols; b0 += slots) {
-        const int64_t b1 = b0 + slots < n_cols ? b0 + slots : n_cols;
+    for (int64_t b0 = 0; b0 < n_tickets; b0 += slots) {
+        const int64_t b1 = b0 + slots < n_tickets ? b0 + slots : n_tickets;
         a.batch_begin = b0;
         a.batch_end = b1;
         const int64_t grid = seed_grid_max < b1 - b0 ? seed_grid_max : b1 - b0;
@@ -1141,7 +1168,7 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
         hipLaunchKernelGGL(seed_fn, dim3((unsigned)grid), dim3(SEED_T), seed_lds, st, a);
         SGF_LAUNCHED();
         if (timed) SGF_HIP(hipEventRecord(e1, st));
-        hipLaunchKernelGGL(shift_fn, dim3((unsigned)(b1 - b0)), dim3(shift_threads), 0, st, a);
+        hipLaunchKernelGGL(shift_fn, dim3((unsigned)(b1 - b0)), dim3(shift_threads), shift_lds, st, a);
         SGF_LAUNCHED();
         if (timed) SGF_HIP(hipEventRecord(e2, st));
     }

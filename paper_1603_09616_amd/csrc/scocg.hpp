@@ -6,11 +6,15 @@
 
 namespace sgf {
 
+constexpr int SEED_T = 64;    // seed pass: one wavefront per workgroup
+constexpr int SHIFT_CH = 16;  // shift pass: backward steps staged in LDS at a time
+constexpr double INV_PI = 0.318309886183790671537767526745;
+
 // Column metadata written by the seed pass for the shift pass.
 struct ColMeta {
     int32_t col;     // column index (-1: slot unused or rejected)
     int32_t iters;   // seed iterations performed
-    int32_t npa;     // projection atoms
+    int32_t npa;     // projection atoms (mixed path: | local atoms << 8)
     int32_t status;  // sgf_col_status
 };
 
@@ -18,6 +22,7 @@ struct SolveArgs {
     // system (device)
     const int32_t *row_ptr, *col;
     const double *h, *s;
+    const float *h32;   // FP32 shadow of h (mixed path)
     // plan (device)
     const int64_t *atom_off, *blk_off, *pa_off;
     const int32_t *loc_atom, *lrow, *lblk, *pa_loc, *center_loc;
@@ -34,6 +39,9 @@ struct SolveArgs {
     const double2 *z, *w;
     double tol;
     int max_iter;       // per column; <= 0: 10 * (local orbitals)
+    int monitor_every;  // mixed: FP64 true-residual check every K iterations (0: at the end only)
+    double drift_tol;   // mixed: DRIFT when ||b - A x_s - s|| > drift_tol ||b||
+    double g_tol;       // mixed: DRIFT when max_k ||r_k||^2 / Im z_k > g_tol max_k |G~_jj(z_k)|
     // outputs
     const int64_t *proj_off;
     double *G, *rho, *resid;
@@ -45,6 +53,7 @@ struct SolveArgs {
     int32_t *nk;        // [slots][ns_pad] freeze iteration of every shift
     double2 *hab;       // [slots][cap][2]: 1/alpha_n, beta_n/alpha_n
     double2 *hr;        // [slots][cap+1][rmax]: projected residuals r_n on P
+                        // (mixed: the same bytes hold r_n on all 64 rows as float2)
     int64_t *ticket;
     // seed-pass LDS carve (bytes)
     size_t off_p, off_s, off_w, off_hs, off_cs, off_rs, off_q, off_r, off_sinv;
@@ -68,5 +77,11 @@ struct HistoryShape {
 
 HistoryShape history_shape(const sgf_plan_totals &tot, int ns, const sgf_solve_opts &o);
 SolveLayout solve_layout(const HistoryShape &hs, int ns, int64_t slots, void *base, size_t cap);
+
+using KernelFn = void (*)(SolveArgs);
+
+// Mixed-precision passes (mixed.hip).
+KernelFn pick_seed_mx(int M, int bmax);
+KernelFn shift_mx_kernel();
 
 }  // namespace sgf
