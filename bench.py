@@ -120,14 +120,13 @@ def main(argv=None):
     log(f"[bench] scheduler trained on {train_info['logged_solves']} logged solves in {train_info['train_s']} s: "
         f"held-out MSE {train_info['heldout_mse']:.4f} (target variance {train_info['target_var']:.4f})")
 
-    s0 = sgf.build_hamiltonian(d_xyz, wl.tb, device=dev)
-    p0 = sgf.prepare_planned(s0, d_cols, d_cp, d_centers, d_radii, prune=True)
-    batch = args.batch or sgf.batch_limit(p0, ns, int(args.ws_gib * (1 << 30)))
-    del s0, p0
+    s_probe = sgf.build_hamiltonian(d_xyz, wl.tb, device=dev)
+    p_probe = sgf.prepare_planned(s_probe, d_cols, d_cp, d_centers, d_radii, prune=True)
+    batch = args.batch or sgf.batch_limit(p_probe, ns, int(args.ws_gib * (1 << 30)))
     log(f"[bench] workload {wl.name}: {wl.n_atoms} atoms, {wl.columns.size} columns, {ns} shifts, "
         f"batch {batch}")
 
-    def make_step(order_mode, batch_cols):
+    def make_step(order_mode, batch_cols, precision="fp64", tol=wl.tol):
         out_buf = {}
 
         def step(profile):
@@ -137,9 +136,9 @@ def main(argv=None):
             if order_mode == "learned":
                 pred = model.predict(sgf.features(prep))
                 order = sgf.order_by_prediction(pred, 0.0, float(np.log(4096.0)))
-            res = sgf.solve_prepared(prep, wl.z, wl.w, tol=wl.tol, g_out=not args.no_g, batch_cols=batch_cols,
-                                     order=order, out=out_buf.get("out"), profile=profile, shift_iters=True,
-                                     shifts_per_lane=args.shifts_per_lane)
+            res = sgf.solve_prepared(prep, wl.z, wl.w, tol=tol, precision=precision, g_out=not args.no_g,
+                                     batch_cols=batch_cols, order=order, out=out_buf.get("out"), profile=profile,
+                                     shift_iters=True, shifts_per_lane=args.shifts_per_lane)
             out_buf["out"] = res._out
             return s, prep, res
         return step
@@ -163,6 +162,19 @@ def main(argv=None):
             f"{shift_ms:.2f} ms ({prof[-1][2]} launches each)")
         return ms, seed_ms, shift_ms, prof[-1][2], (s, prep, res)
 
+    # columns whose outputs are checked against the oracle (the first chunk of
+    # the CPU-baseline sample)
+    check_cols = None if args.no_cpu_baseline else baseline_sample(wl)[:1024]
+    samples = {}
+
+    def keep_sample(name, prep, res):
+        if check_cols is None or res.G is None:
+            return
+        off = prep.proj_off.cpu().numpy()
+        rows = np.concatenate([np.arange(off[c], off[c + 1]) for c in check_cols])
+        idx = torch.as_tensor(rows, device=dev)
+        samples[name] = (res.G[idx].cpu().numpy(), res.rho[idx].cpu().numpy(), res.status.cpu().numpy()[check_cols])
+
     ms_step, seed_ms, shift_ms, launches, (s, prep, res) = timed(make_step("learned", batch), args.steps,
                                                                  args.warmup, "fp64 batched+learned")
     iters = res.iters.cpu().numpy().astype(np.float64)
@@ -184,24 +196,44 @@ def main(argv=None):
     achieved = dom_f / (dom_ms * 1e-3) / 1e12
     variants = {"fp64_batched_learned": {"ms_per_step": ms_step, "solves_per_s": value, "seed_ms": seed_ms,
                                          "shift_ms": shift_ms, "launches": launches, "batch_cols": batch,
-                                         "order": "learned"}}
+                                         "order": "learned", "tol": wl.tol}}
+    keep_sample("fp64_batched_learned", prep, res)
     if not args.no_variants:
         rho_ref = res.rho.clone()
         del res, prep, s
-        for name, mode, b in [("fp64_batched", "natural", batch), ("fp64_plain", "natural", args.plain_batch)]:
+        mixed_batch = args.batch or sgf.batch_limit(p_probe, ns, int(args.ws_gib * (1 << 30)), precision="mixed")
+        specs = [("fp64_batched", "natural", batch, "fp64", wl.tol),
+                 ("fp64_plain", "natural", args.plain_batch, "fp64", wl.tol),
+                 ("mixed_batched_learned", "learned", mixed_batch, "mixed", 1e-5),
+                 ("fp64_batched_learned_tol1e-8", "learned", batch, "fp64", 1e-8),
+                 ("fp64_plain_tol1e-8", "natural", args.plain_batch, "fp64", 1e-8)]
+        for name, mode, b, prec, tol in specs:
             torch.cuda.empty_cache()
-            ms_v, sd_v, sh_v, l_v, (_, _, r_v) = timed(make_step(mode, b), max(2, args.steps // 2), 1, name)
-            same = bool(torch.equal(r_v.rho, rho_ref))
-            variants[name] = {"ms_per_step": ms_v, "solves_per_s": converged / (ms_v * 1e-3), "seed_ms": sd_v,
-                              "shift_ms": sh_v, "launches": l_v, "batch_cols": b, "order": mode,
-                              "rho_bitwise_equal": same}
-            del r_v
+            ms_v, sd_v, sh_v, l_v, (_, p_v, r_v) = timed(make_step(mode, b, prec, tol), max(2, args.steps // 2), 1,
+                                                          name)
+            conv_v = int(np.sum(r_v.status.cpu().numpy() == sgf.CONVERGED)) * ns
+            variants[name] = {"ms_per_step": ms_v, "solves_per_s": conv_v / (ms_v * 1e-3), "seed_ms": sd_v,
+                              "shift_ms": sh_v, "launches": l_v, "batch_cols": b, "order": mode, "tol": tol,
+                              "precision": prec}
+            if prec == "mixed":
+                variants[name]["fp64_fallback_columns"] = int(getattr(r_v, "n_fallback", 0))
+            if tol == wl.tol:
+                variants[name]["rho_bitwise_equal"] = bool(torch.equal(r_v.rho, rho_ref))
+            keep_sample(name, p_v, r_v)
+            del r_v, p_v
+        plain_eq = variants["fp64_plain_tol1e-8"]["ms_per_step"]
         variants["speedup_vs_fp64_plain"] = variants["fp64_plain"]["ms_per_step"] / ms_step
         variants["learned_gain_vs_natural_order"] = variants["fp64_batched"]["ms_per_step"] / ms_step
+        variants["speedup_mixed_vs_fp64_plain_equal_accuracy"] = plain_eq / variants["mixed_batched_learned"][
+            "ms_per_step"]
+        variants["speedup_fp64_batched_learned_vs_plain_equal_accuracy"] = plain_eq / variants[
+            "fp64_batched_learned_tol1e-8"]["ms_per_step"]
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(wl, args.cpu_seconds)
+        cpu, ref = cpu_baseline(wl, args.cpu_seconds)
+        for name, (G, rho, st) in samples.items():
+            variants.setdefault(name, {})["accuracy_vs_oracle"] = accuracy(wl, check_cols, ref, G, rho, st)
 
     line = {
         "metric": "converged (column x shift) solves/s at tol 1e-12",
@@ -248,25 +280,57 @@ def main(argv=None):
     return 0
 
 
+def baseline_sample(wl):
+    """Seeded random order of the workload's columns (indices into wl.columns)."""
+    return np.random.default_rng(1603).permutation(wl.columns.size)
+
+
 def cpu_baseline(wl, seconds):
-    """The FP64 oracle on a seeded sample of the same columns, for ~`seconds`."""
+    """The FP64 oracle on a seeded sample of the same columns, for ~`seconds`.
+    Also returns the oracle's results for the first chunk (1024 columns),
+    against which the GPU variants' outputs are checked."""
     import oracle
     threads = len(os.sched_getaffinity(0))
     threads = min(threads, int(os.environ.get("OMP_NUM_THREADS", threads)))
     b = oracle.system_for(wl)
-    order = np.random.default_rng(1603).permutation(wl.columns.size)
+    order = baseline_sample(wl)
     done = conv = 0
     chunk = 1024
+    first = None
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < seconds and done < order.size:
-        cols = np.sort(wl.columns[order[done:done + chunk]])
-        r = oracle.solve_workload(wl, b, cols=cols, threads=threads)
+        pick = order[done:done + chunk]
+        r = oracle.solve_workload(wl, b, cols=wl.columns[pick], threads=threads)
+        if first is None:
+            first = r
         conv += int(np.sum(r.resid <= wl.tol))
-        done += cols.size
+        done += pick.size
     dt = time.perf_counter() - t0
     log(f"[bench] oracle: {done} columns in {dt:.1f} s on {threads} threads")
-    return {"value": conv / dt, "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done} seeded random columns of the same workload (all 128 shifts), {dt:.1f} s wall"}
+    return ({"value": conv / dt, "unit": "solves/s", "cores": threads, "kind": "oracle",
+             "sample": f"{done} seeded random columns of the same workload (all 128 shifts), {dt:.1f} s wall"},
+            first)
+
+
+def accuracy(wl, cols, ref, G, rho, status):
+    """Errors of one variant's outputs on the checked columns against the
+    oracle: all projection rows of G (max |dG| / max |G| per column), the
+    diagonal G_jj (same, over its shifts; and the worst single shift,
+    relative) and rho (max |drho| / max |rho| per column, and its diagonal)."""
+    e_all = e_jj = e_jj_shift = e_rho = e_rho_jj = 0.0
+    for i, c in enumerate(cols):
+        a, b = ref.proj_ptr[i], ref.proj_ptr[i + 1]
+        d = a + int(np.nonzero(ref.proj_row[a:b] == wl.columns[c])[0][0])
+        scale = np.abs(ref.G[a:b]).max()
+        e_all = max(e_all, np.abs(G[a:b] - ref.G[a:b]).max() / scale)
+        e_jj = max(e_jj, np.abs(G[d] - ref.G[d]).max() / np.abs(ref.G[d]).max())
+        e_jj_shift = max(e_jj_shift, float((np.abs(G[d] - ref.G[d]) / np.abs(ref.G[d])).max()))
+        rs = max(np.abs(ref.rho[a:b]).max(), 1e-300)
+        e_rho = max(e_rho, np.abs(rho[a:b] - ref.rho[a:b]).max() / rs)
+        e_rho_jj = max(e_rho_jj, abs(rho[d] - ref.rho[d]) / rs)
+    return {"columns": int(len(cols)), "G_rows_normwise": e_all, "G_jj_normwise": e_jj,
+            "G_jj_worst_shift": e_jj_shift, "rho_normwise": e_rho, "rho_jj": e_rho_jj,
+            "not_converged": int(np.sum(status != 0))}
 
 
 if __name__ == "__main__":

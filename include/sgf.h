@@ -313,7 +313,7 @@ sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *plan, const 
                              int32_t *d_shift_iters, void *stream);
 
 /* Kernel times of the last sgf_shifted_solve on this thread that ran with
- * opts->profile = 1, from HIP events recorded on its stream around every
+ * opts->profile = 1 (later unprofiled solves do not replace it), from HIP events recorded on its stream around every
  * launch of the seed pass and of the shift pass.  SYNCHRONOUS (waits for
  * those events).  *batches = number of launches of each pass.  EINVAL if no
  * profiled solve is pending; the events are released by this call. */

@@ -1149,8 +1149,8 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
     const int64_t seed_grid_max = opts->grid > 0 ? opts->grid : (int64_t)per_cu * n_cu;
 
     Profile &prof = g_profile;
-    prof.release();
     const bool timed = opts->profile != 0;
+    if (timed) prof.release();  // an unprofiled solve leaves the last profiled one readable
     for (int64_t b0 = 0; b0 < n_tickets; b0 += slots) {
         const int64_t b1 = b0 + slots < n_tickets ? b0 + slots : n_tickets;
         a.batch_begin = b0;
