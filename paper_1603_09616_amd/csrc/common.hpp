@@ -79,12 +79,30 @@ __device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 c) {
 // real * complex
 __device__ __forceinline__ double2 rmul(double r, double2 b) { return make_double2(r * b.x, r * b.y); }
 // 1 / a: both parts are first scaled by a power of two (exact) so that |a|^2
-// neither overflows nor underflows; one division.
+// neither overflows nor underflows; one correctly rounded division.  The
+// seed recurrences use this one: COCG has no look-ahead, so near a
+// breakdown its trajectory is sensitive to the rounding of its scalars.
 __device__ __forceinline__ double2 crcp(double2 a) {
     const int e = ilogb(fmax(fabs(a.x), fabs(a.y)));
     const double x = ldexp(a.x, -e), y = ldexp(a.y, -e);
     const double inv = 1.0 / fma(x, x, y * y);
     return make_double2(ldexp(x * inv, -e), ldexp(-y * inv, -e));
+}
+// 1 / a = conj(a) / |a|^2 with a shorter dependency chain, for the pivots of
+// the shift pass (which feed nothing back into the Krylov process): when
+// |a|^2 is comfortably inside the normal range its reciprocal comes from the
+// hardware estimate refined by two Newton steps r <- r + r (1 - n r) (each
+// squares the relative error; the result is within about an ulp), otherwise
+// the scaled division above.
+__device__ __forceinline__ double2 crcp_fast(double2 a) {
+    const double n = fma(a.x, a.x, a.y * a.y);
+    if (n >= 0x1p-1000 && n <= 0x1p+1000) {
+        double r = __builtin_amdgcn_rcp(n);
+        r = fma(r, fma(-n, r, 1.0), r);
+        r = fma(r, fma(-n, r, 1.0), r);
+        return make_double2(a.x * r, -a.y * r);
+    }
+    return crcp(a);
 }
 __device__ __forceinline__ double2 cdiv(double2 a, double2 b) { return cmul(a, crcp(b)); }
 __device__ __forceinline__ bool cfinite(double2 a) { return isfinite(a.x) && isfinite(a.y); }

@@ -356,7 +356,7 @@ __global__ __launch_bounds__(256) void k_shift_mx(SolveArgs a) {
                                            fmaf(gf.x, S[r].y, fmaf(gf.y, S[r].x, rv.y)));
                     }
                 }
-                const double2 inv = crcp(d);
+                const double2 inv = crcp_fast(d);
                 if (m > 0) g = cmul(ia_p, inv);
                 else y0 = inv;
             }

@@ -347,7 +347,7 @@ __global__ __launch_bounds__(SEED_T) void k_seed_r1(SolveArgs a) {
             res[m] = 1.0;
         }
         double2 rho = one, inv_rho = one;
-        double2 alpha_old = one, beta_old = zero, ia_old = one;
+        double2 ba_old = zero;  // beta_{n-1} / alpha_{n-1}
         int status = SGF_MAXITER, iters = 0, applied = 0;
         double snorm2 = 1.0;
         const int max_iter = a.max_iter > 0 ? a.max_iter : 10 * nl;
@@ -371,7 +371,7 @@ __global__ __launch_bounds__(SEED_T) void k_seed_r1(SolveArgs a) {
             const double2 mu = make_double2(wave_reduce(fma(p.x, w.x, -p.y * w.y)),
                                             wave_reduce(fma(p.x, w.y, p.y * w.x)));
             iters = it + 1;
-            if (!cfinite(mu) || !cfinite(rho)) { status = SGF_NONFINITE; break; }
+            if (!cfinite(mu)) { status = SGF_NONFINITE; break; }  // rho was checked when it was formed
             if (mu.x == 0.0 && mu.y == 0.0) { status = SGF_BREAKDOWN; break; }
             const double2 alpha = cmul(rho, crcp(mu));
             const double2 ia = cmul(mu, inv_rho);  // 1/alpha
@@ -382,23 +382,28 @@ __global__ __launch_bounds__(SEED_T) void k_seed_r1(SolveArgs a) {
                                                  wave_reduce(2.0 * s.x * s.y));
             snorm2 = wave_reduce(fma(s.x, s.x, s.y * s.y));
             const double2 beta = cmul(rho_new, inv_rho);
+            const double2 ba = cmul(beta, ia);  // beta_n / alpha_n
             p = cfma(beta, p, s);
             vp[lane] = p;
 
             // history: 1/alpha_n, beta_n/alpha_n, r_{n+1} on P
             if (lane == 0) {
                 hab[2 * it] = ia;
-                hab[2 * it + 1] = cmul(beta, ia);
+                hab[2 * it + 1] = ba;
             }
             if (pidx >= 0) hr[(size_t)(it + 1) * a.rmax + pidx] = s;
 
-            // collinearity factors; freeze test ||s|| <= tol |pi^k|
-            const double2 coup = cmul(cmul(alpha, beta_old), ia_old);
+            // collinearity factors; freeze test ||s|| <= tol |pi^k|.
+            // pi^k_{n+1} = (1 + alpha sigma_k) pi^k_n + c (pi^k_n - pi^k_{n-1})
+            //            = (1 + c + alpha sigma_k) pi^k_n - c pi^k_{n-1},
+            // c = alpha_n beta_{n-1} / alpha_{n-1}
+            const double2 coup = cmul(alpha, ba_old);
+            const double2 c1 = cadd(one, coup), ncoup = make_double2(-coup.x, -coup.y);
             int alive = 0;
 #pragma unroll
             for (int m = 0; m < M; ++m) {
                 if (!act[m]) continue;
-                const double2 pn = cadd(cmul(cfma(alpha, sigma[m], one), pc[m]), cmul(coup, csub(pc[m], po[m])));
+                const double2 pn = cfma(cfma(alpha, sigma[m], c1), pc[m], cmul(ncoup, po[m]));
                 po[m] = pc[m];
                 pc[m] = pn;
                 const double pn2 = fma(pn.x, pn.x, pn.y * pn.y);
@@ -411,15 +416,14 @@ __global__ __launch_bounds__(SEED_T) void k_seed_r1(SolveArgs a) {
                 }
             }
             applied = it + 1;
-            alpha_old = alpha;
-            beta_old = beta;
-            ia_old = ia;
+            ba_old = ba;
             rho = rho_new;
             wave_lds_fence();  // p is in LDS for the next block product
             const bool any_alive = __any(alive);
             if (!any_alive || snorm2 == 0.0) { status = SGF_CONVERGED; break; }
             if (rho_new.x == 0.0 && rho_new.y == 0.0) { status = SGF_BREAKDOWN; break; }
-            if (!cfinite(rho_new) || !isfinite(snorm2)) { status = SGF_NONFINITE; break; }
+            // a NaN or an infinity anywhere makes the sum non-finite
+            if (!isfinite(rho_new.x + rho_new.y + snorm2)) { status = SGF_NONFINITE; break; }
             inv_rho = crcp(rho_new);
         }
 
@@ -791,7 +795,7 @@ __global__ __launch_bounds__(512) void k_shift(SolveArgs a) {
                         for (int o = 0; o < 4; ++o) S[u][4 * q + o] = cfma(g[u], S[u][4 * q + o], rm[4 * q + o]);
                     }
                 }
-                const double2 inv = crcp(d);
+                const double2 inv = crcp_fast(d);
                 if (m > 0) g[u] = cmul(ia_p, inv);
                 else y0[u] = inv;
             }
@@ -906,7 +910,9 @@ static KernelFn pick_seed_r1_m(int M) {
     }
 }
 
-static KernelFn pick_seed_r1(int M, int bmax) { return bmax <= 6 ? pick_seed_r1_m<6>(M) : pick_seed_r1_m<8>(M); }
+static KernelFn pick_seed_r1(int M, int bmax) {
+    return bmax <= 5 ? pick_seed_r1_m<5>(M) : bmax <= 6 ? pick_seed_r1_m<6>(M) : pick_seed_r1_m<8>(M);
+}
 
 static KernelFn pick_seed_gen(int M) {
     switch (M) {
