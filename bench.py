@@ -79,6 +79,97 @@ def train_scheduler(sgf, W, dev, n_logged=50000):
     return model, info
 
 
+CSRC = os.path.join(ROOT, "paper_1603_09616_amd", "csrc")
+
+
+def kernel_fingerprint(kind):
+    """sha256 over the source a kernel is built from: its own function text
+    (for the solver passes) or file, and the shared device helpers.  Counter
+    figures recorded in profiles/ apply only while this matches."""
+    import hashlib
+    import re
+    common = open(os.path.join(CSRC, "common.hpp")).read()
+    if kind == "apply":
+        text = open(os.path.join(CSRC, "apply.hip")).read()
+    else:
+        src = open(os.path.join(CSRC, "scocg.hip")).read()
+        head = {"seed": r"template <int M, int BMAX>\n__global__ __launch_bounds__\(SEED_T\) void k_seed_r1",
+                "shift": r"template <int NPA, int MS>\n__global__ __launch_bounds__\(512\) void k_shift"}[kind]
+        m = re.search(head, src)
+        if m is None:
+            return None
+        end = src.find("\n}\n", m.start())
+        text = src[m.start():end + 3]
+    return hashlib.sha256((text + common).encode()).hexdigest()
+
+
+def recorded_traffic(kernel, kind):
+    """HBM bytes per launch from the committed counter record, scaled by the
+    copy reference; None when absent or when the kernel changed since."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    k = rec.get("kernels", {}).get(kernel)
+    if not k or k.get("fingerprint") != kernel_fingerprint(kind):
+        return None
+    sc = rec["copy_reference"]
+    return k["fetch_kib"] * 1024 * sc["fetch_scale"] + k["write_kib"] * 1024 * sc["write_scale"]
+
+
+def hbm_stream(sgf, W, dev, reps=50):
+    """The global operator apply y = (z - H) x on the 1,000,300-atom share
+    (570 MB of FP64 blocks, larger than the 256 MB last-level cache), timed
+    with HIP events over `reps` launches per case on the launch stream.
+    Algorithmic bytes per launch: the blocks, their column indices and row
+    pointers once, x read once and y written once."""
+    import torch
+    wl = W.config_large(n_columns=16)
+    s = sgf.system_for(wl)
+    s.add_f32()
+    n = 4 * s.n_atoms
+    z = complex(wl.z[128])
+    g = torch.Generator(device=dev).manual_seed(3)
+    cases = {}
+    for prec, dt, bc, dtn in (("fp64", torch.float64, 16, "double"), ("fp32", torch.float32, 8, "float")):
+        for k in (1, 4, 8):
+            x = torch.complex(torch.randn((n, k), dtype=dt, device=dev, generator=g),
+                              torch.randn((n, k), dtype=dt, device=dev, generator=g)).contiguous()
+            y = torch.empty_like(x)
+            for _ in range(3):
+                sgf.bsr_apply(s, z, x, prec, out=y)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                sgf.bsr_apply(s, z, x, prec, out=y)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            nbytes = s.nnzb * (16 * bc // 2 + 4) + (s.n_atoms + 1) * 4 + 2 * n * k * bc
+            name = {1: f"k_bsr_apply<{dtn}, 1, false>"}.get(k, f"k_bsr_apply_br<{dtn}, {k}, false>")
+            traffic = recorded_traffic(name, "apply")
+            cases[f"{prec}_rhs{k}"] = {"ms": ms, "bytes": nbytes, "GBps": nbytes / ms / 1e6,
+                                       "frac": nbytes / ms / 1e6 / PEAK_HBM_GBS, "traffic": traffic,
+                                       "traffic_GBps": None if traffic is None else traffic / ms / 1e6}
+            log(f"[bench] bsr_apply {prec} x{k}: {ms * 1e3:.1f} us, {nbytes / ms / 1e6:.0f} GB/s")
+            del x, y
+    best = max(cases, key=lambda c: cases[c]["GBps"])
+    return {"kernel": "k_bsr_apply", "workload": "y = (z - H) x on the 1,000,300-atom bundle share "
+            f"({s.n_atoms} block rows, {s.nnzb} 4x4 blocks)", "peak_GBps": PEAK_HBM_GBS, "reps": reps,
+            "cases": cases, "best": best, "best_frac": cases[best]["frac"]}
+
+
+def copy_reference(dev, nbytes=1 << 30, reps=10):
+    """A plain device copy of known size (for scaling HBM counters)."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return {"bytes_read": nbytes, "bytes_written": nbytes, "launches": reps}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +183,9 @@ def main(argv=None):
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-g", action="store_true", help="skip writing G (rho only)")
     ap.add_argument("--shifts-per-lane", type=int, default=0)
+    ap.add_argument("--no-hbm", action="store_true", help="skip the HBM-bound operator-apply measurement")
+    ap.add_argument("--spmv-only", action="store_true",
+                    help="only the operator-apply measurement and a 1 GiB copy (for counter passes)")
     args = ap.parse_args(argv)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: every run of this path uses a single MI355X; columns are "
@@ -106,6 +200,9 @@ def main(argv=None):
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.spmv_only:
+        print(json.dumps({"hbm_stream": hbm_stream(sgf, W, dev), "copy": copy_reference(dev)}), flush=True)
+        return 0
     wl = W.config_bundle()
     ns = wl.z.size
     # resident inputs: positions, columns and their subspace centres
@@ -229,6 +326,12 @@ def main(argv=None):
         variants["speedup_fp64_batched_learned_vs_plain_equal_accuracy"] = plain_eq / variants[
             "fp64_batched_learned_tol1e-8"]["ms_per_step"]
 
+    hbm = None
+    if not args.no_hbm:
+        del s_probe, p_probe
+        torch.cuda.empty_cache()
+        hbm = hbm_stream(sgf, W, dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu, ref = cpu_baseline(wl, args.cpu_seconds)
@@ -262,7 +365,8 @@ def main(argv=None):
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_TFLOPS,
-            "traffic": None,
+            "traffic": recorded_traffic("k_seed_r1<2, 5>" if dominant == "k_seed" else "k_shift<5, 1>",
+                                        "seed" if dominant == "k_seed" else "shift"),
             "launches_per_step": launches,
             "passes": {
                 "k_seed": {"ms_per_step": seed_ms, "tflop_per_step": f_seed / 1e12, "tflops": seed_tf},
@@ -270,6 +374,7 @@ def main(argv=None):
             },
         },
         "cpu_baseline": cpu,
+        "hbm_stream": hbm,
         "variants": variants,
         "scheduler": train_info,
         "converged_solves": converged,

@@ -320,6 +320,22 @@ sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *plan, const 
 sgf_status sgf_solve_profile(double *seed_ms, double *shift_ms, int32_t *batches);
 
 /* ------------------------------------------------------------------------ */
+/* Global operator application                                                */
+/* ------------------------------------------------------------------------ */
+/* d_y = (z S - H) d_x for n_rhs (1, 2, 4 or 8) complex right-hand sides over
+ * the whole system: the operator of the shifted equations (zS - H)x = b of
+ * the Introduction, applied once (e.g. to check a full-system solution
+ * against its right-hand side in FP64).  z: HOST complex (re, im).
+ * precision 0: FP64 operator (h, s), d_x / d_y complex128; 1: FP32 shadows
+ * (h32, s32), complex64.  Layout [4 n_atoms][n_rhs] (right-hand sides
+ * contiguous per orbital); d_x and d_y must not alias.  S = I when the
+ * system has no overlap.  Asynchronous on the stream.  One pass over the
+ * matrix in HBM: 16 n_rhs complex multiply-adds per 4x4 block, so the call
+ * is bound by HBM bandwidth. */
+sgf_status sgf_bsr_apply(const sgf_system *sys, int32_t precision, int32_t n_rhs, const double *z, const void *d_x,
+                         void *d_y, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Learned scheduling                                                         */
 /* ------------------------------------------------------------------------ */
 /* A small network predicts how many Krylov iterations a column needs from

@@ -298,6 +298,31 @@ def local_dense(bsr: BSR, loc_atoms: np.ndarray):
     return H, S, idx
 
 
+def apply(bsr: BSR, z: complex, x: np.ndarray, rows: Optional[np.ndarray] = None) -> np.ndarray:
+    """(z S - H) x over the whole system (the operator of the shifted
+    equations in the Introduction), for x of shape [n_orb] or [n_orb, k].
+    With ``rows``, only those orbital rows of the result, each summed
+    directly over its block row."""
+    if rows is None:
+        import scipy.sparse as sp
+        n = 4 * bsr.n_atoms
+        Hm = sp.bsr_matrix((bsr.h, bsr.col, bsr.row_ptr), shape=(n, n))
+        Sx = x if bsr.s is None else sp.bsr_matrix((bsr.s, bsr.col, bsr.row_ptr), shape=(n, n)) @ x
+        return z * Sx - Hm @ x
+    out = []
+    for i in np.asarray(rows):
+        a, o = int(i) // 4, int(i) % 4
+        acc_h = 0.0
+        acc_s = 0.0 if bsr.s is not None else x[i]
+        for t in range(bsr.row_ptr[a], bsr.row_ptr[a + 1]):
+            xb = x[4 * int(bsr.col[t]):4 * int(bsr.col[t]) + 4]
+            acc_h = acc_h + bsr.h[t][o] @ xb
+            if bsr.s is not None:
+                acc_s = acc_s + bsr.s[t][o] @ xb
+        out.append(z * acc_s - acc_h)
+    return np.array(out)
+
+
 def exact_columns(H: np.ndarray, S: np.ndarray, jl: int, z: np.ndarray) -> np.ndarray:
     """x^k = (z_k S - H)^{-1} e_jl for every shift: [n, n_shifts] (dense LU)."""
     n = H.shape[0]

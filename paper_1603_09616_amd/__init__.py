@@ -26,6 +26,7 @@ EXPORTED = (
     "sgf_build_chain", "sgf_to_f32", "sgf_plan_workspace", "sgf_plan_count", "sgf_plan_build", "sgf_proj_layout",
     "sgf_solve_workspace", "sgf_shifted_solve", "sgf_solve_profile", "sgf_features", "sgf_mlp_normalize",
     "sgf_mlp_forward", "sgf_mlp_train_step", "sgf_mlp_gradient", "sgf_order_workspace", "sgf_order_by_prediction",
+    "sgf_bsr_apply",
 )
 MLP_NFEAT, MLP_NPARAM, MLP_BATCH = 5, 4619, 128
 
@@ -86,6 +87,7 @@ def lib():
             "sgf_build_pattern": [i64, P, dbl, P, szt, P, P, P],
             "sgf_build_hamiltonian": [i64, P, P, P, P, szt, P, i64, P, P, P, P],
             "sgf_build_chain": [i64, P, dbl, P, P, P, P],
+            "sgf_bsr_apply": [P, i32, i32, P, P, P, P],
             "sgf_to_f32": [P, i64, P, P],
             "sgf_plan_workspace": [P, i64, i32, P],
             "sgf_plan_count": [P, P, i32, P, szt, P, szt, P, P],
@@ -489,6 +491,26 @@ def solve_workload(wl, system: Optional[System] = None, cols=None, prune=True, *
             rpc = rpc[[pos[int(j)] for j in cols]]
     kw.setdefault("tol", wl.tol)
     return shifted_solve(system, cols, wl.z, wl.w, radius=wl.radius, radius_per_col=rpc, prune=prune, **kw)
+
+
+# --- global operator ------------------------------------------------------------
+
+def bsr_apply(system: System, z, x, precision="fp64", out=None, stream=None):
+    """y = (z S - H) x over the whole system for x of shape [n_orb] or
+    [n_orb, n_rhs] (n_rhs in 1, 2, 4, 8); complex128 (fp64) or complex64
+    (fp32, on the FP32 shadows, built here if missing)."""
+    torch = _torch()
+    prec = {"fp64": 0, "fp32": 1}[precision]
+    if prec == 1 and system.h32 is None:
+        system.add_f32(stream)
+    dt = torch.complex128 if prec == 0 else torch.complex64
+    assert x.dtype == dt and x.is_contiguous() and x.shape[0] == 4 * system.n_atoms
+    n_rhs = 1 if x.dim() == 1 else x.shape[1]
+    y = torch.empty_like(x) if out is None else out
+    zh = np.array([complex(z).real, complex(z).imag], np.float64)
+    sc = system.c()
+    _call("sgf_bsr_apply", ctypes.byref(sc), prec, n_rhs, zh.ctypes.data_as(P), _ptr(x), _ptr(y), _stream(stream))
+    return y
 
 
 # --- learned scheduling ---------------------------------------------------------

@@ -373,3 +373,24 @@ def test_status_codes(oracle_lib):
     bad.h[b.row_ptr[1]] = np.nan  # first block of atom 1 (chain 0)
     r = O.shifted_solve(bad, wl.xyz, cols, wl.z, None, tol=1e-12, radius=0.6, prune=True)
     assert list(r.status) == [O.NONFINITE, O.NONFINITE, O.CONVERGED, O.CONVERGED]
+
+
+@pytest.mark.parametrize("overlap", [False, True])
+def test_apply_inverts_the_dense_solve(oracle_lib, overlap):
+    """The global operator apply, pinned by an independent LAPACK solve: for
+    x = (z S - H)^{-1} e_j from dense LU on the whole (small) system,
+    (z S - H) x returns e_j; the row-by-row form agrees with the full one."""
+    import oracle
+    wl = W.bundle_workload(1, 2, 6, overlap=overlap, n_shifts=4, config_no=31)
+    b = oracle.system_for(wl)
+    atoms = np.arange(b.n_atoms)
+    H, S, idx = oracle.local_dense(b, atoms)
+    z = complex(wl.z[1])
+    for j in (0, 5, 4 * b.n_atoms - 1):
+        x = oracle.exact_columns(H, S, j, np.array([z]))[:, 0]
+        y = oracle.apply(b, z, x)
+        e = np.zeros_like(y)
+        e[j] = 1.0
+        assert np.abs(y - e).max() < 1e-12
+        rows = np.array([j, (j + 3) % x.size])
+        np.testing.assert_allclose(oracle.apply(b, z, x, rows=rows), y[rows], rtol=0, atol=1e-14)
