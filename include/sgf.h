@@ -219,7 +219,9 @@ typedef struct {
     int32_t profile;       /* 1: record HIP events around each pass (read with sgf_solve_profile) */
     int64_t batch_cols;    /* columns per launch (0: all); the solve also stops at what the workspace holds */
     int32_t shifts_per_lane; /* shift pass: 1 or 2 shifts per lane; 0: chosen from the projection size */
-    int32_t reserved;
+    int32_t shifts_staged; /* 1: z and w are already in the workspace (sgf_solve_stage_shifts with the
+                              same arrays), so the solve issues only kernel launches on the stream
+                              (for capture into a HIP graph); the host z is still read for checks */
     double drift_tol;      /* mixed: a column stops with SGF_DRIFT when its FP64 true seed residual
                               b - (z_s - H) x_s departs from the recursive residual by more than
                               drift_tol ||b||_2 (checked every monitor_every iterations and at the end);
@@ -311,6 +313,15 @@ sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *plan, const 
                              const sgf_solve_opts *opts, void *d_ws, size_t ws_bytes, const int64_t *d_proj_off,
                              double *d_G, double *d_rho, int32_t *d_iters, int32_t *d_status, double *d_resid,
                              int32_t *d_shift_iters, void *stream);
+
+/* Copy z (and w, nullable) into the workspace of later sgf_shifted_solve
+ * calls with opts->shifts_staged = 1 and the same n_shifts: they sit at the
+ * start of the workspace, ahead of every per-column slot.  Asynchronous on
+ * the stream (host arrays are read before it returns only if the copy is
+ * synchronous for pageable memory; keep them alive until the stream has
+ * passed it). */
+sgf_status sgf_solve_stage_shifts(int32_t n_shifts, const double *z, const double *w, void *d_ws, size_t ws_bytes,
+                                  void *stream);
 
 /* Kernel times of the last sgf_shifted_solve on this thread that ran with
  * opts->profile = 1 (later unprofiled solves do not replace it), from HIP events recorded on its stream around every

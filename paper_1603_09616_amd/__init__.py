@@ -26,7 +26,7 @@ EXPORTED = (
     "sgf_build_chain", "sgf_to_f32", "sgf_plan_workspace", "sgf_plan_count", "sgf_plan_build", "sgf_proj_layout",
     "sgf_solve_workspace", "sgf_shifted_solve", "sgf_solve_profile", "sgf_features", "sgf_mlp_normalize",
     "sgf_mlp_forward", "sgf_mlp_train_step", "sgf_mlp_gradient", "sgf_order_workspace", "sgf_order_by_prediction",
-    "sgf_bsr_apply",
+    "sgf_bsr_apply", "sgf_solve_stage_shifts",
 )
 MLP_NFEAT, MLP_NPARAM, MLP_BATCH = 5, 4619, 128
 
@@ -65,7 +65,7 @@ class PlanTotalsC(ctypes.Structure):
 class SolveOptsC(ctypes.Structure):
     _fields_ = [("precision", i32), ("tol", dbl), ("max_iter", i32), ("seed_index", i32), ("monitor_every", i32),
                 ("stage_lds", i32), ("grid", i32), ("profile", i32), ("batch_cols", i64),
-                ("shifts_per_lane", i32), ("reserved", i32), ("drift_tol", dbl), ("g_tol", dbl),
+                ("shifts_per_lane", i32), ("shifts_staged", i32), ("drift_tol", dbl), ("g_tol", dbl),
                 ("queue_len", i64)]
 
 
@@ -87,6 +87,7 @@ def lib():
             "sgf_build_pattern": [i64, P, dbl, P, szt, P, P, P],
             "sgf_build_hamiltonian": [i64, P, P, P, P, szt, P, i64, P, P, P, P],
             "sgf_build_chain": [i64, P, dbl, P, P, P, P],
+            "sgf_solve_stage_shifts": [i32, P, P, P, szt, P],
             "sgf_bsr_apply": [P, i32, i32, P, P, P, P],
             "sgf_to_f32": [P, i64, P, P],
             "sgf_plan_workspace": [P, i64, i32, P],
@@ -371,7 +372,7 @@ def _cplx_host(a) -> Optional[np.ndarray]:
 def solve_prepared(prep: Prepared, z, w=None, tol=1e-10, precision="fp64", max_iter=0, seed_index=-1,
                    g_out=True, order=None, batch_cols=0, stage_lds=-1, grid=0, monitor_every=50, out=None,
                    profile=False, shift_iters=False, shifts_per_lane=0, drift_tol=0.0, g_tol=0.0, queue_len=0,
-                   fallback=True, fallback_tol=1e-9, stream=None) -> Result:
+                   fallback=True, fallback_tol=1e-9, shifts_staged=False, stream=None) -> Result:
     """Shifted COCG on every prepared column (asynchronous on the stream).
 
     precision "mixed" builds the FP32 shadow of H first if the system has
@@ -389,7 +390,7 @@ def solve_prepared(prep: Prepared, z, w=None, tol=1e-10, precision="fp64", max_i
         prep.system.add_f32(stream)
     opts = SolveOptsC({"fp64": 0, "mixed": 1}[precision], float(tol), int(max_iter), int(seed_index),
                       int(monitor_every), int(stage_lds), int(grid), int(bool(profile)), int(batch_cols),
-                      int(shifts_per_lane), 0, float(drift_tol), float(g_tol), int(queue_len))
+                      int(shifts_per_lane), int(bool(shifts_staged)), float(drift_tol), float(g_tol), int(queue_len))
     sc = prep.system.c()
     pc = prep.plan.c()
     ws = ctypes.c_size_t()
@@ -453,6 +454,38 @@ def batch_limit(prep: Prepared, n_shifts, budget_bytes, max_iter=0, precision="f
     per = max(w2 - w1, 1)
     fixed = w1 - per
     return int(max(1, min(max(n, 1), (int(budget_bytes) - fixed) // per)))
+
+
+class SolveGraph:
+    """One shifted solve of a prepared column set, captured into a HIP graph
+    (through torch.cuda.CUDAGraph) and replayed on demand.
+
+    The constructor runs the solve once eagerly, which allocates the outputs
+    and the workspace and stages z and w into it; the captured solve then
+    consists of kernel launches only (ticket clear, seed pass, shift pass per
+    batch) and writes the same output buffers on every replay.  Device data
+    the graph reads (H, the plan, the column order) may change in place
+    between replays, e.g. new Hamiltonian values on the same bond pattern.
+    The column order, if any, must be a device tensor."""
+
+    def __init__(self, prep: Prepared, z, w=None, tol=1e-10, order=None, **kw):
+        torch = _torch()
+        if kw.get("precision", "fp64") == "mixed":
+            kw["fallback"] = False   # the FP64 re-solve reads the status array (a synchronisation)
+        if order is not None and not isinstance(order, torch.Tensor):
+            raise TypeError("SolveGraph: order must be a device tensor")
+        kw.pop("profile", None)
+        self.prep, self.z, self.w, self.tol, self.order, self.kw = prep, z, w, tol, order, kw
+        self.result = solve_prepared(prep, z, w, tol, order=order, **kw)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            solve_prepared(prep, z, w, tol, order=order, out=self.result._out, shifts_staged=True, **kw)
+        torch.cuda.synchronize()
+
+    def replay(self) -> Result:
+        self.graph.replay()
+        return self.result
 
 
 def solve_profile():

@@ -1035,8 +1035,10 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
     }
     SolveLayout L = solve_layout(hs, n_shifts, slots, d_ws, ws_bytes);
     hipStream_t st = as_stream(stream);
-    SGF_HIP(hipMemcpyAsync(L.z, z, 16 * (size_t)n_shifts, hipMemcpyHostToDevice, st));
-    if (w) SGF_HIP(hipMemcpyAsync(L.w, w, 16 * (size_t)n_shifts, hipMemcpyHostToDevice, st));
+    if (!opts->shifts_staged) {
+        SGF_HIP(hipMemcpyAsync(L.z, z, 16 * (size_t)n_shifts, hipMemcpyHostToDevice, st));
+        if (w) SGF_HIP(hipMemcpyAsync(L.w, w, 16 * (size_t)n_shifts, hipMemcpyHostToDevice, st));
+    }
 
     SolveArgs a{};
     a.row_ptr = sys->row_ptr;
@@ -1178,6 +1180,24 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
         SGF_LAUNCHED();
         if (timed) SGF_HIP(hipEventRecord(e2, st));
     }
+    return SGF_OK;
+}
+
+extern "C" sgf_status sgf_solve_stage_shifts(int32_t n_shifts, const double *z, const double *w, void *d_ws,
+                                              size_t ws_bytes, void *stream) {
+    SGF_REQUIRE(n_shifts >= 1 && n_shifts <= 512 && z && d_ws, "sgf_solve_stage_shifts: bad arguments");
+    // z and w sit at the start of the workspace, before any per-column slot,
+    // so their place depends on n_shifts only
+    HistoryShape hs{};
+    hs.cap = 1;
+    hs.rmax = 1;
+    hs.ns_pad = (n_shifts + 63) / 64 * 64;
+    const SolveLayout L0 = solve_layout(hs, n_shifts, 0, nullptr, 0);
+    SGF_REQUIRE(L0.bytes <= ws_bytes, "sgf_solve_stage_shifts: workspace too small");
+    const SolveLayout L = solve_layout(hs, n_shifts, 0, d_ws, ws_bytes);
+    hipStream_t st = as_stream(stream);
+    SGF_HIP(hipMemcpyAsync(L.z, z, 16 * (size_t)n_shifts, hipMemcpyHostToDevice, st));
+    if (w) SGF_HIP(hipMemcpyAsync(L.w, w, 16 * (size_t)n_shifts, hipMemcpyHostToDevice, st));
     return SGF_OK;
 }
 
