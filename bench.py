@@ -220,10 +220,18 @@ def main(argv=None):
     s_probe = sgf.build_hamiltonian(d_xyz, wl.tb, device=dev)
     p_probe = sgf.prepare_planned(s_probe, d_cols, d_cp, d_centers, d_radii, prune=True)
     batch = args.batch or sgf.batch_limit(p_probe, ns, int(args.ws_gib * (1 << 30)))
+    # launch choices for this workload shape (timed on a 32,768-column sample)
+    from paper_1603_09616_amd import autotune
+    tuned = autotune.tune(p_probe, wl.z, wl.w, wl.tol, use_cache=False, log=log)
+    launch = tuned["choice"]
+    torch.cuda.empty_cache()
+    log(f"[bench] autotuned launch: {launch}")
     log(f"[bench] workload {wl.name}: {wl.n_atoms} atoms, {wl.columns.size} columns, {ns} shifts, "
         f"batch {batch}")
 
-    def make_step(order_mode, batch_cols, precision="fp64", tol=wl.tol):
+    def make_step(order_mode, batch_cols, precision="fp64", tol=wl.tol, launch_opts=None):
+        lo = dict(launch_opts or {})
+        lo.setdefault("shifts_per_lane", args.shifts_per_lane)
         out_buf = {}
 
         def step(profile):
@@ -235,7 +243,7 @@ def main(argv=None):
                 order = sgf.order_by_prediction(pred, 0.0, float(np.log(4096.0)))
             res = sgf.solve_prepared(prep, wl.z, wl.w, tol=tol, precision=precision, g_out=not args.no_g,
                                      batch_cols=batch_cols, order=order, out=out_buf.get("out"), profile=profile,
-                                     shift_iters=True, shifts_per_lane=args.shifts_per_lane)
+                                     shift_iters=True, **lo)
             out_buf["out"] = res._out
             return s, prep, res
         return step
@@ -272,8 +280,8 @@ def main(argv=None):
         idx = torch.as_tensor(rows, device=dev)
         samples[name] = (res.G[idx].cpu().numpy(), res.rho[idx].cpu().numpy(), res.status.cpu().numpy()[check_cols])
 
-    ms_step, seed_ms, shift_ms, launches, (s, prep, res) = timed(make_step("learned", batch), args.steps,
-                                                                 args.warmup, "fp64 batched+learned")
+    ms_step, seed_ms, shift_ms, launches, (s, prep, res) = timed(make_step("learned", batch, launch_opts=launch),
+                                                                 args.steps, args.warmup, "fp64 batched+learned")
     iters = res.iters.cpu().numpy().astype(np.float64)
     status = res.status.cpu().numpy()
     resid = res.resid.cpu().numpy()
@@ -293,25 +301,25 @@ def main(argv=None):
     achieved = dom_f / (dom_ms * 1e-3) / 1e12
     variants = {"fp64_batched_learned": {"ms_per_step": ms_step, "solves_per_s": value, "seed_ms": seed_ms,
                                          "shift_ms": shift_ms, "launches": launches, "batch_cols": batch,
-                                         "order": "learned", "tol": wl.tol}}
+                                         "order": "learned", "tol": wl.tol, "launch": launch}}
     keep_sample("fp64_batched_learned", prep, res)
     if not args.no_variants:
         rho_ref = res.rho.clone()
         del res, prep, s
         mixed_batch = args.batch or sgf.batch_limit(p_probe, ns, int(args.ws_gib * (1 << 30)), precision="mixed")
-        specs = [("fp64_batched", "natural", batch, "fp64", wl.tol),
-                 ("fp64_plain", "natural", args.plain_batch, "fp64", wl.tol),
-                 ("mixed_batched_learned", "learned", mixed_batch, "mixed", 1e-5),
-                 ("fp64_batched_learned_tol1e-8", "learned", batch, "fp64", 1e-8),
-                 ("fp64_plain_tol1e-8", "natural", args.plain_batch, "fp64", 1e-8)]
-        for name, mode, b, prec, tol in specs:
+        specs = [("fp64_batched", "natural", batch, "fp64", wl.tol, launch),
+                 ("fp64_plain", "natural", args.plain_batch, "fp64", wl.tol, None),
+                 ("mixed_batched_learned", "learned", mixed_batch, "mixed", 1e-5, None),
+                 ("fp64_batched_learned_tol1e-8", "learned", batch, "fp64", 1e-8, launch),
+                 ("fp64_plain_tol1e-8", "natural", args.plain_batch, "fp64", 1e-8, None)]
+        for name, mode, b, prec, tol, lopts in specs:
             torch.cuda.empty_cache()
-            ms_v, sd_v, sh_v, l_v, (_, p_v, r_v) = timed(make_step(mode, b, prec, tol), max(2, args.steps // 2), 1,
-                                                          name)
+            ms_v, sd_v, sh_v, l_v, (_, p_v, r_v) = timed(make_step(mode, b, prec, tol, lopts),
+                                                          max(2, args.steps // 2), 1, name)
             conv_v = int(np.sum(r_v.status.cpu().numpy() == sgf.CONVERGED)) * ns
             variants[name] = {"ms_per_step": ms_v, "solves_per_s": conv_v / (ms_v * 1e-3), "seed_ms": sd_v,
                               "shift_ms": sh_v, "launches": l_v, "batch_cols": b, "order": mode, "tol": tol,
-                              "precision": prec}
+                              "precision": prec, "launch": lopts or "library defaults"}
             if prec == "mixed":
                 variants[name]["fp64_fallback_columns"] = int(getattr(r_v, "n_fallback", 0))
             if tol == wl.tol:
@@ -375,6 +383,7 @@ def main(argv=None):
         },
         "cpu_baseline": cpu,
         "hbm_stream": hbm,
+        "autotune": {"choice": launch, "timings_ms": tuned["timings_ms"], "sample_columns": 32768},
         "variants": variants,
         "scheduler": train_info,
         "converged_solves": converged,
