@@ -159,6 +159,83 @@ def hbm_stream(sgf, W, dev, reps=50):
             "cases": cases, "best": best, "best_frac": cases[best]["frac"]}
 
 
+def extra_workloads(sgf, W, dev, ws_gib, check_n):
+    """The other two workloads, one timed solve each after a warm-up:
+    the overlap bundle (S != I, per-column radius U[0.6, 1.4] nm, 256 shifts,
+    all 473,200 columns) and the 1,000,300-atom share (256 shifts, all
+    4,001,200 columns, density matrix only: G alone would be 328 GB), both
+    FP64 in workspace-sized launches.  Returns the timings and, per workload,
+    the outputs of `check_n` seeded columns for the oracle comparison."""
+    import torch
+    out, keep = {}, {}
+    for name, wl, g_out in (("bundle_overlap_uneven", W.config_bundle_overlap(), True),
+                            ("large_share", W.config_large(), False)):
+        s = sgf.system_for(wl)
+        prep = sgf.prepare(s, wl.columns, radius=wl.radius, radius_per_col=wl.radius_per_col, prune=True)
+        ns = wl.z.size
+        batch = sgf.batch_limit(prep, ns, int(ws_gib * (1 << 30)))
+        buf = None
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = sgf.solve_prepared(prep, wl.z, wl.w, tol=wl.tol, g_out=g_out, batch_cols=batch, out=buf,
+                                     profile=rep == 1)
+            prof = sgf.solve_profile() if rep == 1 else None
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            buf = res._out
+        st = res.status.cpu().numpy()
+        conv = int(np.sum(res.resid.cpu().numpy() <= wl.tol))
+        t = prep.plan.totals
+        out[name] = {"workload": wl.name + (" (S != I, radius per column U[0.6, 1.4] nm)" if wl.tb.overlap else
+                                            " (1,000,300 atoms)"),
+                     "atoms": int(s.n_atoms), "columns": int(wl.columns.size), "shifts": int(ns), "tol": wl.tol,
+                     "outputs": "G and rho" if g_out else "rho only", "ms": ms, "solves_per_s": conv / (ms * 1e-3),
+                     "seed_ms": prof[0], "shift_ms": prof[1], "launches": prof[2], "batch_cols": int(batch),
+                     "columns_not_converged": int(np.sum(st != 0)),
+                     "iters_mean": float(res.iters.float().mean()), "max_loc_atoms": int(t.max_loc_atoms)}
+        log(f"[bench] {name}: {wl.columns.size} columns x {ns} shifts in {ms:.1f} ms "
+            f"({conv / (ms * 1e-3):.3g} solves/s, {prof[2]} launches)")
+        pick = np.sort(np.random.default_rng(1603).choice(wl.columns.size, check_n, replace=False))
+        off = prep.proj_off.cpu().numpy()
+        rows = np.concatenate([np.arange(off[c], off[c + 1]) for c in pick])
+        idx = torch.as_tensor(rows, device=dev)
+        keep[name] = (wl, pick, None if res.G is None else res.G[idx].cpu().numpy(), res.rho[idx].cpu().numpy(),
+                      st[pick])
+        del res, buf, prep, s
+        torch.cuda.empty_cache()
+    return out, keep
+
+
+def check_extra(keep):
+    """Oracle results for the sampled columns of the extra workloads (part of
+    the CPU-baseline leg) and the errors of the GPU outputs against them."""
+    import oracle
+    threads = min(len(os.sched_getaffinity(0)), int(os.environ.get("OMP_NUM_THREADS", 1 << 30)))
+    acc = {}
+    for name, (wl, pick, G, rho, st) in keep.items():
+        b = oracle.system_for(wl)
+        t0 = time.perf_counter()
+        rpc = None if wl.radius_per_col is None else wl.radius_per_col[pick]
+        ref = oracle.shifted_solve(b, wl.xyz, wl.columns[pick], wl.z, wl.w, tol=wl.tol, radius=wl.radius,
+                                   radius_per_col=rpc, prune=True, threads=threads)
+        dt = time.perf_counter() - t0
+        a = {"columns": int(pick.size), "oracle_s": dt, "oracle_threads": threads}
+        e_rho = e_g = 0.0
+        for i in range(pick.size):
+            lo, hi = ref.proj_ptr[i], ref.proj_ptr[i + 1]
+            e_rho = max(e_rho, np.abs(rho[lo:hi] - ref.rho[lo:hi]).max() / max(np.abs(ref.rho[lo:hi]).max(), 1e-300))
+            if G is not None:
+                e_g = max(e_g, np.abs(G[lo:hi] - ref.G[lo:hi]).max() / np.abs(ref.G[lo:hi]).max())
+        a["rho_normwise"] = e_rho
+        if G is not None:
+            a["G_rows_normwise"] = e_g
+        a["not_converged"] = int(np.sum(st != 0))
+        acc[name] = a
+        log(f"[bench] {name}: oracle on {pick.size} columns in {dt:.1f} s; rho err {e_rho:.2e}")
+    return acc
+
+
 def copy_reference(dev, nbytes=1 << 30, reps=10):
     """A plain device copy of known size (for scaling HBM counters)."""
     import torch
@@ -184,6 +261,7 @@ def main(argv=None):
     ap.add_argument("--no-g", action="store_true", help="skip writing G (rho only)")
     ap.add_argument("--shifts-per-lane", type=int, default=0)
     ap.add_argument("--no-hbm", action="store_true", help="skip the HBM-bound operator-apply measurement")
+    ap.add_argument("--no-extra", action="store_true", help="skip the overlap and 1M-atom workloads")
     ap.add_argument("--spmv-only", action="store_true",
                     help="only the operator-apply measurement and a 1 GiB copy (for counter passes)")
     args = ap.parse_args(argv)
@@ -340,9 +418,17 @@ def main(argv=None):
         torch.cuda.empty_cache()
         hbm = hbm_stream(sgf, W, dev)
 
+    extra, extra_keep = None, None
+    if not args.no_extra:
+        torch.cuda.empty_cache()
+        extra, extra_keep = extra_workloads(sgf, W, dev, min(args.ws_gib, 64.0), 1000)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu, ref = cpu_baseline(wl, args.cpu_seconds)
+        if extra:
+            for name, a in check_extra(extra_keep).items():
+                extra[name]["accuracy_vs_oracle"] = a
         for name, (G, rho, st) in samples.items():
             variants.setdefault(name, {})["accuracy_vs_oracle"] = accuracy(wl, check_cols, ref, G, rho, st)
 
@@ -383,6 +469,7 @@ def main(argv=None):
         },
         "cpu_baseline": cpu,
         "hbm_stream": hbm,
+        "other_workloads": extra,
         "autotune": {"choice": launch, "timings_ms": tuned["timings_ms"], "sample_columns": 32768},
         "variants": variants,
         "scheduler": train_info,
