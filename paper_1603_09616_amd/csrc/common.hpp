@@ -142,12 +142,20 @@ __device__ __forceinline__ double dpp_take(double v) {
     const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, false);
     return __hiloint2double(hi, lo);
 }
+// Shift within rows; lanes without a source read zero (bound control), so
+// no destination needs clearing first.
+template <int CTRL>
+__device__ __forceinline__ double dpp_shr(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
 
 __device__ __forceinline__ double wave_reduce(double v) {
-    v += dpp_take<0x111, 0xf>(v);  // row_shr:1
-    v += dpp_take<0x112, 0xf>(v);  // row_shr:2
-    v += dpp_take<0x114, 0xf>(v);  // row_shr:4
-    v += dpp_take<0x118, 0xf>(v);  // row_shr:8
+    v += dpp_shr<0x111>(v);  // row_shr:1
+    v += dpp_shr<0x112>(v);  // row_shr:2
+    v += dpp_shr<0x114>(v);  // row_shr:4
+    v += dpp_shr<0x118>(v);  // row_shr:8
     v += dpp_take<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
     v += dpp_take<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);

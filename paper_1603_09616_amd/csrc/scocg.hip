@@ -353,18 +353,18 @@ __global__ __launch_bounds__(SEED_T) void k_seed_r1(SolveArgs a) {
         const int max_iter = a.max_iter > 0 ? a.max_iter : 10 * nl;
 
         for (int it = 0; it < max_iter; ++it) {
-            // w = z_s p - H p ; mu = p^T w
+            // w = z_s p - H p ; mu = p^T w.  Every lane runs all BMAX blocks:
+            // the absent ones hold zeros and point at column 0, which keeps
+            // the wavefront free of divergent branches.
             double ax = 0.0, ay = 0.0;
 #pragma unroll
             for (int b = 0; b < BMAX; ++b) {
-                if (b < nb) {
-                    const double2 *pb = &vp[bcol[b]];
+                const double2 *pb = &vp[bcol[b]];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const double2 pv = pb[q];
-                        ax = fma(hrow[b][q], pv.x, ax);
-                        ay = fma(hrow[b][q], pv.y, ay);
-                    }
+                for (int q = 0; q < 4; ++q) {
+                    const double2 pv = pb[q];
+                    ax = fma(hrow[b][q], pv.x, ax);
+                    ay = fma(hrow[b][q], pv.y, ay);
                 }
             }
             const double2 w = make_double2(zs.x * p.x - zs.y * p.y - ax, zs.x * p.y + zs.y * p.x - ay);
@@ -402,18 +402,23 @@ __global__ __launch_bounds__(SEED_T) void k_seed_r1(SolveArgs a) {
             int alive = 0;
 #pragma unroll
             for (int m = 0; m < M; ++m) {
-                if (!act[m]) continue;
+                // computed for every shift, kept only for active ones (selects,
+                // not branches: frozen shifts keep pi^k of their last step)
                 const double2 pn = cfma(cfma(alpha, sigma[m], c1), pc[m], cmul(ncoup, po[m]));
-                po[m] = pc[m];
-                pc[m] = pn;
                 const double pn2 = fma(pn.x, pn.x, pn.y * pn.y);
-                if (snorm2 <= tol2 * pn2) {
-                    act[m] = false;
+                const bool on = act[m];
+                const bool done = on && snorm2 <= tol2 * pn2;
+                // select scalar values (a select between array elements would be
+                // lowered to a select of addresses and push pc/po to scratch)
+                const double2 pcm = pc[m], pom = po[m];
+                po[m] = make_double2(on ? pcm.x : pom.x, on ? pcm.y : pom.y);
+                pc[m] = make_double2(on ? pn.x : pcm.x, on ? pn.y : pcm.y);
+                if (done) {
                     nkm[m] = it + 1;
                     res[m] = sqrt(snorm2 / pn2);
-                } else {
-                    alive = 1;
                 }
+                act[m] = on && !done;
+                alive |= act[m] ? 1 : 0;
             }
             applied = it + 1;
             ba_old = ba;
