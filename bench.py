@@ -262,6 +262,8 @@ def main(argv=None):
     ap.add_argument("--shifts-per-lane", type=int, default=0)
     ap.add_argument("--no-hbm", action="store_true", help="skip the HBM-bound operator-apply measurement")
     ap.add_argument("--no-extra", action="store_true", help="skip the overlap and 1M-atom workloads")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="library default launch (for profiler runs, which distort the tuner's timings)")
     ap.add_argument("--spmv-only", action="store_true",
                     help="only the operator-apply measurement and a 1 GiB copy (for counter passes)")
     args = ap.parse_args(argv)
@@ -300,7 +302,10 @@ def main(argv=None):
     batch = args.batch or sgf.batch_limit(p_probe, ns, int(args.ws_gib * (1 << 30)))
     # launch choices for this workload shape (timed on a 32,768-column sample)
     from paper_1603_09616_amd import autotune
-    tuned = autotune.tune(p_probe, wl.z, wl.w, wl.tol, use_cache=False, log=log)
+    if args.no_autotune:
+        tuned = {"choice": {}, "timings_ms": None}
+    else:
+        tuned = autotune.tune(p_probe, wl.z, wl.w, wl.tol, use_cache=False, log=log)
     launch = tuned["choice"]
     torch.cuda.empty_cache()
     log(f"[bench] autotuned launch: {launch}")
