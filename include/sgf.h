@@ -190,14 +190,19 @@ sgf_status sgf_plan_workspace(const sgf_system *sys, int64_t n_plans, int32_t ma
 /* Count local atoms, local blocks and projection atoms per plan and write
  * the offsets atom_off / blk_off / pa_off.  The spatial hash of the build
  * workspace (d_build_ws, from sgf_build_pattern on the same xyz) finds the
- * atoms in the ball.  SYNCHRONOUS (returns totals).  A ball larger than
- * max_loc_atoms returns SGF_EUNSUPPORTED with the offending plan named. */
+ * atoms in the ball.  SYNCHRONOUS (returns totals).  A subspace larger than
+ * max_loc_atoms returns SGF_EUNSUPPORTED with the offending plan named.
+ * The count first runs with a 256-atom LDS capacity and only a batch with a
+ * larger subspace is counted again at max_loc_atoms. */
 sgf_status sgf_plan_count(const sgf_system *sys, sgf_plan *plan, int32_t max_loc_atoms, const void *d_build_ws,
                           size_t build_ws_bytes, void *d_ws, size_t ws_bytes, sgf_plan_totals *totals,
                           void *stream);
 
-/* Fill loc_atom, lrow, lblk, pa_loc and center_loc (after sgf_plan_count with
- * the same arguments). */
+/* Fill loc_atom, lrow, lblk, pa_loc and center_loc, after sgf_plan_count on
+ * the same system, plan and workspaces.  max_loc_atoms sizes the LDS of the
+ * fill and may be anything from the max_loc_atoms total that the count
+ * returned (the cheapest choice) up to the count's own argument.
+ * SYNCHRONOUS: a plan that does not fit returns SGF_EUNSUPPORTED. */
 sgf_status sgf_plan_build(const sgf_system *sys, sgf_plan *plan, int32_t max_loc_atoms, const void *d_build_ws,
                           size_t build_ws_bytes, void *d_ws, size_t ws_bytes, void *stream);
 
@@ -239,6 +244,13 @@ typedef struct {
  * (returns the total row count). */
 sgf_status sgf_proj_layout(const sgf_plan *plan, int64_t n_cols, const int64_t *d_cols, const int32_t *d_col_plan,
                            int64_t *d_proj_off, int32_t *d_proj_row, int64_t *total_rows, void *stream);
+
+/* Projection rows only, from offsets that sgf_proj_layout already wrote:
+ * d_proj_row[d_proj_off[c] + 4 q + o] = 4 * (q-th projection atom of column
+ * c's plan) + o.  d_proj_row holds d_proj_off[n_cols] int32 (caller-owned).
+ * Asynchronous on the stream. */
+sgf_status sgf_proj_rows(const sgf_plan *plan, int64_t n_cols, const int32_t *d_col_plan, const int64_t *d_proj_off,
+                         int32_t *d_proj_row, void *stream);
 
 /* Scratch bytes for sgf_shifted_solve with opts->batch_cols columns per
  * batch (0: every column at once).  Per column the workspace holds the seed

@@ -24,7 +24,7 @@ CONVERGED, MAXITER, BREAKDOWN, NONFINITE, DRIFT, BADCOLUMN = 0, 1, 2, 3, 4, 5
 EXPORTED = (
     "sgf_last_error", "sgf_version", "sgf_build_workspace", "sgf_build_pattern", "sgf_build_hamiltonian",
     "sgf_build_chain", "sgf_to_f32", "sgf_plan_workspace", "sgf_plan_count", "sgf_plan_build", "sgf_proj_layout",
-    "sgf_solve_workspace", "sgf_shifted_solve", "sgf_solve_profile", "sgf_features", "sgf_mlp_normalize",
+    "sgf_proj_rows", "sgf_solve_workspace", "sgf_shifted_solve", "sgf_solve_profile", "sgf_features", "sgf_mlp_normalize",
     "sgf_mlp_forward", "sgf_mlp_train_step", "sgf_mlp_gradient", "sgf_order_workspace", "sgf_order_by_prediction",
     "sgf_bsr_apply", "sgf_solve_stage_shifts",
 )
@@ -94,6 +94,7 @@ def lib():
             "sgf_plan_count": [P, P, i32, P, szt, P, szt, P, P],
             "sgf_plan_build": [P, P, i32, P, szt, P, szt, P],
             "sgf_proj_layout": [P, i64, P, P, P, P, P, P],
+            "sgf_proj_rows": [P, i64, P, P, P, P],
             "sgf_solve_workspace": [P, P, i64, i32, P, P],
             "sgf_shifted_solve": [P, P, P, i64, P, P, P, i32, P, P, P, P, szt, P, P, P, P, P, P, P, P],
             "sgf_solve_profile": [P, P, P],
@@ -281,7 +282,8 @@ def make_plan(system: System, centers, radii, prune: bool = True, max_loc_atoms:
     plan.pa_loc = torch.empty(max(t.n_proj_atoms, 1), dtype=torch.int32, device=dev)
     plan.center_loc = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
     pc = plan.c()
-    _call("sgf_plan_build", ctypes.byref(sc), ctypes.byref(pc), int(max_loc_atoms), _ptr(bws), bws_bytes,
+    # the fill's LDS is sized from the largest counted subspace
+    _call("sgf_plan_build", ctypes.byref(sc), ctypes.byref(pc), max(int(t.max_loc_atoms), 1), _ptr(bws), bws_bytes,
           _ptr(d_ws), ws.value, st)
     return plan
 
@@ -358,8 +360,7 @@ def prepare_planned(system: System, d_cols, d_col_plan, d_centers, d_radii, prun
     _call("sgf_proj_layout", ctypes.byref(pc), n, _ptr(d_cols), _ptr(d_col_plan), _ptr(proj_off), None,
           ctypes.byref(total), _stream(stream))
     proj_row = torch.empty(max(total.value, 1), dtype=torch.int32, device=dev)
-    _call("sgf_proj_layout", ctypes.byref(pc), n, _ptr(d_cols), _ptr(d_col_plan), _ptr(proj_off), _ptr(proj_row),
-          ctypes.byref(total), _stream(stream))
+    _call("sgf_proj_rows", ctypes.byref(pc), n, _ptr(d_col_plan), _ptr(proj_off), _ptr(proj_row), _stream(stream))
     return Prepared(system, plan, d_cols, d_col_plan, proj_off, proj_row[:total.value], total.value)
 
 

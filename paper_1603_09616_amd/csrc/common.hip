@@ -98,14 +98,27 @@ sgf_status inclusive_scan_i64(int64_t *d_data, int64_t n, void *d_scratch, hipSt
     return SGF_OK;
 }
 
-// One workgroup, in place, tile by tile (SCAN_TILE items, SCAN_ITEMS
-// consecutive items per thread) with a running carry.
-__global__ __launch_bounds__(SCAN_T) void k_scan_one_block(int64_t *data, int64_t n) {
-    __shared__ int64_t part[SCAN_T];
-    __shared__ int64_t carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (int64_t start = 0; start < n; start += SCAN_TILE) {
+// One workgroup of 1024 threads, in place, tile by tile (SCAN_ITEMS
+// consecutive items per thread) with a running carry: per tile, a wavefront
+// scan of the thread totals with cross-lane shifts, then one wavefront scans
+// the 16 wavefront totals.  Two barriers per tile.
+constexpr int SCAN1_T = 1024;
+constexpr int SCAN1_TILE = SCAN1_T * SCAN_ITEMS;
+
+__device__ __forceinline__ int64_t wave_scan_i64(int64_t v, int lane) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t u = __shfl_up(v, off, 64);
+        if (lane >= off) v += u;
+    }
+    return v;
+}
+
+__global__ __launch_bounds__(SCAN1_T) void k_scan_one_block(int64_t *data, int64_t n) {
+    __shared__ int64_t wsum[SCAN1_T / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int64_t carry = 0;  // uniform: every thread adds the same tile totals
+    for (int64_t start = 0; start < n; start += SCAN1_TILE) {
         const int64_t base = start + (int64_t)threadIdx.x * SCAN_ITEMS;
         int64_t v[SCAN_ITEMS];
         int64_t run = 0;
@@ -114,27 +127,25 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_one_block(int64_t *data, int64_
             run += (base + i < n) ? data[base + i] : 0;
             v[i] = run;
         }
-        part[threadIdx.x] = run;
+        const int64_t incl = wave_scan_i64(run, lane);
+        if (lane == 63) wsum[wid] = incl;
         __syncthreads();
-        for (int off = 1; off < SCAN_T; off <<= 1) {
-            const int64_t add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
-            __syncthreads();
-            part[threadIdx.x] += add;
-            __syncthreads();
-        }
-        const int64_t prefix = carry + (threadIdx.x > 0 ? part[threadIdx.x - 1] : 0);
+        const int64_t w = lane < SCAN1_T / 64 ? wsum[lane] : 0;
+        const int64_t wincl = wave_scan_i64(w, lane);
+        const int64_t wpre = __shfl(wincl, wid, 64) - __shfl(w, wid, 64);   // waves before this one
+        const int64_t tile = __shfl(wincl, SCAN1_T / 64 - 1, 64);
+        const int64_t prefix = carry + wpre + incl - run;
 #pragma unroll
         for (int i = 0; i < SCAN_ITEMS; ++i)
             if (base + i < n) data[base + i] = v[i] + prefix;
-        __syncthreads();
-        if (threadIdx.x == SCAN_T - 1) carry += part[SCAN_T - 1];
-        __syncthreads();
+        carry += tile;
+        __syncthreads();  // wsum is rewritten by the next tile
     }
 }
 
 sgf_status inclusive_scan_one_block(int64_t *d_data, int64_t n, hipStream_t st) {
     if (n <= 0) return SGF_OK;
-    k_scan_one_block<<<1, SCAN_T, 0, st>>>(d_data, n);
+    k_scan_one_block<<<1, SCAN1_T, 0, st>>>(d_data, n);
     SGF_LAUNCHED();
     return SGF_OK;
 }

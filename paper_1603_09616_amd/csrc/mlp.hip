@@ -283,16 +283,46 @@ __global__ void k_order_zero(int64_t *cnt, int32_t *fill) {
     }
 }
 
-__global__ void k_order_hist(const float *y, int64_t n, float y_lo, float y_hi, int64_t *cnt) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        atomicAdd(reinterpret_cast<unsigned long long *>(&cnt[order_bucket(y[i], y_lo, y_hi) + 1]), 1ull);
+// Counting sort in chunks of ORDER_CHUNK predictions per workgroup.  The
+// predictions crowd into few buckets, so each workgroup counts its chunk in
+// LDS and touches a global counter once per non-empty bucket, not once per
+// column.
+constexpr int ORDER_T = 256;
+constexpr int ORDER_CHUNK = 8192;
+
+__global__ __launch_bounds__(ORDER_T) void k_order_hist(const float *y, int64_t n, float y_lo, float y_hi,
+                                                        int64_t *cnt) {
+    __shared__ uint32_t h[ORDER_BUCKETS];
+    for (int i = threadIdx.x; i < ORDER_BUCKETS; i += ORDER_T) h[i] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * ORDER_CHUNK;
+    const int64_t end = base + ORDER_CHUNK < n ? base + ORDER_CHUNK : n;
+    for (int64_t i = base + threadIdx.x; i < end; i += ORDER_T) atomicAdd(&h[order_bucket(y[i], y_lo, y_hi)], 1u);
+    __syncthreads();
+    for (int i = threadIdx.x; i < ORDER_BUCKETS; i += ORDER_T)
+        if (h[i]) atomicAdd(reinterpret_cast<unsigned long long *>(&cnt[i + 1]), (unsigned long long)h[i]);
 }
 
-__global__ void k_order_scatter(const float *y, int64_t n, float y_lo, float y_hi, const int64_t *start, int32_t *fill,
-                                int32_t *order) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+// Same chunks: each workgroup reserves a run of every non-empty bucket with
+// one global atomic, then places its columns inside its runs.
+__global__ __launch_bounds__(ORDER_T) void k_order_scatter(const float *y, int64_t n, float y_lo, float y_hi,
+                                                           const int64_t *start, int32_t *fill, int32_t *order) {
+    __shared__ uint32_t h[ORDER_BUCKETS];
+    __shared__ int32_t run0[ORDER_BUCKETS];
+    for (int i = threadIdx.x; i < ORDER_BUCKETS; i += ORDER_T) h[i] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * ORDER_CHUNK;
+    const int64_t end = base + ORDER_CHUNK < n ? base + ORDER_CHUNK : n;
+    for (int64_t i = base + threadIdx.x; i < end; i += ORDER_T) atomicAdd(&h[order_bucket(y[i], y_lo, y_hi)], 1u);
+    __syncthreads();
+    for (int i = threadIdx.x; i < ORDER_BUCKETS; i += ORDER_T) {
+        if (h[i]) run0[i] = atomicAdd(&fill[i], (int32_t)h[i]);
+        h[i] = 0;
+    }
+    __syncthreads();
+    for (int64_t i = base + threadIdx.x; i < end; i += ORDER_T) {
         const int b = order_bucket(y[i], y_lo, y_hi);
-        order[start[b] + atomicAdd(&fill[b], 1)] = (int32_t)i;
+        order[start[b] + run0[b] + (int64_t)atomicAdd(&h[b], 1u)] = (int32_t)i;
     }
 }
 
@@ -379,14 +409,13 @@ extern "C" sgf_status sgf_order_by_prediction(const float *d_pred, int64_t n, fl
     int32_t *fill = cv.take<int32_t>(ORDER_BUCKETS);
     char *scan = cv.take<char>(prefix_scratch_bytes(ORDER_BUCKETS));
     hipStream_t st = as_stream(stream);
-    int64_t blocks = (n + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
+    const int64_t blocks = (n + ORDER_CHUNK - 1) / ORDER_CHUNK;
     k_order_zero<<<(ORDER_BUCKETS + 256) / 256, 256, 0, st>>>(cnt, fill);
-    k_order_hist<<<dim3((unsigned)blocks), 256, 0, st>>>(d_pred, n, y_lo, y_hi, cnt);
+    k_order_hist<<<dim3((unsigned)blocks), ORDER_T, 0, st>>>(d_pred, n, y_lo, y_hi, cnt);
     SGF_LAUNCHED();
     sgf_status rc = inclusive_scan_i64(cnt + 1, ORDER_BUCKETS, scan, st);
     if (rc) return rc;
-    k_order_scatter<<<dim3((unsigned)blocks), 256, 0, st>>>(d_pred, n, y_lo, y_hi, cnt, fill, d_order);
+    k_order_scatter<<<dim3((unsigned)blocks), ORDER_T, 0, st>>>(d_pred, n, y_lo, y_hi, cnt, fill, d_order);
     SGF_LAUNCHED();
     return SGF_OK;
 }

@@ -6,6 +6,8 @@
 // wavefront builds one plan in LDS: ball search through the spatial hash,
 // bitonic sort, frontier BFS for the pruning, then the local block-row
 // structure (local column atom + global block index) and the projection atoms.
+#include <algorithm>
+
 #include "build.hpp"
 
 namespace sgf {
@@ -62,6 +64,53 @@ __device__ __forceinline__ int wave_scan_incl(int v) {
     return v;
 }
 
+__device__ __forceinline__ int wave_max_int(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Running maximum shared by all plans: most plans do not raise it, so read it
+// first and take the atomic only when v is larger.  A stale read can only be
+// lower than the true value, which costs an extra atomic and nothing else.
+__device__ __forceinline__ void raise_max(int64_t *m, int64_t v) {
+    if (v > __hip_atomic_load(m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMax(reinterpret_cast<unsigned long long *>(m), (unsigned long long)v);
+}
+
+// Stage the stored-block ranges of atoms rows[e0 .. min(e0 + 64, e1)) for a
+// pair loop: s_r0[k] is the first block of the k-th atom's row, s_ex[k] the
+// number of pairs before it.  Returns the pair count (uniform).  Ends with a
+// barrier, so the staged ranges are visible to every lane.
+__device__ __forceinline__ int stage_rows(const int32_t *row_ptr, const int32_t *rows, int e0, int e1, int32_t *s_r0,
+                                         int32_t *s_ex) {
+    const int lane = threadIdx.x;
+    const int e = e0 + lane;
+    int32_t r0 = 0;
+    int n = 0;
+    if (e < e1) {
+        const int32_t at = rows[e];
+        r0 = row_ptr[at];
+        n = row_ptr[at + 1] - r0;
+    }
+    const int incl = wave_scan_incl(n);
+    s_r0[lane] = r0;
+    s_ex[lane] = incl - n;
+    __syncthreads();
+    return __shfl(incl, 63, 64);
+}
+
+// Row that owns pair q (0 <= q < pair count): the largest k with s_ex[k] <= q.
+// Rows with no pairs share s_ex with the next row, so the largest such k has
+// at least one pair.
+__device__ __forceinline__ int pair_owner(const int32_t *s_ex, int q) {
+    int k = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1)
+        if (s_ex[k + step] <= q) k += step;
+    return k;
+}
+
 struct PlanArgs {
     int64_t n_plans, n_atoms;
     const int32_t *center;
@@ -72,6 +121,7 @@ struct PlanArgs {
     BuildLayout B;  // spatial hash (valid when has_hash)
     int has_hash;
     int maxl;       // LDS capacity in atoms (power of two)
+    int limit;      // most local atoms a plan may hold (<= maxl); more is PLAN_ERR_OVERFLOW
     int64_t *atom_off, *blk_off, *pa_off;
     int32_t *loc_atom, *lrow, *lblk, *pa_loc, *center_loc;
     PlanMeta *meta;
@@ -80,11 +130,11 @@ struct PlanArgs {
 template <bool FILL>
 __global__ __launch_bounds__(PLAN_T) void k_plan(PlanArgs a) {
     extern __shared__ int32_t lds[];
-    int32_t *cand = lds;                 // [maxl]
-    int32_t *visit = lds + a.maxl;       // [maxl]
+    int32_t *cand = lds;                 // [maxl]; with the next maxl ints, the BFS hash set
     int32_t *queue = lds + 2 * a.maxl;   // [maxl]
     int32_t *list = lds + 3 * a.maxl;    // [maxl]
-    __shared__ int s_n, s_tail, s_bad;
+    __shared__ int s_n, s_tail;
+    __shared__ int32_t s_r0[PLAN_T], s_ex[PLAN_T], s_cnt[PLAN_T];
     const int lane = threadIdx.x;
     const int64_t p = blockIdx.x;
     if (p >= a.n_plans) return;
@@ -94,24 +144,25 @@ __global__ __launch_bounds__(PLAN_T) void k_plan(PlanArgs a) {
         if (lane == 0) plan_fail(a.meta, PLAN_ERR_CENTER, p);
         return;
     }
-    if (lane == 0) { s_n = 0; s_bad = 0; }
+    if (lane == 0) s_n = 0;
     __syncthreads();
 
     int nloc;
-    if (a.prune && R > 0.0) {
-        // Connected component of c inside the ball, found by a breadth-first
-        // search along stored blocks that admits only atoms within R of c; the
-        // ball itself is never enumerated.  Visited atoms go to an open-addressing
-        // hash set in LDS (2 * maxl slots, i.e. cand and visit together).
-        if (!a.xyz) {
+    if (a.prune) {
+        // Connected component of c inside the ball (R <= 0: in the whole block
+        // pattern), found by a breadth-first search along stored blocks that
+        // admits only atoms within R of c; the ball itself is never enumerated.
+        // Visited atoms go to an open-addressing hash set in LDS (2 * maxl
+        // slots, i.e. cand and visit together).
+        if (R > 0.0 && !a.xyz) {
             if (lane == 0) plan_fail(a.meta, PLAN_ERR_NOGEOM, p);
             return;
         }
-        int32_t *hset = cand;  // 2 * maxl slots (cand and visit are adjacent)
+        int32_t *hset = cand;  // 2 * maxl slots
         const uint32_t hmask = (uint32_t)(2 * a.maxl - 1);
         for (int i = lane; i < 2 * a.maxl; i += PLAN_T) hset[i] = -1;
         __syncthreads();
-        const double *rc = &a.xyz[3 * (int64_t)c];
+        const double *rc = R > 0.0 ? &a.xyz[3 * (int64_t)c] : nullptr;
         const double R2 = R * R;
         if (lane == 0) {
             hset[((uint32_t)c * 2654435761u) & hmask] = c;
@@ -124,32 +175,39 @@ __global__ __launch_bounds__(PLAN_T) void k_plan(PlanArgs a) {
             const int tail = s_tail;
             __syncthreads();
             if (head == tail || tail > a.maxl) break;
-            for (int e = head + lane; e < tail; e += PLAN_T) {
-                const int32_t at = queue[e];
-                for (int32_t t = a.row_ptr[at]; t < a.row_ptr[at + 1]; ++t) {
-                    const int32_t b = a.col[t];
-                    if (dist2_exact(rc, &a.xyz[3 * (int64_t)b]) > R2) continue;
-                    // Stop inserting once maxl atoms are in: with at most 63 concurrent
-                    // inserts after this check the set holds < maxl + 64 <= 2 * maxl atoms,
-                    // so the probe below always finds an empty slot.
-                    if (atomicAdd(&s_tail, 0) >= a.maxl) break;
+            // One level: the (frontier atom, stored block) pairs are spread over
+            // the lanes, so the row, column and coordinate loads of a level are
+            // issued together rather than one neighbour at a time per lane.
+            for (int e0 = head; e0 < tail; e0 += PLAN_T) {
+                const int total = stage_rows(a.row_ptr, queue, e0, tail, s_r0, s_ex);
+                for (int q = lane; q < total; q += PLAN_T) {
+                    const int k = pair_owner(s_ex, q);
+                    const int32_t b = a.col[s_r0[k] + q - s_ex[k]];
+                    if (rc && dist2_exact(rc, &a.xyz[3 * (int64_t)b]) > R2) continue;
+                    // Once maxl atoms are in, only look b up: a new b means the
+                    // component has more than maxl atoms.  Before that point at most
+                    // 64 inserts race past the check, so the set holds fewer than
+                    // maxl + 64 <= 2 * maxl atoms and every probe meets an empty slot.
+                    const bool full = *reinterpret_cast<volatile int *>(&s_tail) >= a.maxl;
                     uint32_t h = ((uint32_t)b * 2654435761u) & hmask;
                     while (true) {
-                        const int32_t prev = atomicCAS(&hset[h], -1, b);
+                        const int32_t prev = full ? *reinterpret_cast<volatile int32_t *>(&hset[h])
+                                                  : atomicCAS(&hset[h], -1, b);
+                        if (prev == b) break;
                         if (prev == -1) {
                             const int pos = atomicAdd(&s_tail, 1);
                             if (pos < a.maxl) queue[pos] = b;
                             break;
                         }
-                        if (prev == b) break;
                         h = (h + 1) & hmask;
                     }
                 }
+                __syncthreads();
             }
             head = tail;
             __syncthreads();
         }
-        if (s_tail > a.maxl) {
+        if (s_tail > a.limit) {
             if (lane == 0) plan_fail(a.meta, PLAN_ERR_OVERFLOW, p);
             return;
         }
@@ -173,7 +231,7 @@ __global__ __launch_bounds__(PLAN_T) void k_plan(PlanArgs a) {
     } else {
         // 1. Candidates: the ball around c, or every atom.
         if (R <= 0.0) {
-            if (a.n_atoms > a.maxl) {
+            if (a.n_atoms > a.limit) {
                 if (lane == 0) plan_fail(a.meta, PLAN_ERR_OVERFLOW, p);
                 return;
             }
@@ -207,7 +265,7 @@ __global__ __launch_bounds__(PLAN_T) void k_plan(PlanArgs a) {
                 }
             }
             __syncthreads();
-            if (s_n > a.maxl) {
+            if (s_n > a.limit) {
                 if (lane == 0) plan_fail(a.meta, PLAN_ERR_OVERFLOW, p);
                 return;
             }
@@ -231,99 +289,84 @@ __global__ __launch_bounds__(PLAN_T) void k_plan(PlanArgs a) {
         }
         const int ncand = s_n;
 
-        // 2. Optional pruning to the connected component of c (frontier BFS).
-        if (a.prune) {
-            for (int i = lane; i < ncand; i += PLAN_T) visit[i] = 0;
-            __syncthreads();
-            if (lane == 0) {
-                const int ic = bsearch_lds(cand, ncand, c);
-                visit[ic] = 1;
-                queue[0] = ic;
-                s_tail = 1;
-            }
-            __syncthreads();
-            int head = 0;
-            while (true) {
-                const int tail = s_tail;
-                __syncthreads();
-                if (head == tail) break;
-                for (int e = head + lane; e < tail; e += PLAN_T) {
-                    const int32_t at = cand[queue[e]];
-                    for (int32_t t = a.row_ptr[at]; t < a.row_ptr[at + 1]; ++t) {
-                        const int jb = bsearch_lds(cand, ncand, a.col[t]);
-                        if (jb >= 0 && atomicCAS(&visit[jb], 0, 1) == 0) queue[atomicAdd(&s_tail, 1)] = jb;
-                    }
-                }
-                head = tail;
-                __syncthreads();
-            }
-            // ordered compaction of the visited candidates
-            int base = 0;
-            for (int start = 0; start < ncand; start += PLAN_T) {
-                const int i = start + lane;
-                const int f = (i < ncand && visit[i]) ? 1 : 0;
-                const int incl = wave_scan_incl(f);
-                if (f) list[base + incl - 1] = cand[i];
-                base += __shfl(incl, 63, 64);
-            }
-            nloc = base;
-        } else {
-            for (int i = lane; i < ncand; i += PLAN_T) list[i] = cand[i];
-            nloc = ncand;
-        }
+        // every candidate is local (no pruning)
+        for (int i = lane; i < ncand; i += PLAN_T) list[i] = cand[i];
+        nloc = ncand;
     }
     __syncthreads();
 
-    // 3. Local block rows and projection atoms.
+    // 3. Local block rows and projection atoms.  The stored blocks of 64 local
+    // rows at a time are spread over the lanes as (row, block) pairs; a pair
+    // whose column atom is local is a local block, and its place in lblk is the
+    // count of local blocks before it in (row, column position) order.
     const int64_t abase = FILL ? a.atom_off[p] : 0;
     const int64_t bbase = FILL ? a.blk_off[p] : 0;
-    int carry = 0;
+    int carry = 0, rmax = 0;
     for (int start = 0; start < nloc; start += PLAN_T) {
         const int A = start + lane;
-        int cnt = 0;
-        int32_t r0 = 0, r1 = 0;
-        if (A < nloc) {
-            r0 = a.row_ptr[list[A]];
-            r1 = a.row_ptr[list[A] + 1];
-            for (int32_t t = r0; t < r1; ++t) cnt += bsearch_lds(list, nloc, a.col[t]) >= 0;
-        }
-        const int incl = wave_scan_incl(cnt);
-        if (!FILL && cnt > 0)
-            atomicMax(reinterpret_cast<unsigned long long *>(&a.meta->max_row_blocks), (unsigned long long)cnt);
-        if (FILL && A < nloc) {
-            int pos = carry + incl - cnt;
-            a.loc_atom[abase + A] = list[A];
-            a.lrow[abase + A] = pos;
-            for (int32_t t = r0; t < r1; ++t) {
-                const int B = bsearch_lds(list, nloc, a.col[t]);
-                if (B >= 0) {
-                    a.lblk[2 * (bbase + pos)] = B;
-                    a.lblk[2 * (bbase + pos) + 1] = t;
-                    ++pos;
+        const int total = stage_rows(a.row_ptr, list, start, nloc, s_r0, s_ex);
+        s_cnt[lane] = 0;
+        __syncthreads();
+        int run = carry;
+        for (int q0 = 0; q0 < total; q0 += PLAN_T) {
+            const int q = q0 + lane;
+            int k = 0, B = -1;
+            int32_t t = 0;
+            if (q < total) {
+                k = pair_owner(s_ex, q);
+                t = s_r0[k] + q - s_ex[k];
+                B = bsearch_lds(list, nloc, a.col[t]);
+            }
+            const int hit = B >= 0;
+            const int hincl = wave_scan_incl(hit);
+            if (hit) {
+                atomicAdd(&s_cnt[k], 1);
+                if (FILL) {
+                    const int64_t pos = bbase + run + hincl - 1;
+                    a.lblk[2 * pos] = B;
+                    a.lblk[2 * pos + 1] = t;
                 }
             }
+            run += __shfl(hincl, 63, 64);
         }
-        carry += __shfl(incl, 63, 64);
+        __syncthreads();
+        const int cnt = s_cnt[lane];
+        const int cincl = wave_scan_incl(cnt);
+        if (FILL && A < nloc) {
+            a.loc_atom[abase + A] = list[A];
+            a.lrow[abase + A] = carry + cincl - cnt;
+        }
+        rmax = max(rmax, cnt);
+        carry = run;
+        __syncthreads();
     }
     const int nblk = carry;
-    if (lane == 0) {
-        int npa = 0;
-        for (int32_t t = a.row_ptr[c]; t < a.row_ptr[c + 1]; ++t) {
-            const int B = bsearch_lds(list, nloc, a.col[t]);
-            if (B >= 0) {
-                if (FILL) a.pa_loc[a.pa_off[p] + npa] = B;
-                ++npa;
-            }
+    // projection atoms: local column atoms of the centre's stored blocks, in order
+    int npa = 0;
+    {
+        const int32_t c0 = a.row_ptr[c], c1 = a.row_ptr[c + 1];
+        const int64_t pbase = FILL ? a.pa_off[p] : 0;
+        for (int32_t t0 = c0; t0 < c1; t0 += PLAN_T) {
+            const int32_t t = t0 + lane;
+            const int B = t < c1 ? bsearch_lds(list, nloc, a.col[t]) : -1;
+            const int hit = B >= 0;
+            const int hincl = wave_scan_incl(hit);
+            if (FILL && hit) a.pa_loc[pbase + npa + hincl - 1] = B;
+            npa += __shfl(hincl, 63, 64);
         }
+    }
+    if (!FILL) rmax = wave_max_int(rmax);
+    if (lane == 0) {
         if (FILL) {
             a.center_loc[p] = bsearch_lds(list, nloc, c);
         } else {
             a.atom_off[p + 1] = nloc;
             a.blk_off[p + 1] = nblk;
             a.pa_off[p + 1] = npa;
-            atomicMax(reinterpret_cast<unsigned long long *>(&a.meta->max_loc_atoms), (unsigned long long)nloc);
-            atomicMax(reinterpret_cast<unsigned long long *>(&a.meta->max_loc_blocks), (unsigned long long)nblk);
-            atomicMax(reinterpret_cast<unsigned long long *>(&a.meta->max_proj_atoms), (unsigned long long)npa);
+            raise_max(&a.meta->max_loc_atoms, nloc);
+            raise_max(&a.meta->max_loc_blocks, nblk);
+            raise_max(&a.meta->max_proj_atoms, npa);
+            raise_max(&a.meta->max_row_blocks, rmax);
         }
     }
 }
@@ -370,6 +413,7 @@ static sgf_status plan_args(const char *who, const sgf_system *sys, sgf_plan *pl
         SGF_REQUIRE(a.B.bytes <= build_ws_bytes, "%s: build workspace too small", who);
     }
     a.maxl = maxl_pow2(max_loc_atoms);
+    a.limit = max_loc_atoms;
     a.atom_off = plan->atom_off;
     a.blk_off = plan->blk_off;
     a.pa_off = plan->pa_off;
@@ -418,6 +462,23 @@ extern "C" sgf_status sgf_plan_workspace(const sgf_system *sys, int64_t n_plans,
     return SGF_OK;
 }
 
+// First LDS capacity of the count pass, in atoms.  Residency of the one-wave
+// plan workgroups is bounded by LDS (four arrays of maxl ints each), and the
+// pass is bound by the latency of its dependent loads, so a small capacity
+// (4 KiB, the full 32 waves per CU) is tried first; a batch with a larger
+// subspace is counted again at the caller's capacity.
+constexpr int PLAN_FIRST_MAXL = 256;
+
+static sgf_status launch_plan(bool fill, const PlanArgs &a, hipStream_t st) {
+    const size_t lds = 4 * (size_t)a.maxl * sizeof(int32_t);
+    const void *fn = fill ? reinterpret_cast<const void *>(k_plan<true>) : reinterpret_cast<const void *>(k_plan<false>);
+    SGF_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    if (fill) k_plan<true><<<dim3((unsigned)a.n_plans), dim3(PLAN_T), lds, st>>>(a);
+    else k_plan<false><<<dim3((unsigned)a.n_plans), dim3(PLAN_T), lds, st>>>(a);
+    SGF_LAUNCHED();
+    return SGF_OK;
+}
+
 extern "C" sgf_status sgf_plan_count(const sgf_system *sys, sgf_plan *plan, int32_t max_loc_atoms,
                                      const void *d_build_ws, size_t build_ws_bytes, void *d_ws, size_t ws_bytes,
                                      sgf_plan_totals *totals, void *stream) {
@@ -428,26 +489,29 @@ extern "C" sgf_status sgf_plan_count(const sgf_system *sys, sgf_plan *plan, int3
     if (rc) return rc;
     SGF_REQUIRE(totals, "sgf_plan_count: totals is NULL");
     hipStream_t st = as_stream(stream);
-    k_plan_init<<<1, 64, 0, st>>>(L.meta, plan->atom_off, plan->blk_off, plan->pa_off);
-    SGF_LAUNCHED();
-    if (plan->n_plans > 0) {
-        const size_t lds = 4 * (size_t)a.maxl * sizeof(int32_t);
-        SGF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_plan<false>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        k_plan<false><<<dim3((unsigned)plan->n_plans), dim3(PLAN_T), lds, st>>>(a);
-        SGF_LAUNCHED();
-        for (int64_t *off : {plan->atom_off, plan->blk_off, plan->pa_off}) {
-            rc = inclusive_scan_i64(off + 1, plan->n_plans, L.scan, st);
-            if (rc) return rc;
-        }
-    }
+    const int full_maxl = a.maxl;
     PlanMeta m;
     int64_t t3[3] = {0, 0, 0};
-    SGF_HIP(hipMemcpyAsync(&m, L.meta, sizeof(m), hipMemcpyDeviceToHost, st));
-    SGF_HIP(hipMemcpyAsync(&t3[0], plan->atom_off + plan->n_plans, 8, hipMemcpyDeviceToHost, st));
-    SGF_HIP(hipMemcpyAsync(&t3[1], plan->blk_off + plan->n_plans, 8, hipMemcpyDeviceToHost, st));
-    SGF_HIP(hipMemcpyAsync(&t3[2], plan->pa_off + plan->n_plans, 8, hipMemcpyDeviceToHost, st));
-    SGF_HIP(hipStreamSynchronize(st));
+    const int full_limit = a.limit;
+    for (a.maxl = std::min(full_maxl, PLAN_FIRST_MAXL);; a.maxl = full_maxl) {
+        a.limit = std::min(full_limit, a.maxl);
+        k_plan_init<<<1, 64, 0, st>>>(L.meta, plan->atom_off, plan->blk_off, plan->pa_off);
+        SGF_LAUNCHED();
+        if (plan->n_plans > 0) {
+            rc = launch_plan(false, a, st);
+            if (rc) return rc;
+            for (int64_t *off : {plan->atom_off, plan->blk_off, plan->pa_off}) {
+                rc = inclusive_scan_i64(off + 1, plan->n_plans, L.scan, st);
+                if (rc) return rc;
+            }
+        }
+        SGF_HIP(hipMemcpyAsync(&m, L.meta, sizeof(m), hipMemcpyDeviceToHost, st));
+        SGF_HIP(hipMemcpyAsync(&t3[0], plan->atom_off + plan->n_plans, 8, hipMemcpyDeviceToHost, st));
+        SGF_HIP(hipMemcpyAsync(&t3[1], plan->blk_off + plan->n_plans, 8, hipMemcpyDeviceToHost, st));
+        SGF_HIP(hipMemcpyAsync(&t3[2], plan->pa_off + plan->n_plans, 8, hipMemcpyDeviceToHost, st));
+        SGF_HIP(hipStreamSynchronize(st));
+        if (m.err != PLAN_ERR_OVERFLOW || a.maxl == full_maxl) break;
+    }
     if (m.err == PLAN_ERR_OVERFLOW) {
         set_error("sgf_plan_count: plan %lld holds more than max_loc_atoms=%d atoms", (long long)m.err_plan,
                   max_loc_atoms);
@@ -488,11 +552,21 @@ extern "C" sgf_status sgf_plan_build(const sgf_system *sys, sgf_plan *plan, int3
     SGF_REQUIRE(plan->n_plans == 0 || (plan->loc_atom && plan->lrow && plan->lblk && plan->pa_loc && plan->center_loc),
                 "sgf_plan_build: plan output arrays are NULL");
     if (plan->n_plans == 0) return SGF_OK;
-    const size_t lds = 4 * (size_t)a.maxl * sizeof(int32_t);
-    SGF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_plan<true>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds));
-    k_plan<true><<<dim3((unsigned)plan->n_plans), dim3(PLAN_T), lds, as_stream(stream)>>>(a);
+    hipStream_t st = as_stream(stream);
+    k_plan_init<<<1, 64, 0, st>>>(L.meta, plan->atom_off, plan->blk_off, plan->pa_off);
     SGF_LAUNCHED();
+    rc = launch_plan(true, a, st);
+    if (rc) return rc;
+    PlanMeta m;
+    SGF_HIP(hipMemcpyAsync(&m, L.meta, sizeof(m), hipMemcpyDeviceToHost, st));
+    SGF_HIP(hipStreamSynchronize(st));
+    if (m.err == PLAN_ERR_OVERFLOW) {
+        set_error("sgf_plan_build: plan %lld holds more than max_loc_atoms=%d atoms (pass at least the "
+                  "max_loc_atoms total of sgf_plan_count)", (long long)m.err_plan, max_loc_atoms);
+        return SGF_EUNSUPPORTED;
+    }
+    SGF_REQUIRE(m.err == PLAN_ERR_NONE, "sgf_plan_build: plan %lld failed (code %lld) although it was counted",
+                (long long)m.err_plan, (long long)m.err);
     return SGF_OK;
 }
 
@@ -518,5 +592,18 @@ extern "C" sgf_status sgf_proj_layout(const sgf_plan *plan, int64_t n_cols, cons
     }
     SGF_HIP(hipMemcpyAsync(total_rows, d_proj_off + n_cols, 8, hipMemcpyDeviceToHost, st));
     SGF_HIP(hipStreamSynchronize(st));
+    return SGF_OK;
+}
+
+extern "C" sgf_status sgf_proj_rows(const sgf_plan *plan, int64_t n_cols, const int32_t *d_col_plan,
+                                    const int64_t *d_proj_off, int32_t *d_proj_row, void *stream) {
+    SGF_REQUIRE(plan && plan->pa_off && plan->atom_off && plan->loc_atom && plan->pa_loc,
+                "sgf_proj_rows: plan has not been built");
+    SGF_REQUIRE(n_cols >= 0 && (n_cols == 0 || (d_col_plan && d_proj_off && d_proj_row)), "sgf_proj_rows: NULL array");
+    if (n_cols == 0) return SGF_OK;
+    const unsigned g = (unsigned)((n_cols + 255) / 256);
+    k_proj_rows<<<g, 256, 0, as_stream(stream)>>>(n_cols, plan->n_plans, d_col_plan, plan->atom_off, plan->pa_off,
+                                                  plan->loc_atom, plan->pa_loc, d_proj_off, d_proj_row);
+    SGF_LAUNCHED();
     return SGF_OK;
 }

@@ -133,3 +133,18 @@ def test_train_on_logged_solves_and_schedule(sgf):
     np.testing.assert_array_equal(a.G, b.G)
     np.testing.assert_array_equal(a.rho, b.rho)
     np.testing.assert_array_equal(a.iters, b.iters)
+
+
+def test_order_many_chunks_crowded_buckets(sgf):
+    """The counting sort over several 8192-prediction chunks and a ragged
+    tail, with most predictions in a handful of buckets (as a trained
+    scheduler gives) and some outside [y_lo, y_hi] (clamped)."""
+    import torch
+    g = np.random.default_rng(9)
+    n = 3 * 8192 + 517
+    pred = np.where(g.random(n) < 0.8, g.choice([1.0, 1.5, 2.0], n), g.uniform(-0.5, 3.5, n)).astype(np.float32)
+    order = sgf.order_by_prediction(torch.as_tensor(pred, device="cuda"), 0.0, 3.0)
+    o = order.cpu().numpy()
+    assert np.array_equal(np.sort(o), np.arange(n))
+    po = np.clip(pred[o], 0.0, 3.0)
+    assert np.all(np.diff(po) <= 3.0 / 4096 + 1e-6)
