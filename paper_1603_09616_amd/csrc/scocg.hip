@@ -773,12 +773,36 @@ __global__ __launch_bounds__(512) void k_shift(SolveArgs a) {
     for (int hi = top - 1; hi >= 0; hi -= SHIFT_CH) {
         const int lo = hi - SHIFT_CH + 1 > 0 ? hi - SHIFT_CH + 1 : 0;
         const int nstep = hi - lo + 1;
-        __syncthreads();  // the previous chunk has been consumed
-        for (int idx = tid; idx < (nstep + 1) * 2; idx += T) {
-            const int m = lo - 1 + (idx >> 1);
-            sab[idx >> 1][idx & 1] = m >= 0 ? hab[2 * m + (idx & 1)] : zero;
+        // The chunk's loads are all issued before the barrier that ends the
+        // previous chunk's reads, and written to LDS after it: one memory
+        // latency per chunk instead of one per staged element a thread holds.
+        // UR covers the rows at 128 threads and more; a 64-thread workgroup
+        // stages the rest in a plain loop.
+        constexpr int UR = (SHIFT_CH * 4 * NPA + 127) / 128;
+        const int nab = (nstep + 1) * 2, nrv = nstep * nrow;
+        double2 vab = zero;  // (assigned, not selected: a select of two lvalues goes through scratch)
+        if (tid < nab && lo - 1 + (tid >> 1) >= 0) vab = hab[2 * (lo - 1 + (tid >> 1)) + (tid & 1)];
+        double2 vr[UR];
+#pragma unroll
+        for (int u = 0; u < UR; ++u) {
+            const int idx = tid + u * T;
+            vr[u] = zero;
+            if (idx < nrv) {
+                const int sm = idx / nrow, r = idx - sm * nrow;
+                vr[u] = hr[(size_t)(lo + sm) * a.rmax + r];
+            }
         }
-        for (int idx = tid; idx < nstep * nrow; idx += T) {
+        __syncthreads();  // the previous chunk has been consumed
+        if (tid < nab) sab[tid >> 1][tid & 1] = vab;
+#pragma unroll
+        for (int u = 0; u < UR; ++u) {
+            const int idx = tid + u * T;
+            if (idx < nrv) {
+                const int sm = idx / nrow, r = idx - sm * nrow;
+                srow[sm][r] = vr[u];
+            }
+        }
+        for (int idx = tid + UR * T; idx < nrv; idx += T) {
             const int sm = idx / nrow, r = idx - sm * nrow;
             srow[sm][r] = hr[(size_t)(lo + sm) * a.rmax + r];
         }
@@ -812,7 +836,10 @@ __global__ __launch_bounds__(512) void k_shift(SolveArgs a) {
     // G rows and the density matrix rho_i = -(1/pi) sum_k Im(w_k G_i(z_k))
     double2 wk[MS];
 #pragma unroll
-    for (int u = 0; u < MS; ++u) wk[u] = (kof[u] >= 0 && a.w) ? a.w[kof[u]] : zero;
+    for (int u = 0; u < MS; ++u) {
+        wk[u] = zero;
+        if (kof[u] >= 0 && a.w) wk[u] = a.w[kof[u]];
+    }
     const int64_t out0 = a.proj_off[c];
 #pragma unroll
     for (int r = 0; r < 4 * NPA; ++r) {
