@@ -250,6 +250,7 @@ __global__ __launch_bounds__(SEED_T) void k_seed(SolveArgs a) {
 template <int M, int BMAX>
 __global__ __launch_bounds__(SEED_T) void k_seed_r1(SolveArgs a) {
     __shared__ double2 vp[64];
+    __shared__ __align__(16) double red_mu[2 * 64], red_s[3 * 64];  // wavefront sums through LDS (read as double2)
     const int lane = threadIdx.x;
     const double2 zs = a.z[a.seed];
     double2 sigma[M];
@@ -368,8 +369,13 @@ __global__ __launch_bounds__(SEED_T) void k_seed_r1(SolveArgs a) {
                 }
             }
             const double2 w = make_double2(zs.x * p.x - zs.y * p.y - ax, zs.x * p.y + zs.y * p.x - ay);
-            const double2 mu = make_double2(wave_reduce(fma(p.x, w.x, -p.y * w.y)),
-                                            wave_reduce(fma(p.x, w.y, p.y * w.x)));
+            double2 mu;
+            {
+                const double part[2] = {fma(p.x, w.x, -p.y * w.y), fma(p.x, w.y, p.y * w.x)};
+                double sum[2];
+                wave_sum_lds<2>(part, red_mu, sum);
+                mu = make_double2(sum[0], sum[1]);
+            }
             iters = it + 1;
             if (!cfinite(mu)) { status = SGF_NONFINITE; break; }  // rho was checked when it was formed
             if (mu.x == 0.0 && mu.y == 0.0) { status = SGF_BREAKDOWN; break; }
@@ -378,9 +384,14 @@ __global__ __launch_bounds__(SEED_T) void k_seed_r1(SolveArgs a) {
 
             // s -= alpha w ; rho' = s^T s ; ||s||^2
             s = csub(s, cmul(alpha, w));
-            const double2 rho_new = make_double2(wave_reduce(fma(s.x, s.x, -s.y * s.y)),
-                                                 wave_reduce(2.0 * s.x * s.y));
-            snorm2 = wave_reduce(fma(s.x, s.x, s.y * s.y));
+            double2 rho_new;
+            {
+                const double part[3] = {fma(s.x, s.x, -s.y * s.y), 2.0 * s.x * s.y, fma(s.x, s.x, s.y * s.y)};
+                double sum[3];
+                wave_sum_lds<3>(part, red_s, sum);
+                rho_new = make_double2(sum[0], sum[1]);
+                snorm2 = sum[2];
+            }
             const double2 beta = cmul(rho_new, inv_rho);
             const double2 ba = cmul(beta, ia);  // beta_n / alpha_n
             p = cfma(beta, p, s);
@@ -402,17 +413,15 @@ __global__ __launch_bounds__(SEED_T) void k_seed_r1(SolveArgs a) {
             int alive = 0;
 #pragma unroll
             for (int m = 0; m < M; ++m) {
-                // computed for every shift, kept only for active ones (selects,
-                // not branches: frozen shifts keep pi^k of their last step)
+                // Stepped for every shift, frozen or not: a frozen shift's
+                // pi^k is never read again (its step count and residual were
+                // recorded when it froze), so no selects are spent keeping it.
                 const double2 pn = cfma(cfma(alpha, sigma[m], c1), pc[m], cmul(ncoup, po[m]));
                 const double pn2 = fma(pn.x, pn.x, pn.y * pn.y);
                 const bool on = act[m];
                 const bool done = on && snorm2 <= tol2 * pn2;
-                // select scalar values (a select between array elements would be
-                // lowered to a select of addresses and push pc/po to scratch)
-                const double2 pcm = pc[m], pom = po[m];
-                po[m] = make_double2(on ? pcm.x : pom.x, on ? pcm.y : pom.y);
-                pc[m] = make_double2(on ? pn.x : pcm.x, on ? pn.y : pcm.y);
+                po[m] = pc[m];
+                pc[m] = pn;
                 if (done) {
                     nkm[m] = it + 1;
                     res[m] = sqrt(snorm2 / pn2);
