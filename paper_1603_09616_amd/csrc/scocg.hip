@@ -249,6 +249,9 @@ __global__ __launch_bounds__(SEED_T) void k_seed(SolveArgs a) {
 // ---------------------------------------------------------------------------
 template <int M, int BMAX>
 __global__ __launch_bounds__(SEED_T) void k_seed_r1(SolveArgs a) {
+    // p in LDS, orbital-major: vp[16 o + A] is orbital o of local atom A, so
+    // the rows of different atoms read by one block-product instruction fall
+    // on different LDS banks (atom-major storage put them on two)
     __shared__ double2 vp[64];
     __shared__ __align__(16) double red_mu[2 * 64], red_s[3 * 64];  // wavefront sums through LDS (read as double2)
     const int lane = threadIdx.x;
@@ -317,7 +320,7 @@ __global__ __launch_bounds__(SEED_T) void k_seed_r1(SolveArgs a) {
             hrow[b][0] = hrow[b][1] = hrow[b][2] = hrow[b][3] = 0.0;
             if (b < nb) {
                 const int32_t *lb = &a.lblk[2 * (b0 + t0 + b)];
-                bcol[b] = 4 * lb[0];
+                bcol[b] = lb[0];
                 const double *hb = &a.h[16 * (int64_t)lb[1] + 4 * o];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) hrow[b][q] = hb[q];
@@ -332,7 +335,7 @@ __global__ __launch_bounds__(SEED_T) void k_seed_r1(SolveArgs a) {
 
         // start: x = 0, s_0 = p_0 = e_jl
         double2 s = (row && lane == jl) ? one : zero, p = s;
-        vp[lane] = p;
+        vp[16 * o + A] = p;
         if (pidx >= 0) hr[pidx] = s;
         wave_lds_fence();
 
@@ -360,10 +363,9 @@ __global__ __launch_bounds__(SEED_T) void k_seed_r1(SolveArgs a) {
             double ax = 0.0, ay = 0.0;
 #pragma unroll
             for (int b = 0; b < BMAX; ++b) {
-                const double2 *pb = &vp[bcol[b]];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const double2 pv = pb[q];
+                    const double2 pv = vp[16 * q + bcol[b]];
                     ax = fma(hrow[b][q], pv.x, ax);
                     ay = fma(hrow[b][q], pv.y, ay);
                 }
@@ -395,7 +397,7 @@ __global__ __launch_bounds__(SEED_T) void k_seed_r1(SolveArgs a) {
             const double2 beta = cmul(rho_new, inv_rho);
             const double2 ba = cmul(beta, ia);  // beta_n / alpha_n
             p = cfma(beta, p, s);
-            vp[lane] = p;
+            vp[16 * o + A] = p;
 
             // history: 1/alpha_n, beta_n/alpha_n, r_{n+1} on P
             if (lane == 0) {
@@ -715,6 +717,27 @@ __global__ __launch_bounds__(SEED_T) void k_seed_gen(SolveArgs a) {
 // Shift pass
 // ---------------------------------------------------------------------------
 
+// S <- g S + r for two projection rows, in place; the same four fused
+// multiply-adds per row as cfma(g, S, r), so the same bits.  Written as VALU
+// FMAs with S tied to its own registers: compiled from cfma, the new value
+// lands in the register of the loaded row and is copied back afterwards, two
+// 64-bit moves per row and step.  Both temporaries of a row are formed before
+// that row's S is overwritten.
+__device__ __forceinline__ void cfma_rows2(double2 &S0, double2 &S1, double2 r0, double2 r1, double2 g) {
+    double t0x, t0y, t1x, t1y;
+    asm("v_fma_f64 %[t0x], -%[gy], %[s0y], %[r0x]\n\t"
+        "v_fma_f64 %[t0y], %[gy], %[s0x], %[r0y]\n\t"
+        "v_fma_f64 %[t1x], -%[gy], %[s1y], %[r1x]\n\t"
+        "v_fma_f64 %[t1y], %[gy], %[s1x], %[r1y]\n\t"
+        "v_fma_f64 %[s0x], %[gx], %[s0x], %[t0x]\n\t"
+        "v_fma_f64 %[s0y], %[gx], %[s0y], %[t0y]\n\t"
+        "v_fma_f64 %[s1x], %[gx], %[s1x], %[t1x]\n\t"
+        "v_fma_f64 %[s1y], %[gx], %[s1y], %[t1y]"
+        : [s0x] "+v"(S0.x), [s0y] "+v"(S0.y), [s1x] "+v"(S1.x), [s1y] "+v"(S1.y), [t0x] "=&v"(t0x),
+          [t0y] "=&v"(t0y), [t1x] "=&v"(t1x), [t1y] "=&v"(t1y)
+        : [gx] "v"(g.x), [gy] "v"(g.y), [r0x] "v"(r0.x), [r0y] "v"(r0.y), [r1x] "v"(r1.x), [r1y] "v"(r1.y));
+}
+
 // One workgroup per column; each lane carries MS shifts.  The shifts are
 // first sorted by their step count N_k so that the lanes of a wavefront (and
 // the MS shifts of a lane) end their sweeps together.
@@ -817,28 +840,28 @@ __global__ __launch_bounds__(512) void k_shift(SolveArgs a) {
         }
         __syncthreads();
         if (lo >= wtop) continue;  // nothing for this wavefront in this chunk
-        double2 ia_m = sab[hi - lo + 1][0], ba_m = sab[hi - lo + 1][1];
         for (int m = hi; m >= lo; --m) {
+            // 1/alpha and beta/alpha of steps m and m - 1, read from LDS at every
+            // step (carrying the step-m pair over would cost register moves)
+            const double2 ia_m = sab[m - lo + 1][0], ba_m = sab[m - lo + 1][1];
             const double2 ia_p = sab[m - lo][0], ba_p = sab[m - lo][1];
             const double2 *rm = srow[m - lo];
 #pragma unroll
             for (int u = 0; u < MS; ++u) {
                 if (m >= nk[u]) continue;
-                const double2 diag = cadd(cadd(ia_m, ba_p), sigma[u]);
-                const double2 d = (m == nk[u] - 1) ? diag : csub(diag, cmul(ba_m, g[u]));
+                // g is exactly zero up to the shift's first step (m = N_k - 1),
+                // where this is the bare diagonal
+                const double2 d = csub(cadd(cadd(ia_m, ba_p), sigma[u]), cmul(ba_m, g[u]));
 #pragma unroll
                 for (int q = 0; q < NPA; ++q) {
                     if (q < npa) {
-#pragma unroll
-                        for (int o = 0; o < 4; ++o) S[u][4 * q + o] = cfma(g[u], S[u][4 * q + o], rm[4 * q + o]);
+                        cfma_rows2(S[u][4 * q], S[u][4 * q + 1], rm[4 * q], rm[4 * q + 1], g[u]);
+                        cfma_rows2(S[u][4 * q + 2], S[u][4 * q + 3], rm[4 * q + 2], rm[4 * q + 3], g[u]);
                     }
                 }
-                const double2 inv = crcp_fast(d);
-                if (m > 0) g[u] = cmul(ia_p, inv);
-                else y0[u] = inv;
+                y0[u] = crcp_fast(d);  // the last step of every shift is m = 0: y_0 = 1 / d_0
+                g[u] = cmul(ia_p, y0[u]);  // (at m = 0, ia_p is the zero staged for step -1)
             }
-            ia_m = ia_p;
-            ba_m = ba_p;
         }
     }
 
