@@ -742,7 +742,7 @@ __device__ __forceinline__ void cfma_rows2(double2 &S0, double2 &S1, double2 r0,
 // first sorted by their step count N_k so that the lanes of a wavefront (and
 // the MS shifts of a lane) end their sweeps together.
 template <int NPA, int MS>
-__global__ __launch_bounds__(512) void k_shift(SolveArgs a) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MS == 1 && NPA <= 4 ? 4 : (MS == 1 && NPA <= 6 ? 3 : 1)))) void k_shift(SolveArgs a) {
     __shared__ double2 sab[SHIFT_CH + 1][2];       // 1/alpha, beta/alpha of steps lo-1 .. hi
     __shared__ double2 srow[SHIFT_CH][4 * NPA];    // r_m on P for steps lo .. hi
     __shared__ int skey[512];                      // (N_k << 10) | k, sorted ascending
