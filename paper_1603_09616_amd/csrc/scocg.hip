@@ -475,6 +475,10 @@ __global__ __launch_bounds__(SEED_T) void k_seed_r1(SolveArgs a) {
 // pivoting) and applied as a dense product each iteration.  The recorded
 // history holds r on P: the shifted iterates are combinations of the r_n.
 // ---------------------------------------------------------------------------
+// Row stride (doubles) of the dense local overlap inverse: the smallest
+// 32k + 1 >= nl.  Lane i reading row i then starts on bank pair 2i (mod 64).
+__host__ __device__ inline int sinv_ld(int nl) { return 32 * ((nl + 30) / 32) + 1; }
+
 template <int M>
 __global__ __launch_bounds__(SEED_T) void k_seed_gen(SolveArgs a) {
     extern __shared__ double4 lds4[];
@@ -484,7 +488,7 @@ __global__ __launch_bounds__(SEED_T) void k_seed_gen(SolveArgs a) {
     double2 *vw = reinterpret_cast<double2 *>(lds + a.off_w);
     double2 *vq = reinterpret_cast<double2 *>(lds + a.off_q);
     double2 *vr = reinterpret_cast<double2 *>(lds + a.off_r);
-    double *Si = reinterpret_cast<double *>(lds + a.off_sinv);  // [nl][nl]
+    double *Si = reinterpret_cast<double *>(lds + a.off_sinv);  // [nl][ld]
     const int lane = threadIdx.x;
     const double2 zs = a.z[a.seed];
     double2 sigma[M];
@@ -534,6 +538,9 @@ __global__ __launch_bounds__(SEED_T) void k_seed_gen(SolveArgs a) {
             continue;
         }
         const int nl = 4 * n_loc;
+        // row stride of the dense inverse: 32k + 1 doubles, so that the lanes
+        // of a wavefront, each on its own row, read consecutive LDS banks
+        const int ld = sinv_ld(nl);
         const int jl = 4 * cl + (int)(j & 3);
         const int nprow = 4 * npa;
         const int prow = lane < nprow ? 4 * a.pa_loc[p0 + (lane >> 2)] + (lane & 3) : 0;
@@ -541,7 +548,7 @@ __global__ __launch_bounds__(SEED_T) void k_seed_gen(SolveArgs a) {
         double2 *hr = a.hr + (size_t)slot * (a.cap + 1) * a.rmax;
 
         // dense S_L, then its inverse in place
-        for (int e = lane; e < nl * nl; e += SEED_T) Si[e] = 0.0;
+        for (int e = lane; e < nl * ld; e += SEED_T) Si[e] = 0.0;
         wave_lds_fence();
         for (int A = lane; A < n_loc; A += SEED_T) {
             const int t0 = a.lrow[a0 + A], t1 = A + 1 < n_loc ? a.lrow[a0 + A + 1] : nblk;
@@ -549,20 +556,20 @@ __global__ __launch_bounds__(SEED_T) void k_seed_gen(SolveArgs a) {
                 const int B = a.lblk[2 * (b0 + t)];
                 const double *sb = &a.s[16 * (int64_t)a.lblk[2 * (b0 + t) + 1]];
                 for (int o = 0; o < 4; ++o)
-                    for (int q = 0; q < 4; ++q) Si[(4 * A + o) * nl + 4 * B + q] = sb[4 * o + q];
+                    for (int q = 0; q < 4; ++q) Si[(4 * A + o) * ld + 4 * B + q] = sb[4 * o + q];
             }
         }
         wave_lds_fence();
         for (int kk = 0; kk < nl; ++kk) {
-            const double piv = 1.0 / Si[kk * nl + kk];
+            const double piv = 1.0 / Si[kk * ld + kk];
             wave_lds_fence();
-            for (int jj = lane; jj < nl; jj += SEED_T) Si[kk * nl + jj] = (jj == kk) ? piv : Si[kk * nl + jj] * piv;
+            for (int jj = lane; jj < nl; jj += SEED_T) Si[kk * ld + jj] = (jj == kk) ? piv : Si[kk * ld + jj] * piv;
             wave_lds_fence();
             for (int i = lane; i < nl; i += SEED_T) {
                 if (i == kk) continue;
-                const double f = Si[i * nl + kk];
+                const double f = Si[i * ld + kk];
                 for (int jj = 0; jj < nl; ++jj)
-                    Si[i * nl + jj] = (jj == kk) ? -f * Si[kk * nl + jj] : fma(-f, Si[kk * nl + jj], Si[i * nl + jj]);
+                    Si[i * ld + jj] = (jj == kk) ? -f * Si[kk * ld + jj] : fma(-f, Si[kk * ld + jj], Si[i * ld + jj]);
             }
             wave_lds_fence();
         }
@@ -570,7 +577,7 @@ __global__ __launch_bounds__(SEED_T) void k_seed_gen(SolveArgs a) {
         // start: s_0 = q_0 = e_jl, r_0 = p_0 = S^{-1} e_jl, rho_0 = r_0^T s_0
         for (int i = lane; i < nl; i += SEED_T) {
             const double2 sv = make_double2(i == jl ? 1.0 : 0.0, 0.0);
-            const double2 rv = make_double2(Si[i * nl + jl], 0.0);
+            const double2 rv = make_double2(Si[i * ld + jl], 0.0);
             vs[i] = sv;
             vq[i] = sv;
             vr[i] = rv;
@@ -590,7 +597,7 @@ __global__ __launch_bounds__(SEED_T) void k_seed_gen(SolveArgs a) {
             nkm[m] = 0;
             res[m] = 1.0;
         }
-        double2 rho = make_double2(Si[jl * nl + jl], 0.0);
+        double2 rho = make_double2(Si[jl * ld + jl], 0.0);
         double2 alpha_old = make_double2(1.0, 0.0), beta_old = zero;
         int status = SGF_MAXITER, iters = 0, applied = 0;
         double snorm2 = 1.0;
@@ -638,7 +645,7 @@ __global__ __launch_bounds__(SEED_T) void k_seed_gen(SolveArgs a) {
             double r0 = 0.0, r1 = 0.0;
             for (int i = lane; i < nl; i += SEED_T) {
                 double rx = 0.0, ry = 0.0;
-                const double *srow = &Si[i * nl];
+                const double *srow = &Si[i * ld];
                 for (int jj = 0; jj < nl; ++jj) {
                     const double2 sj = vs[jj];
                     rx = fma(srow[jj], sj.x, rx);
@@ -1188,7 +1195,7 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
         a.off_w = gtake((size_t)nl * 16);
         a.off_q = gtake((size_t)nl * 16);
         a.off_r = gtake((size_t)nl * 16);
-        a.off_sinv = gtake((size_t)nl * nl * 8);
+        a.off_sinv = gtake((size_t)nl * sinv_ld(nl) * 8);
         seed_lds = goff;
         if (seed_lds > 160 * 1024) {
             set_error("sgf_shifted_solve: S != I with a local subspace of %d orbitals needs %zu bytes of LDS "
