@@ -413,6 +413,52 @@ sgf_status sgf_order_workspace(size_t *ws_bytes);
 sgf_status sgf_order_by_prediction(const float *d_pred, int64_t n, float y_lo, float y_hi, int32_t *d_order,
                                    void *d_ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------------------------ */
+/* After rho: traces, electron count, band energy, Fermi level               */
+/* ------------------------------------------------------------------------ */
+
+/* Row j of the restricted equations (z S_L - H_L) x = e_j couples j only to
+ * orbitals sharing a stored block with it, which are the projection rows
+ * P(j); so the projected G gives the per-shift traces over the solved
+ * columns
+ *     T_k = sum_j sum_{i in P(j)} S_ji G_ij(z_k)    (= sum_j (G S)_jj)
+ *     U_k = sum_j sum_{i in P(j)} H_ji G_ij(z_k)    (= sum_j (G H)_jj)
+ * from which, for quadrature weights w of the occupied spectrum, the
+ * electron count tr(rho S) = -(1/pi) sum_k Im(w_k T_k) and the band energy
+ * tr(rho H) = -(1/pi) sum_k Im(w_k U_k) follow (the order-N energy of the
+ * Introduction: the quantities formed from rho after the shifted solves).
+ *
+ * Scratch bytes for sgf_traces over total_rows projection rows. */
+sgf_status sgf_trace_workspace(int64_t total_rows, int32_t n_shifts, size_t *ws_bytes);
+
+/* Traces of one solve's outputs (device arrays as sgf_shifted_solve wrote
+ * them): d_cols[n_cols], d_proj_off[n_cols+1], d_proj_row[total_rows],
+ * d_status[n_cols] (nullable: with it, only SGF_CONVERGED columns count;
+ * a column the solve rejected holds no G or rho), d_G complex
+ * [total_rows][n_shifts] (nullable), d_rho [total_rows] (nullable; one of
+ * the two is required).  Writes d_T and d_U (complex [n_shifts], needed
+ * with d_G) and d_rho_tr (double[2]: tr(rho S), tr(rho H) at the solve's
+ * own weights, needed with d_rho).  Sums in a fixed order (bitwise
+ * repeatable).  Asynchronous on the stream. */
+sgf_status sgf_traces(const sgf_system *sys, int64_t n_cols, const int64_t *d_cols, const int64_t *d_proj_off,
+                      const int32_t *d_proj_row, const int32_t *d_status, int64_t total_rows, const double *d_G,
+                      const double *d_rho, int32_t n_shifts, void *d_ws, size_t ws_bytes, double *d_T, double *d_U,
+                      double *d_rho_tr, void *stream);
+
+/* Host arrays (complex interleaved): electron count and band energy
+ * -(1/pi) sum_k Im(w_k T_k), -(1/pi) sum_k Im(w_k U_k) for any weights w. */
+sgf_status sgf_occupation(int32_t n_shifts, const double *T, const double *U, const double *w, double *n_e,
+                          double *e_band);
+
+/* Host: the Fermi level on a real-axis grid z_k = E_k + i eta (E_k
+ * increasing).  With trapezoid weights (the spacing, halved at the two grid
+ * ends) on E_k <= mu, the electron count N_e(mu) changes only at grid
+ * points; bisection on the grid index returns the first E_m with
+ * N_e(E_m) >= n_target as mu, with N_e and the band energy there.  A target
+ * above the count of the whole grid returns SGF_EUNSUPPORTED. */
+sgf_status sgf_fermi_level(int32_t n_shifts, const double *z, const double *T, const double *U, double n_target,
+                           double *mu, double *n_e, double *e_band);
+
 #ifdef __cplusplus
 }
 #endif

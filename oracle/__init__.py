@@ -329,3 +329,79 @@ def exact_columns(H: np.ndarray, S: np.ndarray, jl: int, z: np.ndarray) -> np.nd
     e = np.zeros(n, np.complex128)
     e[jl] = 1.0
     return np.stack([np.linalg.solve(zk * S - H, e) for zk in z], axis=1)
+
+
+# ---------------------------------------------------------------------------
+# After rho: traces, electron count, band energy, Fermi level.
+# ---------------------------------------------------------------------------
+
+def _block_entry(bsr: BSR, m: np.ndarray, i: int, j: int) -> float:
+    """Entry (i, j) of the block matrix with blocks m (bsr.h or bsr.s)."""
+    a, b = i // 4, j // 4
+    for t in range(int(bsr.row_ptr[a]), int(bsr.row_ptr[a + 1])):
+        if int(bsr.col[t]) == b:
+            return float(m[t, i % 4, j % 4])
+    return 0.0
+
+
+def traces(bsr: BSR, res: Result, cols):
+    """Per-shift traces over the solved columns from the projected G.
+
+    Row j of the restricted equations (z S_L - H_L) x = e_j involves only the
+    orbitals that share a stored block with j, i.e. the projection rows P(j),
+    so  T_k = sum_j sum_{i in P(j)} S_ji G_ij(z_k)  and
+        U_k = sum_j sum_{i in P(j)} H_ji G_ij(z_k).
+    Returns (T, U), complex128 [n_shifts]."""
+    cols = np.asarray(cols, np.int64)
+    ns = res.G.shape[1]
+    T = np.zeros(ns, np.complex128)
+    U = np.zeros(ns, np.complex128)
+    for c, j in enumerate(cols):
+        rows, G, _ = res.column(c)
+        for r, i in enumerate(rows):
+            sji = (1.0 if int(i) == int(j) else 0.0) if bsr.s is None else _block_entry(bsr, bsr.s, int(j), int(i))
+            hji = _block_entry(bsr, bsr.h, int(j), int(i))
+            T += sji * G[r]
+            U += hji * G[r]
+    return T, U
+
+
+def rho_traces(bsr: BSR, res: Result, cols):
+    """(tr(rho S), tr(rho H)) over the solved columns from the projected rho."""
+    cols = np.asarray(cols, np.int64)
+    ts = th = 0.0
+    for c, j in enumerate(cols):
+        rows, _, rho = res.column(c)
+        for r, i in enumerate(rows):
+            sji = (1.0 if int(i) == int(j) else 0.0) if bsr.s is None else _block_entry(bsr, bsr.s, int(j), int(i))
+            ts += sji * rho[r]
+            th += _block_entry(bsr, bsr.h, int(j), int(i)) * rho[r]
+    return ts, th
+
+
+def occupation(T, U, w):
+    """Electron count and band energy for weights w:
+    -(1/pi) sum_k Im(w_k T_k), -(1/pi) sum_k Im(w_k U_k)."""
+    T, U, w = (np.asarray(a, np.complex128) for a in (T, U, w))
+    return float(-np.sum((w * T).imag) / np.pi), float(-np.sum((w * U).imag) / np.pi)
+
+
+def fermi_level(z, T, U, n_target):
+    """Scan of the real-axis grid: the first E_m at which the electron count
+    with trapezoid weights (the spacing, halved at the two grid ends) on
+    E_k <= E_m reaches n_target.  Returns (mu, n_e, e_band); raises when the
+    whole grid holds fewer electrons."""
+    e = np.real(np.asarray(z, np.complex128))
+    n = e.size
+    w = np.full(n, (e[-1] - e[0]) / (n - 1) if n > 1 else 1.0)
+    if n > 1:
+        w[0] *= 0.5
+        w[-1] *= 0.5
+    T, U = np.asarray(T, np.complex128), np.asarray(U, np.complex128)
+    ne = eb = 0.0
+    for m in range(n):
+        ne += -w[m] * T[m].imag / np.pi
+        eb += -w[m] * U[m].imag / np.pi
+        if ne >= n_target:
+            return float(e[m]), float(ne), float(eb)
+    raise ValueError("target exceeds the occupation of the whole grid")

@@ -26,7 +26,8 @@ EXPORTED = (
     "sgf_build_chain", "sgf_to_f32", "sgf_plan_workspace", "sgf_plan_count", "sgf_plan_build", "sgf_proj_layout",
     "sgf_proj_rows", "sgf_solve_workspace", "sgf_shifted_solve", "sgf_solve_profile", "sgf_features", "sgf_mlp_normalize",
     "sgf_mlp_forward", "sgf_mlp_train_step", "sgf_mlp_gradient", "sgf_order_workspace", "sgf_order_by_prediction",
-    "sgf_bsr_apply", "sgf_solve_stage_shifts",
+    "sgf_bsr_apply", "sgf_solve_stage_shifts", "sgf_trace_workspace", "sgf_traces", "sgf_occupation",
+    "sgf_fermi_level",
 )
 MLP_NFEAT, MLP_NPARAM, MLP_BATCH = 5, 4619, 128
 
@@ -105,6 +106,10 @@ def lib():
             "sgf_mlp_gradient": [P, P, P, i32, P, P, P],
             "sgf_order_workspace": [P],
             "sgf_order_by_prediction": [P, i64, ctypes.c_float, ctypes.c_float, P, P, szt, P],
+            "sgf_trace_workspace": [i64, i32, P],
+            "sgf_traces": [P, i64, P, P, P, P, i64, P, P, i32, P, szt, P, P, P, P],
+            "sgf_occupation": [i32, P, P, P, P, P],
+            "sgf_fermi_level": [i32, P, P, P, dbl, P, P, P],
         }
         for name, args in sigs.items():
             f = getattr(L, name)
@@ -545,6 +550,54 @@ def bsr_apply(system: System, z, x, precision="fp64", out=None, stream=None):
     sc = system.c()
     _call("sgf_bsr_apply", ctypes.byref(sc), prec, n_rhs, zh.ctypes.data_as(P), _ptr(x), _ptr(y), _stream(stream))
     return y
+
+
+# --- after rho: traces, electron count, band energy, Fermi level ----------------
+
+def traces(prep: Prepared, res: Result, converged_only=True, stream=None):
+    """Per-shift traces over the solved columns from a solve's outputs:
+    T_k = sum_j (G S)_jj and U_k = sum_j (G H)_jj (complex128 [n_shifts],
+    None when the solve kept no G), and (tr(rho S), tr(rho H)) at the solve's
+    own weights; with ``converged_only`` a column that did not converge
+    contributes nothing.  Synchronises the stream."""
+    torch = _torch()
+    dev = prep.cols.device
+    n = prep.cols.numel()
+    rows = int(prep.n_rows)
+    ns = 1 if res.G is None else int(res.G.shape[1])
+    ws = ctypes.c_size_t()
+    _call("sgf_trace_workspace", rows, ns, ctypes.byref(ws))
+    d_ws = _bytes(ws.value, dev)
+    T = torch.empty(ns, dtype=torch.complex128, device=dev) if res.G is not None else None
+    U = torch.empty(ns, dtype=torch.complex128, device=dev) if res.G is not None else None
+    rtr = torch.empty(2, dtype=torch.float64, device=dev)
+    sc = prep.system.c()
+    status = res.status if converged_only else None
+    _call("sgf_traces", ctypes.byref(sc), n, _ptr(prep.cols), _ptr(prep.proj_off), _ptr(prep.proj_row), _ptr(status),
+          rows, _ptr(res.G), _ptr(res.rho), ns, _ptr(d_ws), ws.value, _ptr(T), _ptr(U), _ptr(rtr), _stream(stream))
+    out_t = None if T is None else T.cpu().numpy()
+    out_u = None if U is None else U.cpu().numpy()
+    r = rtr.cpu().numpy()
+    return out_t, out_u, (float(r[0]), float(r[1]))
+
+
+def occupation(T, U, w):
+    """(electron count, band energy) = -(1/pi) sum_k Im(w_k T_k), -(1/pi) sum_k Im(w_k U_k)."""
+    t, u, wv = (np.ascontiguousarray(np.asarray(a, np.complex128)) for a in (T, U, w))
+    ne, eb = ctypes.c_double(), ctypes.c_double()
+    _call("sgf_occupation", t.size, t.ctypes.data_as(P), u.ctypes.data_as(P), wv.ctypes.data_as(P),
+          ctypes.byref(ne), ctypes.byref(eb))
+    return ne.value, eb.value
+
+
+def fermi_level(z, T, U, n_target):
+    """(mu, electron count, band energy): the first grid energy at which the
+    trapezoid-weighted electron count reaches n_target."""
+    zz, t, u = (np.ascontiguousarray(np.asarray(a, np.complex128)) for a in (z, T, U))
+    mu, ne, eb = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _call("sgf_fermi_level", zz.size, zz.ctypes.data_as(P), t.ctypes.data_as(P), u.ctypes.data_as(P),
+          float(n_target), ctypes.byref(mu), ctypes.byref(ne), ctypes.byref(eb))
+    return mu.value, ne.value, eb.value
 
 
 # --- learned scheduling ---------------------------------------------------------
