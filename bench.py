@@ -247,6 +247,36 @@ def copy_reference(dev, nbytes=1 << 30, reps=10):
     return {"bytes_read": nbytes, "bytes_written": nbytes, "launches": reps}
 
 
+def after_rho(sgf, prep, res, wl, reps=5):
+    """The step after rho on the timed step's outputs: the traces of the
+    projected G (an HBM-bound pass that streams all of G once), then the
+    half-filling Fermi level, electron count and band energy from them, and
+    the row identity z_k T_k - U_k = n_cols as a check."""
+    import torch
+    n_rows, ns = int(prep.n_rows), int(res.G.shape[1])
+    ms = []
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        T, U, (ts, th) = sgf.traces(prep, res)
+        e1.record()
+        torch.cuda.synchronize()
+        if r:
+            ms.append(e0.elapsed_time(e1))
+    n = int(prep.cols.numel())
+    g_bytes = n_rows * ns * 16
+    # G once; per row the coefficient written and read back (16 + 16 B) and its proj_row entry
+    alg = g_bytes + n_rows * (16 + 16 + 4) + n * (8 + 8 + 4)
+    t = float(np.median(ms))
+    mu, ne, eb = sgf.fermi_level(wl.z, T, U, 0.5 * n)
+    return {"what": "T_k = sum_j (G S)_jj, U_k = sum_j (G H)_jj over all columns, then the half-filling Fermi level",
+            "ms": t, "G_bytes": g_bytes, "alg_bytes": alg, "GBps": alg / (t * 1e-3) / 1e9,
+            "frac_of_8TBps": alg / (t * 1e-3) / 8e12, "reps": reps,
+            "identity_gap_max": float(np.abs(wl.z * T - U - n).max()), "identity_bound": 10 * wl.tol * n,
+            "mu_half_filling_eV": mu, "n_e": ne, "e_band_eV": eb, "tr_rho_S": ts, "tr_rho_H_eV": th}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -386,6 +416,11 @@ def main(argv=None):
                                          "shift_ms": shift_ms, "launches": launches, "batch_cols": batch,
                                          "order": "learned", "tol": wl.tol, "launch": launch}}
     keep_sample("fp64_batched_learned", prep, res)
+    post = None
+    if res.G is not None:
+        post = after_rho(sgf, prep, res, wl)
+        log(f"[bench] after rho: traces in {post['ms']:.2f} ms ({post['GBps']:.0f} GB/s), "
+            f"mu(half filling) = {post['mu_half_filling_eV']:.4f} eV")
     if not args.no_variants:
         rho_ref = res.rho.clone()
         del res, prep, s
@@ -474,6 +509,7 @@ def main(argv=None):
         },
         "cpu_baseline": cpu,
         "hbm_stream": hbm,
+        "after_rho": post,
         "other_workloads": extra,
         "autotune": {"choice": launch, "timings_ms": tuned["timings_ms"], "sample_columns": 32768},
         "variants": variants,

@@ -20,23 +20,27 @@ namespace sgf {
 constexpr int TR_NB = 1024;   // workgroups of the partial-sum passes
 constexpr int TR_UNROLL = 8;  // projection rows in flight per thread
 constexpr int TR_RHO_T = 256;
+constexpr int TR_RED_T = 256;  // threads of the final reductions
+constexpr int TR_COEF_L = 16; // lanes per column in the coefficient pass
 constexpr double INV_PI_D = 0.318309886183790671537767526745;
 
-// S_ji and H_ji of every projection row (one thread per column).  A row
-// whose atom shares no stored block with the column's atom gets zeros (it
-// cannot occur for rows built by sgf_proj_layout), and so do all rows of a
-// column that is left out.
+// S_ji and H_ji of every projection row (TR_COEF_L lanes per column, each
+// taking every TR_COEF_L-th row of it).  A row whose atom shares no stored
+// block with the column's atom gets zeros (it cannot occur for rows built by
+// sgf_proj_layout), and so do all rows of a column that is left out.
 __global__ void k_trace_coef(int64_t n_cols, int64_t n_orb, const int64_t *cols, const int64_t *proj_off,
                              const int32_t *proj_row, const int32_t *status, const int32_t *row_ptr,
                              const int32_t *col, const double *h, const double *s, double2 *coef) {
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_cols; c += (int64_t)gridDim.x * blockDim.x) {
+    const int lane = (int)(threadIdx.x % TR_COEF_L);
+    const int64_t step = (int64_t)gridDim.x * (blockDim.x / TR_COEF_L);
+    for (int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / TR_COEF_L; c < n_cols; c += step) {
         const int64_t j = cols[c];
         // a column left out (status given and not converged) contributes zeros
         const bool ok = j >= 0 && j < n_orb && (!status || status[c] == SGF_CONVERGED);
         const int32_t a = ok ? (int32_t)(j >> 2) : 0;
         const int o = (int)(j & 3);
         const int32_t t0 = ok ? row_ptr[a] : 0, t1 = ok ? row_ptr[a + 1] : 0;
-        for (int64_t r = proj_off[c]; r < proj_off[c + 1]; ++r) {
+        for (int64_t r = proj_off[c] + lane; r < proj_off[c + 1]; r += TR_COEF_L) {
             const int32_t i = proj_row[r];
             const int32_t b = i >> 2;
             const int q = i & 3;
@@ -89,17 +93,39 @@ __global__ void k_trace_partial(int64_t n_rows, int32_t ns, const double2 *G, co
     }
 }
 
-// T_k and U_k: the workgroups' partials added in workgroup order.
-__global__ void k_trace_final(int32_t ns, int nb, const double2 *part, double2 *T, double2 *U) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= ns) return;
+// Fixed-shape sum of the block's (t, u) pairs: strided per thread, then an
+// LDS tree, so the result does not depend on timing.
+__device__ inline void tree_sum2(double2 &t, double2 &u, double2 (*red)[2]) {
+    red[threadIdx.x][0] = t;
+    red[threadIdx.x][1] = u;
+    __syncthreads();
+    for (int off = TR_RED_T / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            red[threadIdx.x][0] = cadd(red[threadIdx.x][0], red[threadIdx.x + off][0]);
+            red[threadIdx.x][1] = cadd(red[threadIdx.x][1], red[threadIdx.x + off][1]);
+        }
+        __syncthreads();
+    }
+    t = red[0][0];
+    u = red[0][1];
+}
+
+// T_k and U_k: one workgroup per shift adds the partials of all workgroups
+// of the partial pass.
+__global__ __launch_bounds__(TR_RED_T) void k_trace_final(int32_t ns, int nb, const double2 *part, double2 *T,
+                                                          double2 *U) {
+    __shared__ double2 red[TR_RED_T][2];
+    const int k = blockIdx.x;
     double2 t = make_double2(0.0, 0.0), u = make_double2(0.0, 0.0);
-    for (int b = 0; b < nb; ++b) {
+    for (int b = threadIdx.x; b < nb; b += TR_RED_T) {
         t = cadd(t, part[((size_t)b * ns + k) * 2]);
         u = cadd(u, part[((size_t)b * ns + k) * 2 + 1]);
     }
-    T[k] = t;
-    U[k] = u;
+    tree_sum2(t, u, red);
+    if (threadIdx.x == 0) {
+        T[k] = t;
+        U[k] = u;
+    }
 }
 
 // tr(rho S) and tr(rho H) over the projection rows: per-workgroup sums
@@ -125,12 +151,15 @@ __global__ __launch_bounds__(TR_RHO_T) void k_trace_rho_partial(int64_t n_rows, 
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-__global__ void k_trace_rho_final(int nb, const double2 *part, double *out) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    double2 t = make_double2(0.0, 0.0);
-    for (int b = 0; b < nb; ++b) t = cadd(t, part[b]);
-    out[0] = t.x;
-    out[1] = t.y;
+__global__ __launch_bounds__(TR_RED_T) void k_trace_rho_final(int nb, const double2 *part, double *out) {
+    __shared__ double2 red[TR_RED_T][2];
+    double2 t = make_double2(0.0, 0.0), u = make_double2(0.0, 0.0);
+    for (int b = threadIdx.x; b < nb; b += TR_RED_T) t = cadd(t, part[b]);
+    tree_sum2(t, u, red);
+    if (threadIdx.x == 0) {
+        out[0] = t.x;
+        out[1] = t.y;
+    }
 }
 
 struct TraceLayout {
@@ -181,7 +210,8 @@ extern "C" sgf_status sgf_traces(const sgf_system *sys, int64_t n_cols, const in
     SGF_REQUIRE(L.bytes <= ws_bytes, "sgf_traces: workspace %zu bytes < %zu", ws_bytes, L.bytes);
     hipStream_t st = as_stream(stream);
     if (n_cols > 0) {
-        const unsigned g = (unsigned)((n_cols + 255) / 256 < 65536 ? (n_cols + 255) / 256 : 65536);
+        const int64_t per_wg = 256 / TR_COEF_L;
+        const unsigned g = (unsigned)((n_cols + per_wg - 1) / per_wg < 65536 ? (n_cols + per_wg - 1) / per_wg : 65536);
         k_trace_coef<<<g, 256, 0, st>>>(n_cols, 4 * sys->n_atoms, d_cols, d_proj_off, d_proj_row, d_status,
                                         sys->row_ptr, sys->col, sys->h, sys->s, L.coef);
         SGF_LAUNCHED();
@@ -192,14 +222,14 @@ extern "C" sgf_status sgf_traces(const sgf_system *sys, int64_t n_cols, const in
         k_trace_partial<<<nb, threads, 0, st>>>(total_rows, n_shifts, reinterpret_cast<const double2 *>(d_G), L.coef,
                                                 L.part);
         SGF_LAUNCHED();
-        k_trace_final<<<(n_shifts + 127) / 128, 128, 0, st>>>(n_shifts, nb, L.part, reinterpret_cast<double2 *>(d_T),
-                                                              reinterpret_cast<double2 *>(d_U));
+        k_trace_final<<<n_shifts, TR_RED_T, 0, st>>>(n_shifts, nb, L.part, reinterpret_cast<double2 *>(d_T),
+                                                     reinterpret_cast<double2 *>(d_U));
         SGF_LAUNCHED();
     }
     if (d_rho) {
         k_trace_rho_partial<<<nb, TR_RHO_T, 0, st>>>(total_rows, d_rho, L.coef, L.rpart);
         SGF_LAUNCHED();
-        k_trace_rho_final<<<1, 64, 0, st>>>(nb, L.rpart, d_rho_tr);
+        k_trace_rho_final<<<1, TR_RED_T, 0, st>>>(nb, L.rpart, d_rho_tr);
         SGF_LAUNCHED();
     }
     return SGF_OK;
