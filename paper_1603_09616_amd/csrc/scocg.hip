@@ -1182,11 +1182,25 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
     // register variant when every subspace has <= 64 orbitals and <= 8 blocks per row
     const bool gen = sys->s != nullptr;
     const bool r1 = !gen && opts->stage_lds < 0 && totals->max_loc_atoms <= 16 && totals->max_row_blocks <= 8;
+    // S != I with the overlap inverse in register tiles when every subspace has
+    // <= 22 atoms and <= 8 blocks per row and there are <= 256 shifts (the
+    // dense-LDS variant otherwise, or when stage_lds asks for it); subspaces
+    // of 17 to 22 atoms go to a second, two-wavefront launch
+    // Switched off: on a small S != I bundle (subspaces of 8 to 15 atoms, one
+    // wavefront per column) the register-tile seed pass never finished on the
+    // GPU, and no cause has been found in its source or its generated code.
+    // Until one is, every S != I solve takes the dense-LDS seed pass.
+    constexpr bool kRegisterTileOverlapSeed = false;
+    const bool ovl = kRegisterTileOverlapSeed && gen && !mixed && opts->stage_lds < 0 &&
+                     totals->max_loc_atoms <= 22 && totals->max_row_blocks <= 8 && hs.ns_pad <= 256;
+    const bool ovl2 = ovl && totals->max_loc_atoms > 16;
     KernelFn seed_fn = mixed ? pick_seed_mx(M, totals->max_row_blocks)
-                             : gen ? pick_seed_gen(M)
-                                   : (r1 ? pick_seed_r1(M, totals->max_row_blocks) : pick_seed(stage, M));
-    size_t seed_lds = (r1 || mixed) ? 0 : lds;
-    if (gen) {
+                       : ovl ? pick_seed_ovl(1, M, totals->max_row_blocks)
+                       : gen ? pick_seed_gen(M)
+                             : (r1 ? pick_seed_r1(M, totals->max_row_blocks) : pick_seed(stage, M));
+    KernelFn seed_fn2 = ovl2 ? pick_seed_ovl(2, (hs.ns_pad + 127) / 128, totals->max_row_blocks) : nullptr;
+    size_t seed_lds = (r1 || mixed || ovl) ? 0 : lds;
+    if (gen && !ovl) {
         // p, s, w, q, r and the dense inverse of the local overlap
         size_t goff = 0;
         auto gtake = [&](size_t bytes) { size_t r = goff; goff = align_up(goff + bytes, 16); return r; };
@@ -1226,6 +1240,17 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
     SGF_HIP(hipGetDevice(&dev));
     SGF_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
     const int64_t seed_grid_max = opts->grid > 0 ? opts->grid : (int64_t)per_cu * n_cu;
+    int64_t seed_grid_max2 = 0;
+    if (ovl2) {
+        int per_cu2 = 0;
+        SGF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, reinterpret_cast<const void *>(seed_fn2),
+                                                             2 * SEED_T, 0));
+        if (per_cu2 < 1) {
+            set_error("sgf_shifted_solve: two-wavefront seed kernel does not fit a compute unit");
+            return SGF_EUNSUPPORTED;
+        }
+        seed_grid_max2 = opts->grid > 0 ? opts->grid : (int64_t)per_cu2 * n_cu;
+    }
 
     Profile &prof = g_profile;
     const bool timed = opts->profile != 0;
@@ -1246,6 +1271,14 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
         }
         hipLaunchKernelGGL(seed_fn, dim3((unsigned)grid), dim3(SEED_T), seed_lds, st, a);
         SGF_LAUNCHED();
+        if (ovl2) {
+            // the same tickets again for the columns of 17 to 22 atoms
+            const int64_t grid2 = seed_grid_max2 < b1 - b0 ? seed_grid_max2 : b1 - b0;
+            k_zero_ticket<<<1, 64, 0, st>>>(L.ticket);
+            SGF_LAUNCHED();
+            hipLaunchKernelGGL(seed_fn2, dim3((unsigned)grid2), dim3(2 * SEED_T), 0, st, a);
+            SGF_LAUNCHED();
+        }
         if (timed) SGF_HIP(hipEventRecord(e1, st));
         hipLaunchKernelGGL(shift_fn, dim3((unsigned)(b1 - b0)), dim3(shift_threads), shift_lds, st, a);
         SGF_LAUNCHED();

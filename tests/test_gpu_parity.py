@@ -321,3 +321,33 @@ def test_overlap_workload_sampled(sgf, O):
     sub.proj_row, sub.G, sub.rho = got.proj_row[rows], got.G[rows], got.rho[rows]
     sub.status, sub.iters = got.status[pick], got.iters[pick]
     compare(sub, ref)
+
+
+@pytest.mark.skip(reason="the register-tile S != I seed pass did not finish on the GPU (small overlap bundle, "
+                         "one wavefront per column); cause not found, so the path is switched off in the library")
+def test_overlap_register_tiles_match_dense_inverse(sgf):
+    """S != I seed pass with the overlap inverse in register tiles (one
+    wavefront up to 16 local atoms, two for 17 to 22) against the variant
+    that keeps the dense inverse in LDS, on columns of both sizes: same
+    layout and status, G and rho within 1e-10 per column (two inverses of the
+    same well-conditioned S_L, each iteration converged to 1e-12)."""
+    wl = W.config_bundle_overlap(n_columns=4096)
+    s = sgf.system_for(wl)
+    prep = sgf.prepare(s, wl.columns, radius_per_col=wl.radius_per_col)
+    n_loc = np.diff(prep.plan.atom_off.cpu().numpy())[prep.col_plan.cpu().numpy()]
+    print(f"  local atoms {n_loc.min()}..{n_loc.max()}: {int((n_loc <= 16).sum())} columns <= 16, "
+          f"{int((n_loc > 16).sum())} above", flush=True)
+    assert n_loc.min() <= 16 < n_loc.max() <= 22 and np.any(n_loc == 16) and np.any(n_loc == 17)
+    a = sgf.solve_prepared(prep, wl.z, wl.w, tol=wl.tol).numpy()
+    b = sgf.solve_prepared(prep, wl.z, wl.w, tol=wl.tol, stage_lds=0).numpy()
+    np.testing.assert_array_equal(a.status, b.status)
+    assert np.all(a.status == sgf.CONVERGED)
+    err_g = err_r = 0.0
+    for c in range(0, wl.columns.size, 7):
+        r0, r1 = a.proj_off[c], a.proj_off[c + 1]
+        err_g = max(err_g, np.abs(a.G[r0:r1] - b.G[r0:r1]).max() / np.abs(b.G[r0:r1]).max())
+        err_r = max(err_r, np.abs(a.rho[r0:r1] - b.rho[r0:r1]).max() / np.abs(b.rho[r0:r1]).max())
+    print(f"  tiles vs dense: G {err_g:.2e}  rho {err_r:.2e}; iterations {a.iters.mean():.1f} vs "
+          f"{b.iters.mean():.1f}", flush=True)
+    assert err_g < 1e-10 and err_r < 1e-10
+    assert abs(a.iters.mean() - b.iters.mean()) <= 0.02 * b.iters.mean()
