@@ -11,6 +11,8 @@ Contents:
 * this module: ctypes binding, plus the dense definitions the iterative result
   must agree with (exact restricted solve, eigen-expansion).
 * ``mlp.py``: FP64 reference of the iteration-count network.
+* ``wp.py``: wavepacket time propagation (exact by eigen-decomposition, and
+  the Chebyshev series), Gershgorin bounds.
 """
 from __future__ import annotations
 

@@ -38,6 +38,7 @@ STREAM_GEOMETRY = 0
 STREAM_COLUMNS = 1
 STREAM_RADII = 2
 STREAM_MLP = 3
+STREAM_WAVEPACKET = 4
 
 
 def rng(config_no: int, stream: int) -> np.random.Generator:
@@ -292,3 +293,44 @@ def mlp_init(seed: int = 0) -> np.ndarray:
     p[o:o + MLP_NH] = g.normal(0, np.sqrt(1.0 / MLP_NH), MLP_NH)
     return p
 
+
+
+# ---------------------------------------------------------------------------
+# Initial wavepackets of the time-propagation workload.
+# ---------------------------------------------------------------------------
+
+def wavepacket(wl: Workload, n_packets: int = 1, *, width: float = 0.5, k_z: float = 10.0,
+               config_no: int = 6) -> np.ndarray:
+    """Initial wavepackets [n_orb, n_packets] complex128, each of unit 2-norm.
+
+    Packet p is centred on a seeded atom c_p.  Atom A within 4 * width of it
+    (nm; for the chain, site distance in units of one site) carries
+    exp(-|r_A - r_c|^2 / (4 width^2)) * exp(i k_z (z_A - z_c)) times a seeded
+    unit vector of orbital weights (the same for every atom of the packet);
+    all other entries are zero.
+    """
+    g = rng(config_no, STREAM_WAVEPACKET)
+    n_atoms = wl.n_atoms
+    if wl.xyz is None:  # chain: one orbital per site, sites on a line
+        pos = np.zeros((wl.n_orb, 3))
+        pos[:, 2] = np.arange(wl.n_orb, dtype=np.float64)
+        per_site = True
+    else:
+        pos = wl.xyz
+        per_site = False
+    out = np.zeros((wl.n_orb, n_packets), np.complex128)
+    n_centres = wl.n_orb if per_site else n_atoms
+    for p in range(n_packets):
+        c = int(g.integers(0, n_centres))
+        u = g.normal(size=4)
+        u /= np.linalg.norm(u)
+        d = pos - pos[c]
+        r2 = (d * d).sum(axis=1)
+        near = r2 <= (4.0 * width) ** 2
+        amp = np.where(near, np.exp(-r2 / (4.0 * width * width)) * np.exp(1j * k_z * d[:, 2]), 0.0)
+        if per_site:
+            out[:, p] = amp
+        else:
+            out[:, p] = (amp[:, None] * u[None, :]).ravel()
+        out[:, p] /= np.linalg.norm(out[:, p])
+    return out
