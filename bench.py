@@ -159,6 +159,48 @@ def hbm_stream(sgf, W, dev, reps=50):
             "cases": cases, "best": best, "best_frac": cases[best]["frac"]}
 
 
+def wp_stream(sgf, W, dev, steps=10):
+    """Wavepacket propagation (Chebyshev steps of exp(-i H h / hbar), h = 0.1
+    fs) on the 1,000,300-atom share, 1 and 8 packets, `steps` steps timed with
+    HIP events after one warm-up step.  Algorithmic bytes per step: each of
+    the K series terms reads the blocks, their column indices and row
+    pointers once, plus the vectors it streams (first term: T_0 read, T_1 and
+    the sum written; middle terms: T_k read, T_{k-1} read and written, the sum
+    read and written; last term: T_k read, T_{k-1} read and written, the sum
+    read)."""
+    import torch
+    wl = W.config_large(n_columns=16)
+    s = sgf.system_for(wl)
+    n = 4 * s.n_atoms
+    lo, hi = sgf.wp_bounds(s)
+    a_tau = 0.5 * (hi - lo) * 0.1 / sgf.HBAR_EV_FS
+    K = sgf.wp_terms(a_tau, 1e-13)
+    cases = {}
+    for k in (1, 8):
+        psi0 = torch.as_tensor(W.wavepacket(wl, k), device=dev)
+        psi = (psi0[:, 0] if k == 1 else psi0).contiguous().clone()
+        sgf.wp_propagate(s, psi, 0.1, 1, lo, hi, K)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sgf.wp_propagate(s, psi, 0.1, steps, lo, hi, K)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        mat = s.nnzb * (128 + 4) + (s.n_atoms + 1) * 4
+        vec = n * k * 16
+        nbytes = K * mat + vec * (3 + 5 * (K - 3) + 4)
+        norm = torch.linalg.vector_norm(psi.reshape(n, k), dim=0).cpu().numpy()
+        cases[f"rhs{k}"] = {"ms_per_step": ms, "terms": K, "bytes_per_step": nbytes, "GBps": nbytes / ms / 1e6,
+                            "frac": nbytes / ms / 1e6 / PEAK_HBM_GBS, "fs_per_s": 0.1 / (ms * 1e-3),
+                            "norm_drift": float(np.abs(norm - 1).max())}
+        log(f"[bench] wavepacket x{k}: {ms:.2f} ms per 0.1 fs step ({K} terms), {nbytes / ms / 1e6:.0f} GB/s")
+        del psi, psi0
+    return {"kernel": "k_cheb_term", "workload": "wavepacket steps of 0.1 fs on the 1,000,300-atom bundle share "
+            f"({s.n_atoms} block rows, {s.nnzb} 4x4 blocks), Gershgorin bounds [{lo:.2f}, {hi:.2f}] eV",
+            "peak_GBps": PEAK_HBM_GBS, "steps": steps, "cases": cases}
+
+
 def extra_workloads(sgf, W, dev, ws_gib, check_n):
     """The other two workloads, one timed solve each after a warm-up:
     the overlap bundle (S != I, per-column radius U[0.6, 1.4] nm, 256 shifts,
@@ -457,6 +499,7 @@ def main(argv=None):
         del s_probe, p_probe
         torch.cuda.empty_cache()
         hbm = hbm_stream(sgf, W, dev)
+        hbm["wavepacket"] = wp_stream(sgf, W, dev)
 
     extra, extra_keep = None, None
     if not args.no_extra:

@@ -459,6 +459,48 @@ sgf_status sgf_occupation(int32_t n_shifts, const double *T, const double *U, co
 sgf_status sgf_fermi_level(int32_t n_shifts, const double *z, const double *T, const double *U, double n_target,
                            double *mu, double *n_e, double *e_band);
 
+/* ------------------------------------------------------------------------ */
+/* Wavepacket propagation                                                     */
+/* ------------------------------------------------------------------------ */
+
+/* The wavepacket dynamics of Sec. 5 (Fig. 5) integrate d/dt Psi = -i H Psi
+ * / hbar (H in eV, t in fs, hbar = 0.6582119569509066 eV fs) in steps of
+ * h (0.1 fs in the paper) with the tight-binding H in an orthogonal basis
+ * (S = I).  One step applies exp(-i tau H), tau = h / hbar, as the Chebyshev
+ * series of Tal-Ezer and Kosloff (J. Chem. Phys. 81, 3967 (1984)): with
+ * a = (e_max - e_min)/2 and b = (e_max + e_min)/2 from bounds of the
+ * spectrum, exp(-i tau H) = exp(-i tau b) sum_{k<K} c_k T_k((H - b)/a),
+ * c_0 = J_0(a tau), c_k = 2 (-i)^k J_k(a tau). */
+
+/* Bytes of device workspace for sgf_wp_bounds and sgf_wp_propagate on a
+ * system of n_atoms atoms with n_rhs (1, 2, 4 or 8) packets: two complex
+ * vectors [4 n_atoms][n_rhs]. */
+sgf_status sgf_wp_workspace(int64_t n_atoms, int32_t n_rhs, size_t *ws_bytes);
+
+/* Gershgorin bounds of H: e_min = min_i (H_ii - R_i), e_max =
+ * max_i (H_ii + R_i), R_i = sum_{j != i} |H_ij|, which contain its spectrum.
+ * SYNCHRONOUS (host outputs; waits for the stream).  d_ws: a workspace of at
+ * least sgf_wp_workspace(n_atoms, 1) bytes. */
+sgf_status sgf_wp_bounds(const sgf_system *sys, void *d_ws, size_t ws_bytes, double *e_min, double *e_max,
+                         void *stream);
+
+/* Host: number of series terms K for argument a tau (a = half the width of
+ * the bounds): the smallest K > |a tau| with |J_K| and |J_{K+1}| <= tol (the
+ * Bessel functions decay faster than geometrically beyond |a tau|, so the
+ * dropped tail is about tol); at least 3. */
+sgf_status sgf_wp_terms(double a_tau, double tol, int32_t *n_terms);
+
+/* n_steps steps of length h_fs (negative h runs backwards) of the n_rhs
+ * packets in d_psi: complex128 [4 n_atoms][n_rhs] (packets contiguous per
+ * orbital), overwritten with the result.  e_min < e_max must contain the
+ * spectrum (sgf_wp_bounds); n_terms >= 3 (sgf_wp_terms).  Per term one
+ * pass over H in HBM fused with the recurrence and the accumulation of the
+ * series; d_ws (sgf_wp_workspace bytes) holds the two other Chebyshev
+ * vectors.  SGF_EUNSUPPORTED when the system has an overlap S.
+ * Asynchronous on the stream. */
+sgf_status sgf_wp_propagate(const sgf_system *sys, int32_t n_rhs, double *d_psi, double h_fs, int32_t n_steps,
+                            double e_min, double e_max, int32_t n_terms, void *d_ws, size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

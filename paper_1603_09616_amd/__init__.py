@@ -27,7 +27,7 @@ EXPORTED = (
     "sgf_proj_rows", "sgf_solve_workspace", "sgf_shifted_solve", "sgf_solve_profile", "sgf_features", "sgf_mlp_normalize",
     "sgf_mlp_forward", "sgf_mlp_train_step", "sgf_mlp_gradient", "sgf_order_workspace", "sgf_order_by_prediction",
     "sgf_bsr_apply", "sgf_solve_stage_shifts", "sgf_trace_workspace", "sgf_traces", "sgf_occupation",
-    "sgf_fermi_level",
+    "sgf_fermi_level", "sgf_wp_workspace", "sgf_wp_bounds", "sgf_wp_terms", "sgf_wp_propagate",
 )
 MLP_NFEAT, MLP_NPARAM, MLP_BATCH = 5, 4619, 128
 
@@ -110,6 +110,10 @@ def lib():
             "sgf_traces": [P, i64, P, P, P, P, i64, P, P, i32, P, szt, P, P, P, P],
             "sgf_occupation": [i32, P, P, P, P, P],
             "sgf_fermi_level": [i32, P, P, P, dbl, P, P, P],
+            "sgf_wp_workspace": [i64, i32, P],
+            "sgf_wp_bounds": [P, P, szt, P, P, P],
+            "sgf_wp_terms": [dbl, dbl, P],
+            "sgf_wp_propagate": [P, i32, P, dbl, i32, dbl, dbl, i32, P, szt, P],
         }
         for name, args in sigs.items():
             f = getattr(L, name)
@@ -686,3 +690,46 @@ def order_by_prediction(pred, y_lo, y_hi, stream=None):
           ws.value, _stream(stream))
     return order[:n]
 
+
+
+# --- wavepacket propagation ---------------------------------------------------
+
+HBAR_EV_FS = 0.6582119569509066  # eV fs
+
+
+def wp_bounds(system: System, stream=None):
+    """(e_min, e_max): Gershgorin bounds of H (synchronous)."""
+    ws = ctypes.c_size_t()
+    _call("sgf_wp_workspace", int(system.n_atoms), 1, ctypes.byref(ws))
+    d_ws = _bytes(ws.value, system.row_ptr.device)
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    _call("sgf_wp_bounds", ctypes.byref(system.c()), _ptr(d_ws), ws.value, ctypes.byref(lo), ctypes.byref(hi),
+          _stream(stream))
+    return lo.value, hi.value
+
+
+def wp_terms(a_tau: float, tol: float = 1e-13) -> int:
+    """Series length for argument a tau (smallest K > |a tau| with
+    |J_K|, |J_{K+1}| <= tol, at least 3)."""
+    k = ctypes.c_int32()
+    _call("sgf_wp_terms", float(a_tau), float(tol), ctypes.byref(k))
+    return k.value
+
+
+def wp_propagate(system: System, psi, h_fs: float, n_steps: int, e_min: float, e_max: float, n_terms: int,
+                 stream=None):
+    """n_steps Chebyshev steps of length h_fs of the packets in psi, in place:
+    complex128 device tensor [n_orb] or [n_orb, n_rhs] (n_rhs in 1, 2, 4, 8),
+    contiguous.  Returns psi."""
+    torch = _torch()
+    if psi.dtype != torch.complex128 or not psi.is_contiguous():
+        raise ValueError("psi must be a contiguous complex128 tensor")
+    n_rhs = 1 if psi.dim() == 1 else int(psi.shape[1])
+    if psi.shape[0] != 4 * system.n_atoms:
+        raise ValueError("psi must have 4 * n_atoms rows")
+    ws = ctypes.c_size_t()
+    _call("sgf_wp_workspace", int(system.n_atoms), n_rhs, ctypes.byref(ws))
+    d_ws = _bytes(ws.value, psi.device)
+    _call("sgf_wp_propagate", ctypes.byref(system.c()), n_rhs, _ptr(psi), float(h_fs), int(n_steps), float(e_min),
+          float(e_max), int(n_terms), _ptr(d_ws), ws.value, _stream(stream))
+    return psi
