@@ -338,6 +338,7 @@ def main(argv=None):
                     help="library default launch (for profiler runs, which distort the tuner's timings)")
     ap.add_argument("--spmv-only", action="store_true",
                     help="only the operator-apply measurement and a 1 GiB copy (for counter passes)")
+    ap.add_argument("--wp-only", action="store_true", help="only the wavepacket-propagation measurement")
     args = ap.parse_args(argv)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: every run of this path uses a single MI355X; columns are "
@@ -354,6 +355,9 @@ def main(argv=None):
     torch.cuda.set_device(dev)
     if args.spmv_only:
         print(json.dumps({"hbm_stream": hbm_stream(sgf, W, dev), "copy": copy_reference(dev)}), flush=True)
+        return 0
+    if args.wp_only:
+        print(json.dumps({"wavepacket": wp_stream(sgf, W, dev)}), flush=True)
         return 0
     wl = W.config_bundle()
     ns = wl.z.size
