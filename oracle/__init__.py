@@ -13,6 +13,8 @@ Contents:
 * ``mlp.py``: FP64 reference of the iteration-count network.
 * ``wp.py``: wavepacket time propagation (exact by eigen-decomposition, and
   the Chebyshev series), Gershgorin bounds.
+* ``forces.py``: band-structure forces -dE_band/dR at fixed rho (Slater-Koster
+  block gradient).
 """
 from __future__ import annotations
 
