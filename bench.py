@@ -290,10 +290,11 @@ def copy_reference(dev, nbytes=1 << 30, reps=10):
 
 
 def after_rho(sgf, prep, res, wl, reps=5):
-    """The step after rho on the timed step's outputs: the traces of the
+    """The steps after rho on the timed step's outputs: the traces of the
     projected G (an HBM-bound pass that streams all of G once), then the
-    half-filling Fermi level, electron count and band energy from them, and
-    the row identity z_k T_k - U_k = n_cols as a check."""
+    half-filling Fermi level, electron count and band energy from them, the
+    row identity z_k T_k - U_k = n_cols as a check, and the band forces
+    -dE_band/dR at fixed rho."""
     import torch
     n_rows, ns = int(prep.n_rows), int(res.G.shape[1])
     ms = []
@@ -312,11 +313,26 @@ def after_rho(sgf, prep, res, wl, reps=5):
     alg = g_bytes + n_rows * (16 + 16 + 4) + n * (8 + 8 + 4)
     t = float(np.median(ms))
     mu, ne, eb = sgf.fermi_level(wl.z, T, U, 0.5 * n)
+    # band forces -dE_band/dR at fixed rho from the same step
+    fms = []
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        F = sgf.band_forces(prep, res, wl.tb)
+        e1.record()
+        torch.cuda.synchronize()
+        if r:
+            fms.append(e0.elapsed_time(e1))
+    Fh = F.cpu().numpy()
     return {"what": "T_k = sum_j (G S)_jj, U_k = sum_j (G H)_jj over all columns, then the half-filling Fermi level",
             "ms": t, "G_bytes": g_bytes, "alg_bytes": alg, "GBps": alg / (t * 1e-3) / 1e9,
             "frac_of_8TBps": alg / (t * 1e-3) / 8e12, "reps": reps,
             "identity_gap_max": float(np.abs(wl.z * T - U - n).max()), "identity_bound": 10 * wl.tol * n,
-            "mu_half_filling_eV": mu, "n_e": ne, "e_band_eV": eb, "tr_rho_S": ts, "tr_rho_H_eV": th}
+            "mu_half_filling_eV": mu, "n_e": ne, "e_band_eV": eb, "tr_rho_S": ts, "tr_rho_H_eV": th,
+            "band_forces": {"ms": float(np.median(fms)), "rows_per_s": n_rows / (float(np.median(fms)) * 1e-3),
+                            "max_abs_eV_per_nm": float(np.abs(Fh).max()),
+                            "sum_over_atoms_max": float(np.abs(Fh.sum(axis=0)).max())}}
 
 
 def main(argv=None):

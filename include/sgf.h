@@ -501,6 +501,28 @@ sgf_status sgf_wp_terms(double a_tau, double tol, int32_t *n_terms);
 sgf_status sgf_wp_propagate(const sgf_system *sys, int32_t n_rhs, double *d_psi, double h_fs, int32_t n_steps,
                             double e_min, double e_max, int32_t n_terms, void *d_ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------------------------ */
+/* Band-structure forces                                                      */
+/* ------------------------------------------------------------------------ */
+
+/* The force step of the quantum molecular dynamics (Sec. 2): with S = I,
+ * F_A = -dE_band/dR_A at fixed rho, where E_band = sum_j sum_{i in P(j)}
+ * rho_ij H_ij over the solved columns (per spin; the tr(rho H) of
+ * sgf_traces).  Each term acts on both atoms of its block: with i on atom B
+ * and j on atom C (B != C), g = rho_ij d h_{o_i q_j}/dd at d = R_C - R_B
+ * (the Slater-Koster block of sgf_build_hamiltonian with parameters p)
+ * enters F_C with a minus sign and F_B with a plus sign, so the forces sum
+ * to zero.  With all columns solved this is the Hellmann-Feynman band force;
+ * the repulsive and van der Waals terms are not included.
+ * d_xyz: positions (nm, [n_atoms][3]); d_cols, d_proj_off, d_proj_row and
+ * d_rho: the columns and projected density matrix of a solve.  Writes
+ * d_force [n_atoms][3] (eV/nm), cleared first.  FP64 atomics add the terms,
+ * in no fixed order: repeated runs agree to rounding.  SGF_EUNSUPPORTED
+ * when the system has an overlap S.  Asynchronous on the stream. */
+sgf_status sgf_band_forces(const sgf_system *sys, const double *d_xyz, const sgf_tb_params *p, int64_t n_cols,
+                           const int64_t *d_cols, const int64_t *d_proj_off, const int32_t *d_proj_row,
+                           const double *d_rho, double *d_force, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,6 +28,7 @@ EXPORTED = (
     "sgf_mlp_forward", "sgf_mlp_train_step", "sgf_mlp_gradient", "sgf_order_workspace", "sgf_order_by_prediction",
     "sgf_bsr_apply", "sgf_solve_stage_shifts", "sgf_trace_workspace", "sgf_traces", "sgf_occupation",
     "sgf_fermi_level", "sgf_wp_workspace", "sgf_wp_bounds", "sgf_wp_terms", "sgf_wp_propagate",
+    "sgf_band_forces",
 )
 MLP_NFEAT, MLP_NPARAM, MLP_BATCH = 5, 4619, 128
 
@@ -114,6 +115,7 @@ def lib():
             "sgf_wp_bounds": [P, P, szt, P, P, P],
             "sgf_wp_terms": [dbl, dbl, P],
             "sgf_wp_propagate": [P, i32, P, dbl, i32, dbl, dbl, i32, P, szt, P],
+            "sgf_band_forces": [P, P, P, i64, P, P, P, P, P, P],
         }
         for name, args in sigs.items():
             f = getattr(L, name)
@@ -733,3 +735,21 @@ def wp_propagate(system: System, psi, h_fs: float, n_steps: int, e_min: float, e
     _call("sgf_wp_propagate", ctypes.byref(system.c()), n_rhs, _ptr(psi), float(h_fs), int(n_steps), float(e_min),
           float(e_max), int(n_terms), _ptr(d_ws), ws.value, _stream(stream))
     return psi
+
+
+# --- band-structure forces ---------------------------------------------------------
+
+def band_forces(prep: Prepared, res: Result, params, xyz=None, stream=None):
+    """F = -dE_band/dR at fixed rho (S = I), E_band over the solved columns:
+    float64 [n_atoms, 3] on the device (eV/nm).  params: the tight-binding
+    parameters the system was built with; xyz: positions [n_atoms, 3] (nm;
+    the system's own when omitted)."""
+    torch = _torch()
+    dev = prep.cols.device
+    d_xyz = _dev(prep.system.xyz if xyz is None else xyz, torch.float64, dev)
+    F = torch.empty((prep.system.n_atoms, 3), dtype=torch.float64, device=dev)
+    sc = prep.system.c()
+    tb = _tb_c(params)
+    _call("sgf_band_forces", ctypes.byref(sc), _ptr(d_xyz), ctypes.byref(tb), int(prep.cols.numel()), _ptr(prep.cols),
+          _ptr(prep.proj_off), _ptr(prep.proj_row), _ptr(res.rho), _ptr(F), _stream(stream))
+    return F

@@ -1,0 +1,130 @@
+// forces.hip -- band-structure forces from the density matrix (the force
+// step of the quantum molecular dynamics, Sec. 2 of the paper).
+//
+// Orthogonal basis (S = I).  The band energy of the solved columns is
+// E_band = sum_j sum_{i in P(j)} rho_ij H_ij (per spin), and the force is
+// F_A = -dE_band/dR_A at fixed rho.  Each column's rho comes from its own
+// local subspace, so rho is not symmetric and both atoms of a block take
+// part: H_ij for orbital i on atom B and j on atom C (B != C) is element
+// (o_i, q_j) of the Slater-Koster block h(d), d = R_C - R_B, and the term
+// g = rho_ij grad h_{o_i q_j}(d) enters F_C with a minus sign and F_B with a
+// plus sign.  On-site blocks do not depend on positions.
+//
+// One thread per column walks its projection rows, sums the terms of each
+// neighbour atom (its rows are consecutive) and adds them, and the total of
+// the column, into the force array with FP64 atomics.  The summation order of
+// those atomics is not fixed: repeated runs agree to rounding, not bit for
+// bit.
+#include "common.hpp"
+
+namespace sgf {
+
+namespace {
+
+constexpr int FORCE_T = 256;
+
+// Gradient with respect to d of element (o, q) of the Slater-Koster block
+// (orbitals s, px, py, pz): with c = d / r and f = (r0 / r)^power,
+// dc_a/dd_k = (delta_ak - c_a c_k) / r and df/dd_k = -power f c_k / r.
+__device__ void sk_elem_grad(const sgf_tb_params &p, double d0, double d1, double d2, int o, int q, double g[3]) {
+    const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    const double ir = 1.0 / r;
+    const double c[3] = {d0 * ir, d1 * ir, d2 * ir};
+    const double f = pow(p.r0 * ir, p.power);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double df = -p.power * f * c[k] * ir;
+        double v;
+        if (o == 0 && q == 0) {
+            v = p.v_sss * df;
+        } else if (o == 0 || q == 0) {
+            const int a = (o == 0 ? q : o) - 1;
+            const double dca = ((a == k ? 1.0 : 0.0) - c[a] * c[k]) * ir;
+            v = p.v_sps * (dca * f + c[a] * df);
+            if (q == 0) v = -v;
+        } else {
+            const int a = o - 1, b = q - 1;
+            const double dca = ((a == k ? 1.0 : 0.0) - c[a] * c[k]) * ir;
+            const double dcb = ((b == k ? 1.0 : 0.0) - c[b] * c[k]) * ir;
+            v = (dca * c[b] + c[a] * dcb) * (p.v_pps - p.v_ppp) * f +
+                (c[a] * c[b] * (p.v_pps - p.v_ppp) + (a == b ? p.v_ppp : 0.0)) * df;
+        }
+        g[k] = v;
+    }
+}
+
+__device__ __forceinline__ void add3(double *F, int64_t atom, const double g[3], double sign) {
+    atomicAdd(&F[3 * atom + 0], sign * g[0]);
+    atomicAdd(&F[3 * atom + 1], sign * g[1]);
+    atomicAdd(&F[3 * atom + 2], sign * g[2]);
+}
+
+__global__ __launch_bounds__(FORCE_T) void k_zero_f64(int64_t n, double *x) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = 0.0;
+}
+
+__global__ __launch_bounds__(FORCE_T) void k_band_force(int64_t n_cols, int64_t n_atoms, const double *xyz,
+                                                        sgf_tb_params p, const int64_t *cols, const int64_t *proj_off,
+                                                        const int32_t *proj_row, const double *rho, double *F) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cols) return;
+    const int64_t j = cols[c];
+    const int64_t C = j >> 2;
+    if (j < 0 || C >= n_atoms) return;
+    const int q = (int)(j & 3);
+    const double rc0 = xyz[3 * C], rc1 = xyz[3 * C + 1], rc2 = xyz[3 * C + 2];
+    double own[3] = {0.0, 0.0, 0.0}, nb[3] = {0.0, 0.0, 0.0};
+    int64_t cur = -1;
+    for (int64_t t = proj_off[c]; t < proj_off[c + 1]; ++t) {
+        const int32_t i = proj_row[t];
+        const int64_t B = i >> 2;
+        if (B == C || B < 0 || B >= n_atoms) continue;
+        if (B != cur) {
+            if (cur >= 0) add3(F, cur, nb, 1.0);
+            cur = B;
+            nb[0] = nb[1] = nb[2] = 0.0;
+        }
+        double g[3];
+        sk_elem_grad(p, rc0 - xyz[3 * B], rc1 - xyz[3 * B + 1], rc2 - xyz[3 * B + 2], i & 3, q, g);
+        const double w = rho[t];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            nb[k] = fma(w, g[k], nb[k]);
+            own[k] = fma(w, g[k], own[k]);
+        }
+    }
+    if (cur >= 0) add3(F, cur, nb, 1.0);
+    add3(F, C, own, -1.0);
+}
+
+}  // namespace
+
+}  // namespace sgf
+
+using namespace sgf;
+
+extern "C" sgf_status sgf_band_forces(const sgf_system *sys, const double *d_xyz, const sgf_tb_params *p,
+                                      int64_t n_cols, const int64_t *d_cols, const int64_t *d_proj_off,
+                                      const int32_t *d_proj_row, const double *d_rho, double *d_force,
+                                      void *stream) {
+    SGF_REQUIRE(sys && d_xyz && p && d_force, "sgf_band_forces: NULL argument");
+    SGF_REQUIRE(sys->n_atoms > 0 && n_cols >= 0, "sgf_band_forces: bad sizes");
+    SGF_REQUIRE(n_cols == 0 || (d_cols && d_proj_off && d_proj_row && d_rho), "sgf_band_forces: column layout is NULL");
+    SGF_REQUIRE(p->r0 > 0.0, "sgf_band_forces: r0 must be positive");
+    if (sys->s) {
+        set_error("sgf_band_forces: forces are built for an orthogonal basis (S = I)");
+        return SGF_EUNSUPPORTED;
+    }
+    hipStream_t st = as_stream(stream);
+    const int64_t nf = 3 * sys->n_atoms;
+    const unsigned gz = (unsigned)((nf + FORCE_T - 1) / FORCE_T < 65536 ? (nf + FORCE_T - 1) / FORCE_T : 65536);
+    k_zero_f64<<<gz, FORCE_T, 0, st>>>(nf, d_force);
+    SGF_LAUNCHED();
+    if (n_cols > 0) {
+        k_band_force<<<(unsigned)((n_cols + FORCE_T - 1) / FORCE_T), FORCE_T, 0, st>>>(
+            n_cols, sys->n_atoms, d_xyz, *p, d_cols, d_proj_off, d_proj_row, d_rho, d_force);
+        SGF_LAUNCHED();
+    }
+    return SGF_OK;
+}
