@@ -472,14 +472,19 @@ __global__ __launch_bounds__(SEED_T) void k_seed_r1(SolveArgs a) {
 // w = (z_s S - H) p = z_s q - H p, so mu = p^T w and rho = r^T s.  The inverse
 // of the local overlap S_L is formed once per column in LDS by in-place
 // Gauss-Jordan elimination (S_L is symmetric positive definite, so no
-// pivoting) and applied as a dense product each iteration.  The recorded
-// history holds r on P: the shifted iterates are combinations of the r_n.
+// pivoting) and applied as a dense product each iteration, four independent
+// partial sums per row so that the LDS reads overlap.  Lane l owns rows l
+// and l + 64; with BMAX > 0 their blocks of H (at most BMAX per row) and
+// local columns stay in registers for the whole column, with BMAX = 0 (any
+// number of blocks per row) they are read from the local operator in global
+// memory every iteration.  The recorded history holds r on P: the
+// shifted iterates are combinations of the r_n.
 // ---------------------------------------------------------------------------
 // Row stride (doubles) of the dense local overlap inverse: the smallest
 // 32k + 1 >= nl.  Lane i reading row i then starts on bank pair 2i (mod 64).
 __host__ __device__ inline int sinv_ld(int nl) { return 32 * ((nl + 30) / 32) + 1; }
 
-template <int M>
+template <int M, int BMAX>
 __global__ __launch_bounds__(SEED_T) void k_seed_gen(SolveArgs a) {
     extern __shared__ double4 lds4[];
     char *lds = reinterpret_cast<char *>(lds4);
@@ -526,7 +531,7 @@ __global__ __launch_bounds__(SEED_T) void k_seed_gen(SolveArgs a) {
             p0 = a.pa_off[pl];
             npa = (int)(a.pa_off[pl + 1] - p0);
             cl = a.center_loc[pl];
-            bad = n_loc < 1 || n_loc > a.max_loc_atoms || npa < 1 || 4 * npa > a.rmax || cl < 0 || cl >= n_loc ||
+            bad = n_loc < 1 || n_loc > 32 || n_loc > a.max_loc_atoms || npa < 1 || 4 * npa > a.rmax || cl < 0 || cl >= n_loc ||
                   a.loc_atom[a0 + cl] != (int32_t)(j >> 2);
         }
         if (bad) {
@@ -538,6 +543,43 @@ __global__ __launch_bounds__(SEED_T) void k_seed_gen(SolveArgs a) {
             continue;
         }
         const int nl = 4 * n_loc;
+        // rows lane and lane + 64 of H: their blocks and local columns;
+        // absent blocks hold zeros and point at atom 0
+        constexpr int NBR = BMAX > 0 ? BMAX : 1;
+        int bcol[2][NBR];
+        double hrow[2][NBR][4];
+        bool wide = false;
+#pragma unroll
+        for (int r = 0; r < (BMAX > 0 ? 2 : 0); ++r) {
+            const int i = lane + 64 * r;
+            const int A = i >> 2, o = i & 3;
+            int t0 = 0, nb = 0;
+            if (i < nl) {
+                t0 = a.lrow[a0 + A];
+                nb = (A + 1 < n_loc ? a.lrow[a0 + A + 1] : nblk) - t0;
+            }
+            wide = wide || nb > BMAX;
+#pragma unroll
+            for (int b = 0; b < NBR; ++b) {
+                bcol[r][b] = 0;
+                hrow[r][b][0] = hrow[r][b][1] = hrow[r][b][2] = hrow[r][b][3] = 0.0;
+                if (b < nb) {
+                    const int32_t *lb = &a.lblk[2 * (b0 + t0 + b)];
+                    bcol[r][b] = lb[0];
+                    const double *hb = &a.h[16 * (int64_t)lb[1] + 4 * o];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) hrow[r][b][q] = hb[q];
+                }
+            }
+        }
+        if (__any(wide)) {
+            if (lane == 0) {
+                *meta = ColMeta{-1, 0, 0, SGF_BADCOLUMN};
+                a.iters[c] = 0;
+                a.status[c] = SGF_BADCOLUMN;
+            }
+            continue;
+        }
         // row stride of the dense inverse: 32k + 1 doubles, so that the lanes
         // of a wavefront, each on its own row, read consecutive LDS banks
         const int ld = sinv_ld(nl);
@@ -565,11 +607,34 @@ __global__ __launch_bounds__(SEED_T) void k_seed_gen(SolveArgs a) {
             wave_lds_fence();
             for (int jj = lane; jj < nl; jj += SEED_T) Si[kk * ld + jj] = (jj == kk) ? piv : Si[kk * ld + jj] * piv;
             wave_lds_fence();
-            for (int i = lane; i < nl; i += SEED_T) {
-                if (i == kk) continue;
-                const double f = Si[i * ld + kk];
-                for (int jj = 0; jj < nl; ++jj)
-                    Si[i * ld + jj] = (jj == kk) ? -f * Si[kk * ld + jj] : fma(-f, Si[kk * ld + jj], Si[i * ld + jj]);
+            // rows lane and lane + 64 (not the pivot row): a_ij -= a_ik a_kj for
+            // every j, then a_ik = -a_ik piv; the two rows share each read of
+            // the pivot row (nl is a multiple of 4)
+            {
+                const double *pr = &Si[kk * ld];
+                const int i0 = lane, i1 = lane + 64;
+                const bool e0 = i0 < nl && i0 != kk, e1 = i1 < nl && i1 != kk;
+                double *w0 = &Si[(e0 ? i0 : kk) * ld], *w1 = &Si[(e1 ? i1 : kk) * ld];
+                const double f0 = e0 ? w0[kk] : 0.0, f1 = e1 ? w1[kk] : 0.0;
+                if (nl > 64) {
+                    if (e0 || e1) {
+                        for (int jj = 0; jj < nl; jj += 4) {
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                const double pv = pr[jj + u];
+                                if (e0) w0[jj + u] = fma(-f0, pv, w0[jj + u]);
+                                if (e1) w1[jj + u] = fma(-f1, pv, w1[jj + u]);
+                            }
+                        }
+                    }
+                } else if (e0) {
+                    for (int jj = 0; jj < nl; jj += 4) {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) w0[jj + u] = fma(-f0, pr[jj + u], w0[jj + u]);
+                    }
+                }
+                if (e0) w0[kk] = -f0 * piv;
+                if (e1) w1[kk] = -f1 * piv;
             }
             wave_lds_fence();
         }
@@ -606,18 +671,33 @@ __global__ __launch_bounds__(SEED_T) void k_seed_gen(SolveArgs a) {
         for (int it = 0; it < max_iter; ++it) {
             // w = z_s q - H p ; mu = p^T w
             double m0 = 0.0, m1 = 0.0;
-            for (int i = lane; i < nl; i += SEED_T) {
-                const int A = i >> 2, o = i & 3;
-                double ax = 0.0, ay = 0.0;
-                const int t0 = a.lrow[a0 + A], t1 = A + 1 < n_loc ? a.lrow[a0 + A + 1] : nblk;
-                for (int t = t0; t < t1; ++t) {
-                    const int B = a.lblk[2 * (b0 + t)];
-                    const double *hrow = &a.h[16 * (int64_t)a.lblk[2 * (b0 + t) + 1] + 4 * o];
-                    const double2 *pb = &vp[4 * B];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        ax = fma(hrow[q], pb[q].x, ax);
-                        ay = fma(hrow[q], pb[q].y, ay);
+            for (int r = 0; r < 2; ++r) {
+                const int i = lane + 64 * r;
+                if (i >= nl) continue;
+                double ax = 0.0, ay = 0.0;
+                if constexpr (BMAX > 0) {
+#pragma unroll
+                    for (int b = 0; b < BMAX; ++b) {
+                        const double2 *pb = &vp[4 * bcol[r][b]];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            ax = fma(hrow[r][b][q], pb[q].x, ax);
+                            ay = fma(hrow[r][b][q], pb[q].y, ay);
+                        }
+                    }
+                } else {
+                    const int A = i >> 2, o = i & 3;
+                    const int t0 = a.lrow[a0 + A], t1 = A + 1 < n_loc ? a.lrow[a0 + A + 1] : nblk;
+                    for (int t = t0; t < t1; ++t) {
+                        const int B = a.lblk[2 * (b0 + t)];
+                        const double *hb = &a.h[16 * (int64_t)a.lblk[2 * (b0 + t) + 1] + 4 * o];
+                        const double2 *pb = &vp[4 * B];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            ax = fma(hb[q], pb[q].x, ax);
+                            ay = fma(hb[q], pb[q].y, ay);
+                        }
                     }
                 }
                 const double2 pi_ = vp[i], qi = vq[i];
@@ -641,20 +721,51 @@ __global__ __launch_bounds__(SEED_T) void k_seed_gen(SolveArgs a) {
             }
             snorm2 = wave_reduce(r2);
             wave_lds_fence();
-            // r = S^{-1} s ; rho' = r^T s
+            // r = S^{-1} s ; rho' = r^T s.  Rows lane and lane + 64 share each
+            // read of s (nl is a multiple of 4).
             double r0 = 0.0, r1 = 0.0;
-            for (int i = lane; i < nl; i += SEED_T) {
-                double rx = 0.0, ry = 0.0;
-                const double *srow = &Si[i * ld];
-                for (int jj = 0; jj < nl; ++jj) {
-                    const double2 sj = vs[jj];
-                    rx = fma(srow[jj], sj.x, rx);
-                    ry = fma(srow[jj], sj.y, ry);
+            {
+                const int i0 = lane, i1 = lane + 64;
+                const double *s0 = &Si[(i0 < nl ? i0 : 0) * ld], *s1 = &Si[(i1 < nl ? i1 : 0) * ld];
+                double ax[4] = {0.0, 0.0, 0.0, 0.0}, ay[4] = {0.0, 0.0, 0.0, 0.0};
+                double bx[4] = {0.0, 0.0, 0.0, 0.0}, by[4] = {0.0, 0.0, 0.0, 0.0};
+                if (nl > 64) {
+                    for (int jj = 0; jj < nl; jj += 4) {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const double2 sj = vs[jj + u];
+                            const double a = s0[jj + u], b = s1[jj + u];
+                            ax[u] = fma(a, sj.x, ax[u]);
+                            ay[u] = fma(a, sj.y, ay[u]);
+                            bx[u] = fma(b, sj.x, bx[u]);
+                            by[u] = fma(b, sj.y, by[u]);
+                        }
+                    }
+                } else {
+                    for (int jj = 0; jj < nl; jj += 4) {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const double2 sj = vs[jj + u];
+                            const double a = s0[jj + u];
+                            ax[u] = fma(a, sj.x, ax[u]);
+                            ay[u] = fma(a, sj.y, ay[u]);
+                        }
+                    }
                 }
-                vr[i] = make_double2(rx, ry);
-                const double2 si = vs[i];
-                r0 = fma(rx, si.x, fma(-ry, si.y, r0));
-                r1 = fma(rx, si.y, fma(ry, si.x, r1));
+                if (i0 < nl) {
+                    const double rxs = (ax[0] + ax[1]) + (ax[2] + ax[3]), rys = (ay[0] + ay[1]) + (ay[2] + ay[3]);
+                    vr[i0] = make_double2(rxs, rys);
+                    const double2 si = vs[i0];
+                    r0 = fma(rxs, si.x, fma(-rys, si.y, r0));
+                    r1 = fma(rxs, si.y, fma(rys, si.x, r1));
+                }
+                if (i1 < nl) {
+                    const double rxs = (bx[0] + bx[1]) + (bx[2] + bx[3]), rys = (by[0] + by[1]) + (by[2] + by[3]);
+                    vr[i1] = make_double2(rxs, rys);
+                    const double2 si = vs[i1];
+                    r0 = fma(rxs, si.x, fma(-rys, si.y, r0));
+                    r1 = fma(rxs, si.y, fma(rys, si.x, r1));
+                }
             }
             const double2 rho_new = make_double2(wave_reduce(r0), wave_reduce(r1));
             const double2 ia = crcp(alpha);
@@ -985,14 +1096,22 @@ static KernelFn pick_seed_r1(int M, int bmax) {
     return bmax <= 5 ? pick_seed_r1_m<5>(M) : bmax <= 6 ? pick_seed_r1_m<6>(M) : pick_seed_r1_m<8>(M);
 }
 
-static KernelFn pick_seed_gen(int M) {
+template <int BMAX>
+static KernelFn pick_seed_gen_m(int M) {
     switch (M) {
-        case 1: return k_seed_gen<1>;
-        case 2: return k_seed_gen<2>;
+        case 1: return k_seed_gen<1, BMAX>;
+        case 2: return k_seed_gen<2, BMAX>;
         case 3:
-        case 4: return k_seed_gen<4>;
-        default: return k_seed_gen<8>;
+        case 4: return k_seed_gen<4, BMAX>;
+        default: return k_seed_gen<8, BMAX>;
     }
+}
+
+// BMAX = 0: rows of more than 8 blocks, read from global memory
+static KernelFn pick_seed_gen(int M, int bmax) {
+    return bmax <= 5 ? pick_seed_gen_m<5>(M)
+           : bmax <= 6 ? pick_seed_gen_m<6>(M)
+           : bmax <= 8 ? pick_seed_gen_m<8>(M) : pick_seed_gen_m<0>(M);
 }
 
 template <int MS>
@@ -1196,7 +1315,7 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
     const bool ovl2 = ovl && totals->max_loc_atoms > 16;
     KernelFn seed_fn = mixed ? pick_seed_mx(M, totals->max_row_blocks)
                        : ovl ? pick_seed_ovl(1, M, totals->max_row_blocks)
-                       : gen ? pick_seed_gen(M)
+                       : gen ? pick_seed_gen(M, totals->max_row_blocks)
                              : (r1 ? pick_seed_r1(M, totals->max_row_blocks) : pick_seed(stage, M));
     KernelFn seed_fn2 = ovl2 ? pick_seed_ovl(2, (hs.ns_pad + 127) / 128, totals->max_row_blocks) : nullptr;
     size_t seed_lds = (r1 || mixed || ovl) ? 0 : lds;
