@@ -531,9 +531,12 @@ __global__ __launch_bounds__(SEED_T) void k_seed_gen(SolveArgs a) {
             p0 = a.pa_off[pl];
             npa = (int)(a.pa_off[pl + 1] - p0);
             cl = a.center_loc[pl];
-            bad = n_loc < 1 || n_loc > 32 || n_loc > a.max_loc_atoms || npa < 1 || 4 * npa > a.rmax || cl < 0 || cl >= n_loc ||
-                  a.loc_atom[a0 + cl] != (int32_t)(j >> 2);
+            bad = n_loc < 1 || n_loc > 32 || n_loc > a.max_loc_atoms || npa < 1 || 4 * npa > a.rmax || cl < 0 ||
+                  cl >= n_loc || a.loc_atom[a0 + cl] != (int32_t)(j >> 2);
         }
+        // a launch for one size class leaves the other columns to the other
+        // launch; unsolvable columns are reported by the first
+        if (a.loc_hi > 0 && (bad ? a.loc_lo > 1 : (n_loc < a.loc_lo || n_loc > a.loc_hi))) continue;
         if (bad) {
             if (lane == 0) {
                 *meta = ColMeta{-1, 0, 0, SGF_BADCOLUMN};
@@ -1319,23 +1322,37 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
                              : (r1 ? pick_seed_r1(M, totals->max_row_blocks) : pick_seed(stage, M));
     KernelFn seed_fn2 = ovl2 ? pick_seed_ovl(2, (hs.ns_pad + 127) / 128, totals->max_row_blocks) : nullptr;
     size_t seed_lds = (r1 || mixed || ovl) ? 0 : lds;
-    if (gen && !ovl) {
-        // p, s, w, q, r and the dense inverse of the local overlap
+    // S != I: p, s, w, q, r and the dense inverse of the local overlap, laid
+    // out for subspaces of up to nlx orbitals
+    auto gen_layout = [](SolveArgs &g, int nlx) {
         size_t goff = 0;
         auto gtake = [&](size_t bytes) { size_t r = goff; goff = align_up(goff + bytes, 16); return r; };
-        a.off_p = gtake((size_t)nl * 16);
-        a.off_s = gtake((size_t)nl * 16);
-        a.off_w = gtake((size_t)nl * 16);
-        a.off_q = gtake((size_t)nl * 16);
-        a.off_r = gtake((size_t)nl * 16);
-        a.off_sinv = gtake((size_t)nl * sinv_ld(nl) * 8);
-        seed_lds = goff;
+        g.off_p = gtake((size_t)nlx * 16);
+        g.off_s = gtake((size_t)nlx * 16);
+        g.off_w = gtake((size_t)nlx * 16);
+        g.off_q = gtake((size_t)nlx * 16);
+        g.off_r = gtake((size_t)nlx * 16);
+        g.off_sinv = gtake((size_t)nlx * sinv_ld(nlx) * 8);
+        return goff;
+    };
+    // Subspaces of up to 16 atoms take a launch of their own with the LDS
+    // they need (about twice the wavefronts per compute unit at 21 atoms),
+    // the larger ones a second launch.
+    const bool gen_split = gen && !ovl && !mixed && opts->stage_lds < 0 && totals->max_loc_atoms > 16;
+    SolveArgs a_small{};
+    size_t lds_small = 0;
+    if (gen && !ovl) {
+        seed_lds = gen_layout(a, nl);
         if (seed_lds > 160 * 1024) {
             set_error("sgf_shifted_solve: S != I with a local subspace of %d orbitals needs %zu bytes of LDS "
                       "for the dense local overlap inverse (limit 163840); prune the subspaces or reduce the radius",
                       nl, seed_lds);
             return SGF_EUNSUPPORTED;
         }
+    }
+    if (gen_split) {
+        a.loc_lo = 17;
+        a.loc_hi = totals->max_loc_atoms;
     }
     const int ms = mixed ? 1 : shift_ms(totals->max_proj_atoms, opts->shifts_per_lane);
     KernelFn shift_fn = mixed ? shift_mx_kernel() : pick_shift(totals->max_proj_atoms, ms);
@@ -1370,6 +1387,21 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
         }
         seed_grid_max2 = opts->grid > 0 ? opts->grid : (int64_t)per_cu2 * n_cu;
     }
+    int64_t seed_grid_small = 0;
+    if (gen_split) {
+        a_small = a;
+        lds_small = gen_layout(a_small, 64);
+        a_small.loc_lo = 0;
+        a_small.loc_hi = 16;
+        int per_cu_s = 0;
+        SGF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_s, reinterpret_cast<const void *>(seed_fn),
+                                                             SEED_T, lds_small));
+        if (per_cu_s < 1) {
+            set_error("sgf_shifted_solve: seed kernel does not fit a compute unit (LDS %zu)", lds_small);
+            return SGF_EUNSUPPORTED;
+        }
+        seed_grid_small = opts->grid > 0 ? opts->grid : (int64_t)per_cu_s * n_cu;
+    }
 
     Profile &prof = g_profile;
     const bool timed = opts->profile != 0;
@@ -1387,6 +1419,17 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
             SGF_HIP(prof.add(e1));
             SGF_HIP(prof.add(e2));
             SGF_HIP(hipEventRecord(e0, st));
+        }
+        if (gen_split) {
+            // subspaces of up to 16 atoms first, then the same tickets again
+            // for the larger ones
+            a_small.batch_begin = b0;
+            a_small.batch_end = b1;
+            const int64_t gs = seed_grid_small < b1 - b0 ? seed_grid_small : b1 - b0;
+            hipLaunchKernelGGL(seed_fn, dim3((unsigned)gs), dim3(SEED_T), lds_small, st, a_small);
+            SGF_LAUNCHED();
+            k_zero_ticket<<<1, 64, 0, st>>>(L.ticket);
+            SGF_LAUNCHED();
         }
         hipLaunchKernelGGL(seed_fn, dim3((unsigned)grid), dim3(SEED_T), seed_lds, st, a);
         SGF_LAUNCHED();

@@ -28,6 +28,10 @@ struct SolveArgs {
     const int32_t *loc_atom, *lrow, *lblk, *pa_loc, *center_loc;
     int64_t n_plans;
     int max_loc_atoms, max_loc_blocks, npa_max;
+    // S != I seed pass: with loc_hi > 0 this launch takes only the columns of
+    // loc_lo .. loc_hi local atoms, and only a launch with loc_lo <= 1
+    // reports columns that cannot be solved
+    int loc_lo, loc_hi;
     // columns
     int64_t n_cols;
     const int64_t *cols;

@@ -323,6 +323,22 @@ def test_overlap_workload_sampled(sgf, O):
     compare(sub, ref)
 
 
+def test_overlap_size_classes_bitwise(sgf):
+    """S != I: the seed pass in two launches (subspaces of <= 16 atoms with
+    their own, smaller LDS layout, then the larger ones) gives the same bits
+    as one launch laid out for the largest subspace."""
+    wl = W.config_bundle_overlap(n_columns=4096)
+    s = sgf.system_for(wl)
+    prep = sgf.prepare(s, wl.columns, radius_per_col=wl.radius_per_col)
+    n_loc = np.diff(prep.plan.atom_off.cpu().numpy())[prep.col_plan.cpu().numpy()]
+    assert n_loc.min() <= 16 < n_loc.max()
+    a = sgf.solve_prepared(prep, wl.z, wl.w, tol=wl.tol).numpy()
+    b = sgf.solve_prepared(prep, wl.z, wl.w, tol=wl.tol, stage_lds=0).numpy()
+    for f in ("status", "iters", "G", "rho", "resid"):
+        np.testing.assert_array_equal(getattr(a, f), getattr(b, f))
+    assert np.all(a.status == sgf.CONVERGED)
+
+
 @pytest.mark.skip(reason="the register-tile S != I seed pass did not finish on the GPU (small overlap bundle, "
                          "one wavefront per column); cause not found, so the path is switched off in the library")
 def test_overlap_register_tiles_match_dense_inverse(sgf):
