@@ -94,7 +94,7 @@ def kernel_fingerprint(kind):
     else:
         src = open(os.path.join(CSRC, "scocg.hip")).read()
         head = {"seed": r"template <int M, int BMAX>\n__global__ __launch_bounds__\(SEED_T\) void k_seed_r1",
-                "shift": r"template <int NPA, int MS>\n__global__ __launch_bounds__\(512\) void k_shift"}[kind]
+                "shift": r"template <int NPA, int MS>\n__global__ __launch_bounds__\(512\)[^\n]* void k_shift"}[kind]
         m = re.search(head, src)
         if m is None:
             return None
