@@ -355,6 +355,8 @@ def main(argv=None):
     ap.add_argument("--spmv-only", action="store_true",
                     help="only the operator-apply measurement and a 1 GiB copy (for counter passes)")
     ap.add_argument("--wp-only", action="store_true", help="only the wavepacket-propagation measurement")
+    ap.add_argument("--extra-only", action="store_true",
+                    help="only the overlap and 1,000,300-atom workloads (one timed solve each)")
     args = ap.parse_args(argv)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: every run of this path uses a single MI355X; columns are "
@@ -374,6 +376,10 @@ def main(argv=None):
         return 0
     if args.wp_only:
         print(json.dumps({"wavepacket": wp_stream(sgf, W, dev)}), flush=True)
+        return 0
+    if args.extra_only:
+        extra, _ = extra_workloads(sgf, W, dev, min(args.ws_gib, 64.0), 1)
+        print(json.dumps({"other_workloads": extra}), flush=True)
         return 0
     wl = W.config_bundle()
     ns = wl.z.size
