@@ -217,9 +217,12 @@ typedef struct {
     int32_t max_iter;      /* <= 0: 10 * (local orbitals) per column (mixed precision: 40 *) */
     int32_t seed_index;    /* < 0: n_shifts / 2 */
     int32_t monitor_every; /* mixed: FP64 true residual every K iterations (0: only at the end) */
-    int32_t stage_lds;     /* seed pass: -1 auto (register rows for subspaces of <= 64 orbitals and
+    int32_t stage_lds;     /* seed pass, S = I: -1 auto (register rows for subspaces of <= 64 orbitals and
                               <= 8 blocks per row, else an LDS-staged operator when it fits);
-                              1 LDS-staged operator; 0 operator read from global */
+                              1 LDS-staged operator; 0 operator read from global.
+                              S != I: -1 auto (subspaces of <= 16 atoms in a launch with the dense
+                              overlap inverse, larger ones in a second launch with its packed
+                              triangle); 0 one launch, dense; 1 one launch, packed */
     int32_t grid;          /* seed-pass persistent workgroups; 0: fill the device */
     int32_t profile;       /* 1: record HIP events around each pass (read with sgf_solve_profile) */
     int64_t batch_cols;    /* columns per launch (0: all); the solve also stops at what the workspace holds */

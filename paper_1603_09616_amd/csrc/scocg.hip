@@ -470,10 +470,11 @@ __global__ __launch_bounds__(SEED_T) void k_seed_r1(SolveArgs a) {
 // form [u, v] = u^T S v (A is symmetric in it since H and S are real
 // symmetric): s is the true-space residual, r = S^{-1} s, q = S p and
 // w = (z_s S - H) p = z_s q - H p, so mu = p^T w and rho = r^T s.  The inverse
-// of the local overlap S_L is formed once per column in LDS by in-place
-// Gauss-Jordan elimination (S_L is symmetric positive definite, so no
-// pivoting) and applied as a dense product each iteration, four independent
-// partial sums per row so that the LDS reads overlap.  Lane l owns rows l
+// of the local overlap S_L is formed once per column in LDS, in the packed
+// lower triangle of a symmetric matrix, by the sweep operator (Gauss-Jordan
+// elimination that keeps the matrix symmetric; S_L is positive definite, so
+// no pivoting), and applied as a dense product each iteration, four
+// independent partial sums per row so that the LDS reads overlap.  Lane l owns rows l
 // and l + 64; with BMAX > 0 their blocks of H (at most BMAX per row) and
 // local columns stay in registers for the whole column, with BMAX = 0 (any
 // number of blocks per row) they are read from the local operator in global
@@ -483,8 +484,11 @@ __global__ __launch_bounds__(SEED_T) void k_seed_r1(SolveArgs a) {
 // Row stride (doubles) of the dense local overlap inverse: the smallest
 // 32k + 1 >= nl.  Lane i reading row i then starts on bank pair 2i (mod 64).
 __host__ __device__ inline int sinv_ld(int nl) { return 32 * ((nl + 30) / 32) + 1; }
+// Packed lower triangle of a symmetric nl x nl matrix: entry (i, j), j <= i,
+// at tri(i) + j, tri(i) = i (i + 1) / 2; (j, i) shares it.
+__host__ __device__ inline int tri(int i) { return i * (i + 1) / 2; }
 
-template <int M, int BMAX>
+template <int M, int BMAX, bool PACKED>
 __global__ __launch_bounds__(SEED_T) void k_seed_gen(SolveArgs a) {
     extern __shared__ double4 lds4[];
     char *lds = reinterpret_cast<char *>(lds4);
@@ -493,7 +497,7 @@ __global__ __launch_bounds__(SEED_T) void k_seed_gen(SolveArgs a) {
     double2 *vw = reinterpret_cast<double2 *>(lds + a.off_w);
     double2 *vq = reinterpret_cast<double2 *>(lds + a.off_q);
     double2 *vr = reinterpret_cast<double2 *>(lds + a.off_r);
-    double *Si = reinterpret_cast<double *>(lds + a.off_sinv);  // [nl][ld]
+    double *Si = reinterpret_cast<double *>(lds + a.off_sinv);  // packed lower triangle, tri(nl) doubles
     const int lane = threadIdx.x;
     const double2 zs = a.z[a.seed];
     double2 sigma[M];
@@ -583,69 +587,125 @@ __global__ __launch_bounds__(SEED_T) void k_seed_gen(SolveArgs a) {
             }
             continue;
         }
-        // row stride of the dense inverse: 32k + 1 doubles, so that the lanes
-        // of a wavefront, each on its own row, read consecutive LDS banks
-        const int ld = sinv_ld(nl);
         const int jl = 4 * cl + (int)(j & 3);
         const int nprow = 4 * npa;
         const int prow = lane < nprow ? 4 * a.pa_loc[p0 + (lane >> 2)] + (lane & 3) : 0;
         double2 *hab = a.hab + (size_t)slot * a.cap * 2;
         double2 *hr = a.hr + (size_t)slot * (a.cap + 1) * a.rmax;
 
-        // dense S_L, then its inverse in place
-        for (int e = lane; e < nl * ld; e += SEED_T) Si[e] = 0.0;
-        wave_lds_fence();
-        for (int A = lane; A < n_loc; A += SEED_T) {
-            const int t0 = a.lrow[a0 + A], t1 = A + 1 < n_loc ? a.lrow[a0 + A + 1] : nblk;
-            for (int t = t0; t < t1; ++t) {
-                const int B = a.lblk[2 * (b0 + t)];
-                const double *sb = &a.s[16 * (int64_t)a.lblk[2 * (b0 + t) + 1]];
-                for (int o = 0; o < 4; ++o)
-                    for (int q = 0; q < 4; ++q) Si[(4 * A + o) * ld + 4 * B + q] = sb[4 * o + q];
+        if constexpr (!PACKED) {
+            // row stride of the dense inverse: 32k + 1 doubles, so that the lanes
+            // of a wavefront, each on its own row, read consecutive LDS banks
+            const int ld = sinv_ld(nl);
+            // dense S_L, then its inverse in place
+            for (int e = lane; e < nl * ld; e += SEED_T) Si[e] = 0.0;
+            wave_lds_fence();
+            for (int A = lane; A < n_loc; A += SEED_T) {
+                const int t0 = a.lrow[a0 + A], t1 = A + 1 < n_loc ? a.lrow[a0 + A + 1] : nblk;
+                for (int t = t0; t < t1; ++t) {
+                    const int B = a.lblk[2 * (b0 + t)];
+                    const double *sb = &a.s[16 * (int64_t)a.lblk[2 * (b0 + t) + 1]];
+                    for (int o = 0; o < 4; ++o)
+                        for (int q = 0; q < 4; ++q) Si[(4 * A + o) * ld + 4 * B + q] = sb[4 * o + q];
+                }
             }
-        }
-        wave_lds_fence();
-        for (int kk = 0; kk < nl; ++kk) {
-            const double piv = 1.0 / Si[kk * ld + kk];
             wave_lds_fence();
-            for (int jj = lane; jj < nl; jj += SEED_T) Si[kk * ld + jj] = (jj == kk) ? piv : Si[kk * ld + jj] * piv;
-            wave_lds_fence();
-            // rows lane and lane + 64 (not the pivot row): a_ij -= a_ik a_kj for
-            // every j, then a_ik = -a_ik piv; the two rows share each read of
-            // the pivot row (nl is a multiple of 4)
-            {
-                const double *pr = &Si[kk * ld];
-                const int i0 = lane, i1 = lane + 64;
-                const bool e0 = i0 < nl && i0 != kk, e1 = i1 < nl && i1 != kk;
-                double *w0 = &Si[(e0 ? i0 : kk) * ld], *w1 = &Si[(e1 ? i1 : kk) * ld];
-                const double f0 = e0 ? w0[kk] : 0.0, f1 = e1 ? w1[kk] : 0.0;
-                if (nl > 64) {
-                    if (e0 || e1) {
-                        for (int jj = 0; jj < nl; jj += 4) {
+            for (int kk = 0; kk < nl; ++kk) {
+                const double piv = 1.0 / Si[kk * ld + kk];
+                wave_lds_fence();
+                for (int jj = lane; jj < nl; jj += SEED_T) Si[kk * ld + jj] = (jj == kk) ? piv : Si[kk * ld + jj] * piv;
+                wave_lds_fence();
+                // rows lane and lane + 64 (not the pivot row): a_ij -= a_ik a_kj for
+                // every j, then a_ik = -a_ik piv; the two rows share each read of
+                // the pivot row (nl is a multiple of 4)
+                {
+                    const double *pr = &Si[kk * ld];
+                    const int i0 = lane, i1 = lane + 64;
+                    const bool e0 = i0 < nl && i0 != kk, e1 = i1 < nl && i1 != kk;
+                    double *w0 = &Si[(e0 ? i0 : kk) * ld], *w1 = &Si[(e1 ? i1 : kk) * ld];
+                    const double f0 = e0 ? w0[kk] : 0.0, f1 = e1 ? w1[kk] : 0.0;
+                    if (nl > 64) {
+                        if (e0 || e1) {
+                            for (int jj = 0; jj < nl; jj += 4) {
 #pragma unroll
-                            for (int u = 0; u < 4; ++u) {
-                                const double pv = pr[jj + u];
-                                if (e0) w0[jj + u] = fma(-f0, pv, w0[jj + u]);
-                                if (e1) w1[jj + u] = fma(-f1, pv, w1[jj + u]);
+                                for (int u = 0; u < 4; ++u) {
+                                    const double pv = pr[jj + u];
+                                    if (e0) w0[jj + u] = fma(-f0, pv, w0[jj + u]);
+                                    if (e1) w1[jj + u] = fma(-f1, pv, w1[jj + u]);
+                                }
                             }
                         }
-                    }
-                } else if (e0) {
-                    for (int jj = 0; jj < nl; jj += 4) {
+                    } else if (e0) {
+                        for (int jj = 0; jj < nl; jj += 4) {
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) w0[jj + u] = fma(-f0, pr[jj + u], w0[jj + u]);
+                            for (int u = 0; u < 4; ++u) w0[jj + u] = fma(-f0, pr[jj + u], w0[jj + u]);
+                        }
                     }
+                    if (e0) w0[kk] = -f0 * piv;
+                    if (e1) w1[kk] = -f1 * piv;
                 }
-                if (e0) w0[kk] = -f0 * piv;
-                if (e1) w1[kk] = -f1 * piv;
+                wave_lds_fence();
+            }
+        } else {
+            // S_L packed, then the sweep in place
+            for (int e = lane; e < tri(nl); e += SEED_T) Si[e] = 0.0;
+            wave_lds_fence();
+            for (int A = lane; A < n_loc; A += SEED_T) {
+                const int t0 = a.lrow[a0 + A], t1 = A + 1 < n_loc ? a.lrow[a0 + A + 1] : nblk;
+                for (int t = t0; t < t1; ++t) {
+                    const int B = a.lblk[2 * (b0 + t)];
+                    if (B > A) continue;  // the upper blocks mirror the lower ones
+                    const double *sb = &a.s[16 * (int64_t)a.lblk[2 * (b0 + t) + 1]];
+                    for (int o = 0; o < 4; ++o)
+                        for (int q = 0; q < 4; ++q)
+                            if (4 * B + q <= 4 * A + o) Si[tri(4 * A + o) + 4 * B + q] = sb[4 * o + q];
+                }
             }
             wave_lds_fence();
+            // Sweep on pivot k, v = column k, d = v_k: a_ij -= v_i v_j / d for
+            // i, j != k, a_ik = v_i / d for i != k, a_kk = -1 / d.  After the last
+            // pivot the triangle holds -S_L^{-1}.  v lives in vw, which is free
+            // until the iteration starts.
+            {
+                double *v = reinterpret_cast<double *>(vw);
+                const int i0 = lane, i1 = lane + 64;
+                double *row0 = &Si[tri(i0 < nl ? i0 : 0)], *row1 = &Si[tri(i1 < nl ? i1 : 0)];
+                for (int kk = 0; kk < nl; ++kk) {
+                    for (int i = lane; i < nl; i += SEED_T) v[i] = i >= kk ? Si[tri(i) + kk] : Si[tri(kk) + i];
+                    wave_lds_fence();
+                    const double id = 1.0 / v[kk];
+                    const bool g0 = i0 < nl && i0 != kk, g1 = i1 < nl && i1 != kk;
+                    const double c0 = g0 ? v[i0] * id : 0.0, c1 = g1 ? v[i1] * id : 0.0;
+                    // both rows of the lane in one pass over the columns of the longer
+                    const int len = g1 ? i1 + 1 : (g0 ? i0 + 1 : 0);
+                    for (int jj = 0; jj < len; ++jj) {
+                        const double vj = v[jj];
+                        if (g0 && jj <= i0) row0[jj] = fma(-c0, vj, row0[jj]);
+                        if (g1) row1[jj] = fma(-c1, vj, row1[jj]);
+                    }
+                    if (g0 && kk <= i0) row0[kk] = c0;
+                    if (g1 && kk <= i1) row1[kk] = c1;
+                    // the pivot row
+                    if (i0 == kk || i1 == kk) {
+                        double *rk = i0 == kk ? row0 : row1;
+                        for (int jj = 0; jj < kk; ++jj) rk[jj] = v[jj] * id;
+                        rk[kk] = -id;
+                    }
+                    wave_lds_fence();
+                }
+            }
+
         }
 
         // start: s_0 = q_0 = e_jl, r_0 = p_0 = S^{-1} e_jl, rho_0 = r_0^T s_0
         for (int i = lane; i < nl; i += SEED_T) {
             const double2 sv = make_double2(i == jl ? 1.0 : 0.0, 0.0);
-            const double2 rv = make_double2(Si[i * ld + jl], 0.0);
+            double rvx;
+            if constexpr (PACKED)
+                rvx = -(i >= jl ? Si[tri(i) + jl] : Si[tri(jl) + i]);
+            else
+                rvx = Si[i * sinv_ld(nl) + jl];
+            const double2 rv = make_double2(rvx, 0.0);
             vs[i] = sv;
             vq[i] = sv;
             vr[i] = rv;
@@ -665,7 +725,7 @@ __global__ __launch_bounds__(SEED_T) void k_seed_gen(SolveArgs a) {
             nkm[m] = 0;
             res[m] = 1.0;
         }
-        double2 rho = make_double2(Si[jl * ld + jl], 0.0);
+        double2 rho = make_double2(PACKED ? -Si[tri(jl) + jl] : Si[jl * sinv_ld(nl) + jl], 0.0);
         double2 alpha_old = make_double2(1.0, 0.0), beta_old = zero;
         int status = SGF_MAXITER, iters = 0, applied = 0;
         double snorm2 = 1.0;
@@ -725,34 +785,79 @@ __global__ __launch_bounds__(SEED_T) void k_seed_gen(SolveArgs a) {
             snorm2 = wave_reduce(r2);
             wave_lds_fence();
             // r = S^{-1} s ; rho' = r^T s.  Rows lane and lane + 64 share each
-            // read of s (nl is a multiple of 4).
+            // read of s (nl is a multiple of 4).  Dense inverse: row i is
+            // contiguous.  Packed triangle A = -S^{-1}: row i reads its own
+            // entries (j <= i), then column i of the rows below it, and the
+            // sums are negated.
             double r0 = 0.0, r1 = 0.0;
             {
                 const int i0 = lane, i1 = lane + 64;
-                const double *s0 = &Si[(i0 < nl ? i0 : 0) * ld], *s1 = &Si[(i1 < nl ? i1 : 0) * ld];
                 double ax[4] = {0.0, 0.0, 0.0, 0.0}, ay[4] = {0.0, 0.0, 0.0, 0.0};
                 double bx[4] = {0.0, 0.0, 0.0, 0.0}, by[4] = {0.0, 0.0, 0.0, 0.0};
-                if (nl > 64) {
-                    for (int jj = 0; jj < nl; jj += 4) {
+                if constexpr (!PACKED) {
+                    const int ld = sinv_ld(nl);
+                    const double *s0 = &Si[(i0 < nl ? i0 : 0) * ld], *s1 = &Si[(i1 < nl ? i1 : 0) * ld];
+                    if (nl > 64) {
+                        for (int jj = 0; jj < nl; jj += 4) {
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const double2 sj = vs[jj + u];
-                            const double a = s0[jj + u], b = s1[jj + u];
-                            ax[u] = fma(a, sj.x, ax[u]);
-                            ay[u] = fma(a, sj.y, ay[u]);
-                            bx[u] = fma(b, sj.x, bx[u]);
-                            by[u] = fma(b, sj.y, by[u]);
+                            for (int u = 0; u < 4; ++u) {
+                                const double2 sj = vs[jj + u];
+                                const double a = s0[jj + u], b = s1[jj + u];
+                                ax[u] = fma(a, sj.x, ax[u]);
+                                ay[u] = fma(a, sj.y, ay[u]);
+                                bx[u] = fma(b, sj.x, bx[u]);
+                                by[u] = fma(b, sj.y, by[u]);
+                            }
+                        }
+                    } else {
+                        for (int jj = 0; jj < nl; jj += 4) {
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                const double2 sj = vs[jj + u];
+                                const double a = s0[jj + u];
+                                ax[u] = fma(a, sj.x, ax[u]);
+                                ay[u] = fma(a, sj.y, ay[u]);
+                            }
                         }
                     }
                 } else {
-                    for (int jj = 0; jj < nl; jj += 4) {
+                    const int c0 = i0 < nl ? i0 : nl - 1, c1 = i1 < nl ? i1 : nl - 1;  // rows read (clamped)
+                    const int b0t = tri(c0), b1t = tri(c1);
+                    int tj = 0;  // tri(jj)
+                    if (nl > 64) {
+                        for (int jj = 0; jj < nl; jj += 4) {
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const double2 sj = vs[jj + u];
-                            const double a = s0[jj + u];
-                            ax[u] = fma(a, sj.x, ax[u]);
-                            ay[u] = fma(a, sj.y, ay[u]);
+                            for (int u = 0; u < 4; ++u) {
+                                const int jn = jj + u;
+                                const double2 sj = vs[jn];
+                                const double av = Si[jn <= c0 ? b0t + jn : tj + c0];
+                                const double bv = Si[jn <= c1 ? b1t + jn : tj + c1];
+                                tj += jn + 1;
+                                ax[u] = fma(av, sj.x, ax[u]);
+                                ay[u] = fma(av, sj.y, ay[u]);
+                                bx[u] = fma(bv, sj.x, bx[u]);
+                                by[u] = fma(bv, sj.y, by[u]);
+                            }
                         }
+                    } else {
+                        for (int jj = 0; jj < nl; jj += 4) {
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                const int jn = jj + u;
+                                const double2 sj = vs[jn];
+                                const double av = Si[jn <= c0 ? b0t + jn : tj + c0];
+                                tj += jn + 1;
+                                ax[u] = fma(av, sj.x, ax[u]);
+                                ay[u] = fma(av, sj.y, ay[u]);
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        ax[u] = -ax[u];
+                        ay[u] = -ay[u];
+                        bx[u] = -bx[u];
+                        by[u] = -by[u];
                     }
                 }
                 if (i0 < nl) {
@@ -1099,22 +1204,27 @@ static KernelFn pick_seed_r1(int M, int bmax) {
     return bmax <= 5 ? pick_seed_r1_m<5>(M) : bmax <= 6 ? pick_seed_r1_m<6>(M) : pick_seed_r1_m<8>(M);
 }
 
-template <int BMAX>
+template <int BMAX, bool PACKED>
 static KernelFn pick_seed_gen_m(int M) {
     switch (M) {
-        case 1: return k_seed_gen<1, BMAX>;
-        case 2: return k_seed_gen<2, BMAX>;
+        case 1: return k_seed_gen<1, BMAX, PACKED>;
+        case 2: return k_seed_gen<2, BMAX, PACKED>;
         case 3:
-        case 4: return k_seed_gen<4, BMAX>;
-        default: return k_seed_gen<8, BMAX>;
+        case 4: return k_seed_gen<4, BMAX, PACKED>;
+        default: return k_seed_gen<8, BMAX, PACKED>;
     }
 }
 
+template <bool PACKED>
+static KernelFn pick_seed_gen_p(int M, int bmax) {
+    return bmax <= 5   ? pick_seed_gen_m<5, PACKED>(M)
+           : bmax <= 6 ? pick_seed_gen_m<6, PACKED>(M)
+           : bmax <= 8 ? pick_seed_gen_m<8, PACKED>(M) : pick_seed_gen_m<0, PACKED>(M);
+}
+
 // BMAX = 0: rows of more than 8 blocks, read from global memory
-static KernelFn pick_seed_gen(int M, int bmax) {
-    return bmax <= 5 ? pick_seed_gen_m<5>(M)
-           : bmax <= 6 ? pick_seed_gen_m<6>(M)
-           : bmax <= 8 ? pick_seed_gen_m<8>(M) : pick_seed_gen_m<0>(M);
+static KernelFn pick_seed_gen(int M, int bmax, bool packed) {
+    return packed ? pick_seed_gen_p<true>(M, bmax) : pick_seed_gen_p<false>(M, bmax);
 }
 
 template <int MS>
@@ -1316,15 +1426,22 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
     const bool ovl = kRegisterTileOverlapSeed && gen && !mixed && opts->stage_lds < 0 &&
                      totals->max_loc_atoms <= 22 && totals->max_row_blocks <= 8 && hs.ns_pad <= 256;
     const bool ovl2 = ovl && totals->max_loc_atoms > 16;
+    // S != I, dense-LDS variant.  stage_lds < 0: subspaces of up to 16 atoms
+    // in a launch of their own with the dense inverse, the larger ones in a
+    // second launch with the packed triangle (half the LDS, so twice the
+    // wavefronts per compute unit).  stage_lds = 0: one launch, dense;
+    // stage_lds = 1: one launch, packed.
+    const bool gen_split = gen && !ovl && !mixed && opts->stage_lds < 0 && totals->max_loc_atoms > 16;
+    const bool gen_packed = gen_split || (gen && opts->stage_lds == 1);
     KernelFn seed_fn = mixed ? pick_seed_mx(M, totals->max_row_blocks)
                        : ovl ? pick_seed_ovl(1, M, totals->max_row_blocks)
-                       : gen ? pick_seed_gen(M, totals->max_row_blocks)
+                       : gen ? pick_seed_gen(M, totals->max_row_blocks, gen_packed)
                              : (r1 ? pick_seed_r1(M, totals->max_row_blocks) : pick_seed(stage, M));
     KernelFn seed_fn2 = ovl2 ? pick_seed_ovl(2, (hs.ns_pad + 127) / 128, totals->max_row_blocks) : nullptr;
     size_t seed_lds = (r1 || mixed || ovl) ? 0 : lds;
     // S != I: p, s, w, q, r and the dense inverse of the local overlap, laid
     // out for subspaces of up to nlx orbitals
-    auto gen_layout = [](SolveArgs &g, int nlx) {
+    auto gen_layout = [](SolveArgs &g, int nlx, bool packed) {
         size_t goff = 0;
         auto gtake = [&](size_t bytes) { size_t r = goff; goff = align_up(goff + bytes, 16); return r; };
         g.off_p = gtake((size_t)nlx * 16);
@@ -1332,17 +1449,15 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
         g.off_w = gtake((size_t)nlx * 16);
         g.off_q = gtake((size_t)nlx * 16);
         g.off_r = gtake((size_t)nlx * 16);
-        g.off_sinv = gtake((size_t)nlx * sinv_ld(nlx) * 8);
+        g.off_sinv = gtake(packed ? (size_t)tri(nlx) * 8 : (size_t)nlx * sinv_ld(nlx) * 8);
         return goff;
     };
-    // Subspaces of up to 16 atoms take a launch of their own with the LDS
-    // they need (about twice the wavefronts per compute unit at 21 atoms),
-    // the larger ones a second launch.
-    const bool gen_split = gen && !ovl && !mixed && opts->stage_lds < 0 && totals->max_loc_atoms > 16;
+    // the launch for subspaces of up to 16 atoms (gen_split)
     SolveArgs a_small{};
+    KernelFn seed_fn_small = gen_split ? pick_seed_gen(M, totals->max_row_blocks, false) : nullptr;
     size_t lds_small = 0;
     if (gen && !ovl) {
-        seed_lds = gen_layout(a, nl);
+        seed_lds = gen_layout(a, nl, gen_packed);
         if (seed_lds > 160 * 1024) {
             set_error("sgf_shifted_solve: S != I with a local subspace of %d orbitals needs %zu bytes of LDS "
                       "for the dense local overlap inverse (limit 163840); prune the subspaces or reduce the radius",
@@ -1390,11 +1505,13 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
     int64_t seed_grid_small = 0;
     if (gen_split) {
         a_small = a;
-        lds_small = gen_layout(a_small, 64);
+        lds_small = gen_layout(a_small, 64, false);
         a_small.loc_lo = 0;
         a_small.loc_hi = 16;
         int per_cu_s = 0;
-        SGF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_s, reinterpret_cast<const void *>(seed_fn),
+        SGF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(seed_fn_small),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_small));
+        SGF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_s, reinterpret_cast<const void *>(seed_fn_small),
                                                              SEED_T, lds_small));
         if (per_cu_s < 1) {
             set_error("sgf_shifted_solve: seed kernel does not fit a compute unit (LDS %zu)", lds_small);
@@ -1426,7 +1543,7 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
             a_small.batch_begin = b0;
             a_small.batch_end = b1;
             const int64_t gs = seed_grid_small < b1 - b0 ? seed_grid_small : b1 - b0;
-            hipLaunchKernelGGL(seed_fn, dim3((unsigned)gs), dim3(SEED_T), lds_small, st, a_small);
+            hipLaunchKernelGGL(seed_fn_small, dim3((unsigned)gs), dim3(SEED_T), lds_small, st, a_small);
             SGF_LAUNCHED();
             k_zero_ticket<<<1, 64, 0, st>>>(L.ticket);
             SGF_LAUNCHED();
