@@ -13,8 +13,8 @@ Contents:
 * ``mlp.py``: FP64 reference of the iteration-count network.
 * ``wp.py``: wavepacket time propagation (exact by eigen-decomposition, and
   the Chebyshev series), Gershgorin bounds.
-* ``forces.py``: band-structure forces -dE_band/dR at fixed rho (Slater-Koster
-  block gradient).
+* ``forces.py``: band-structure forces at fixed rho (Slater-Koster block
+  gradient) and, with an overlap, the energy-density matrix and its term.
 """
 from __future__ import annotations
 
