@@ -238,6 +238,8 @@ def extra_workloads(sgf, W, dev, ws_gib, check_n):
                      "iters_mean": float(res.iters.float().mean()), "max_loc_atoms": int(t.max_loc_atoms)}
         log(f"[bench] {name}: {wl.columns.size} columns x {ns} shifts in {ms:.1f} ms "
             f"({conv / (ms * 1e-3):.3g} solves/s, {prof[2]} launches)")
+        if wl.tb.overlap:
+            out[name]["after_rho"] = overlap_forces(sgf, prep, res, wl)
         pick = np.sort(np.random.default_rng(1603).choice(wl.columns.size, check_n, replace=False))
         off = prep.proj_off.cpu().numpy()
         rows = np.concatenate([np.arange(off[c], off[c + 1]) for c in pick])
@@ -247,6 +249,44 @@ def extra_workloads(sgf, W, dev, ws_gib, check_n):
         del res, buf, prep, s
         torch.cuda.empty_cache()
     return out, keep
+
+
+def overlap_forces(sgf, prep, res, wl, reps=3):
+    """After an S != I solve that kept G: the energy-density matrix
+    eps = -(1/pi) sum_k Im(w_k z_k G(z_k)) on every projection row (one HBM
+    pass over G), the band forces with its term, and the whole-solve
+    identity tr(eps S) = tr(rho H) (from the traces of rho and of eps)."""
+    import dataclasses
+    import torch
+
+    def timed(fn):
+        ts, r = [], None
+        for i in range(reps + 1):
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            r = fn()
+            e1.record()
+            torch.cuda.synchronize()
+            if i:
+                ts.append(e0.elapsed_time(e1))
+        return r, float(np.median(ts))
+
+    n_rows, ns = int(prep.n_rows), int(res.G.shape[1])
+    eps, e_ms = timed(lambda: sgf.energy_density(res, wl.z, wl.w))
+    F, f_ms = timed(lambda: sgf.band_forces(prep, res, wl.tb, eps=eps))
+    alg = n_rows * ns * 16 + n_rows * 8
+    _, _, (_, rho_h) = sgf.traces(prep, dataclasses.replace(res, G=None))
+    _, _, (eps_s, _) = sgf.traces(prep, dataclasses.replace(res, G=None, rho=eps))
+    Fh = F.cpu().numpy()
+    log(f"[bench] energy density {e_ms:.2f} ms ({alg / (e_ms * 1e-3) / 1e12:.2f} TB/s), forces {f_ms:.2f} ms, "
+        f"tr(eps S) - tr(rho H) = {eps_s - rho_h:.2e}")
+    return {"energy_density": {"ms": e_ms, "alg_bytes": alg, "GBps": alg / (e_ms * 1e-3) / 1e9,
+                               "frac_of_8TBps": alg / (e_ms * 1e-3) / 8e12},
+            "band_forces": {"ms": f_ms, "rows_per_s": n_rows / (f_ms * 1e-3),
+                            "max_abs_eV_per_nm": float(np.abs(Fh).max()),
+                            "sum_over_atoms_max": float(np.abs(Fh.sum(axis=0)).max())},
+            "tr_eps_S": eps_s, "tr_rho_H_eV": rho_h, "identity_gap": eps_s - rho_h, "reps": reps}
 
 
 def check_extra(keep):

@@ -462,6 +462,19 @@ sgf_status sgf_occupation(int32_t n_shifts, const double *T, const double *U, co
 sgf_status sgf_fermi_level(int32_t n_shifts, const double *z, const double *T, const double *U, double n_target,
                            double *mu, double *n_e, double *e_band);
 
+/* The energy-density matrix on the projection rows of a solve, the
+ * quadrature of rho with the weight w_k z_k (the term of the forces that an
+ * overlap adds, Sec. 2):
+ *   d_eps[t] = -(1/pi) sum_k Im(w_k z_k G_t(z_k)),  t < total_rows.
+ * For real weights, (z S - H) G = I gives sum_{i in P(j)} eps_ij S_ji =
+ * sum_{i in P(j)} rho_ij H_ji for every column.  d_z, d_w: device complex
+ * [n_shifts] (interleaved re, im; the solve's shifts and weights); d_G:
+ * complex [total_rows][n_shifts] as sgf_shifted_solve wrote it.  Sums in a
+ * fixed order (bitwise repeatable).  SGF_EUNSUPPORTED above 512 shifts.
+ * Asynchronous on the stream. */
+sgf_status sgf_energy_density(int64_t total_rows, int32_t n_shifts, const double *d_z, const double *d_w,
+                              const double *d_G, double *d_eps, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Wavepacket propagation                                                     */
 /* ------------------------------------------------------------------------ */
@@ -508,23 +521,31 @@ sgf_status sgf_wp_propagate(const sgf_system *sys, int32_t n_rhs, double *d_psi,
 /* Band-structure forces                                                      */
 /* ------------------------------------------------------------------------ */
 
-/* The force step of the quantum molecular dynamics (Sec. 2): with S = I,
- * F_A = -dE_band/dR_A at fixed rho, where E_band = sum_j sum_{i in P(j)}
- * rho_ij H_ij over the solved columns (per spin; the tr(rho H) of
- * sgf_traces).  Each term acts on both atoms of its block: with i on atom B
- * and j on atom C (B != C), g = rho_ij d h_{o_i q_j}/dd at d = R_C - R_B
- * (the Slater-Koster block of sgf_build_hamiltonian with parameters p)
- * enters F_C with a minus sign and F_B with a plus sign, so the forces sum
- * to zero.  With all columns solved this is the Hellmann-Feynman band force;
- * the repulsive and van der Waals terms are not included.
+/* The force step of the quantum molecular dynamics (Sec. 2).  E_band =
+ * sum_j sum_{i in P(j)} rho_ij H_ij over the solved columns (per spin; the
+ * tr(rho H) of sgf_traces).  With S = I the force is F_A = -dE_band/dR_A
+ * at fixed rho.  With an overlap S, Hellmann-Feynman for H c = lambda S c
+ * adds the energy-density matrix (sgf_energy_density):
+ *   F_A = -sum_j sum_{i in P(j)} (rho_ij dH_ij/dR_A - eps_ij dS_ij/dR_A).
+ * Each term acts on both atoms of its block: with i on atom B and j on atom
+ * C (B != C), g = rho_ij d h_{o_i q_j}/dd - eps_ij d s_{o_i q_j}/dd at
+ * d = R_C - R_B (the Slater-Koster block h and the overlap block s =
+ * s_amp exp(-(r - r0)/s_decay) I4 of sgf_build_hamiltonian with parameters
+ * p) enters F_C with a minus sign and F_B with a plus sign, so the forces sum
+ * to zero.  A row whose atom lies farther than p->r_cut from the column's
+ * atom has no block and adds nothing.  With all columns solved this is the
+ * Hellmann-Feynman band force; the repulsive and van der Waals terms are not
+ * included.
  * d_xyz: positions (nm, [n_atoms][3]); d_cols, d_proj_off, d_proj_row and
- * d_rho: the columns and projected density matrix of a solve.  Writes
- * d_force [n_atoms][3] (eV/nm), cleared first.  FP64 atomics add the terms,
- * in no fixed order: repeated runs agree to rounding.  SGF_EUNSUPPORTED
- * when the system has an overlap S.  Asynchronous on the stream. */
+ * d_rho: the columns and projected density matrix of a solve; d_eps: the
+ * energy-density matrix on the same rows, required when the system has an
+ * overlap and ignored (may be NULL) when it has none.  p->overlap must match
+ * the system.  Writes d_force [n_atoms][3] (eV/nm), cleared first.  FP64
+ * atomics add the terms, in no fixed order: repeated runs agree to
+ * rounding.  Asynchronous on the stream. */
 sgf_status sgf_band_forces(const sgf_system *sys, const double *d_xyz, const sgf_tb_params *p, int64_t n_cols,
                            const int64_t *d_cols, const int64_t *d_proj_off, const int32_t *d_proj_row,
-                           const double *d_rho, double *d_force, void *stream);
+                           const double *d_rho, const double *d_eps, double *d_force, void *stream);
 
 #ifdef __cplusplus
 }

@@ -28,7 +28,7 @@ EXPORTED = (
     "sgf_mlp_forward", "sgf_mlp_train_step", "sgf_mlp_gradient", "sgf_order_workspace", "sgf_order_by_prediction",
     "sgf_bsr_apply", "sgf_solve_stage_shifts", "sgf_trace_workspace", "sgf_traces", "sgf_occupation",
     "sgf_fermi_level", "sgf_wp_workspace", "sgf_wp_bounds", "sgf_wp_terms", "sgf_wp_propagate",
-    "sgf_band_forces",
+    "sgf_band_forces", "sgf_energy_density",
 )
 MLP_NFEAT, MLP_NPARAM, MLP_BATCH = 5, 4619, 128
 
@@ -115,7 +115,8 @@ def lib():
             "sgf_wp_bounds": [P, P, szt, P, P, P],
             "sgf_wp_terms": [dbl, dbl, P],
             "sgf_wp_propagate": [P, i32, P, dbl, i32, dbl, dbl, i32, P, szt, P],
-            "sgf_band_forces": [P, P, P, i64, P, P, P, P, P, P],
+            "sgf_band_forces": [P, P, P, i64, P, P, P, P, P, P, P],
+            "sgf_energy_density": [i64, i32, P, P, P, P, P],
         }
         for name, args in sigs.items():
             f = getattr(L, name)
@@ -739,11 +740,12 @@ def wp_propagate(system: System, psi, h_fs: float, n_steps: int, e_min: float, e
 
 # --- band-structure forces ---------------------------------------------------------
 
-def band_forces(prep: Prepared, res: Result, params, xyz=None, stream=None):
-    """F = -dE_band/dR at fixed rho (S = I), E_band over the solved columns:
-    float64 [n_atoms, 3] on the device (eV/nm).  params: the tight-binding
-    parameters the system was built with; xyz: positions [n_atoms, 3] (nm;
-    the system's own when omitted)."""
+def band_forces(prep: Prepared, res: Result, params, xyz=None, eps=None, stream=None):
+    """Band forces at fixed rho (and, with an overlap, fixed energy-density
+    matrix ``eps``, one value per projection row, e.g. from
+    energy_density): float64 [n_atoms, 3] on the device (eV/nm).  params:
+    the tight-binding parameters the system was built with; xyz: positions
+    [n_atoms, 3] (nm; the system's own when omitted)."""
     torch = _torch()
     dev = prep.cols.device
     d_xyz = _dev(prep.system.xyz if xyz is None else xyz, torch.float64, dev)
@@ -751,5 +753,22 @@ def band_forces(prep: Prepared, res: Result, params, xyz=None, stream=None):
     sc = prep.system.c()
     tb = _tb_c(params)
     _call("sgf_band_forces", ctypes.byref(sc), _ptr(d_xyz), ctypes.byref(tb), int(prep.cols.numel()), _ptr(prep.cols),
-          _ptr(prep.proj_off), _ptr(prep.proj_row), _ptr(res.rho), _ptr(F), _stream(stream))
+          _ptr(prep.proj_off), _ptr(prep.proj_row), _ptr(res.rho), _ptr(eps), _ptr(F), _stream(stream))
     return F
+
+
+def energy_density(res: Result, z, w, stream=None):
+    """eps_t = -(1/pi) sum_k Im(w_k z_k G_t(z_k)) on every projection row of
+    a solve that kept G: float64 [rows] on the device."""
+    torch = _torch()
+    if res.G is None:
+        raise ValueError("energy_density: the solve did not keep G")
+    dev = res.G.device
+    rows, ns = int(res.G.shape[0]), int(res.G.shape[1])
+    d_z = _dev(np.asarray(z, np.complex128), torch.complex128, dev)
+    d_w = _dev(np.asarray(w, np.complex128), torch.complex128, dev)
+    if d_z.numel() != ns or d_w.numel() != ns:
+        raise ValueError(f"energy_density: {d_z.numel()} shifts and {d_w.numel()} weights for G with {ns}")
+    eps = torch.empty(max(rows, 1), dtype=torch.float64, device=dev)
+    _call("sgf_energy_density", rows, ns, _ptr(d_z), _ptr(d_w), _ptr(res.G), _ptr(eps), _stream(stream))
+    return eps[:rows]

@@ -1,14 +1,20 @@
 // forces.hip -- band-structure forces from the density matrix (the force
 // step of the quantum molecular dynamics, Sec. 2 of the paper).
 //
-// Orthogonal basis (S = I).  The band energy of the solved columns is
-// E_band = sum_j sum_{i in P(j)} rho_ij H_ij (per spin), and the force is
-// F_A = -dE_band/dR_A at fixed rho.  Each column's rho comes from its own
-// local subspace, so rho is not symmetric and both atoms of a block take
-// part: H_ij for orbital i on atom B and j on atom C (B != C) is element
-// (o_i, q_j) of the Slater-Koster block h(d), d = R_C - R_B, and the term
-// g = rho_ij grad h_{o_i q_j}(d) enters F_C with a minus sign and F_B with a
-// plus sign.  On-site blocks do not depend on positions.
+// The band energy of the solved columns is E_band = sum_j sum_{i in P(j)}
+// rho_ij H_ij (per spin).  With an orthogonal basis (S = I) the force is
+// F_A = -dE_band/dR_A at fixed rho.  With an overlap S, Hellmann-Feynman
+// for H c = lambda S c adds the energy-density matrix eps (the quadrature of
+// rho with the weight w_k z_k):
+//   F_A = -sum_j sum_{i in P(j)} (rho_ij dH_ij/dR_A - eps_ij dS_ij/dR_A).
+// Each column's rho and eps come from its own local subspace, so they are
+// not symmetric and both atoms of a block take part: H_ij and S_ij for
+// orbital i on atom B and j on atom C (B != C) are element (o_i, q_j) of the
+// Slater-Koster block h(d) and of the overlap block s(d) = s_amp
+// exp(-(r - r0)/s_decay) I4, d = R_C - R_B, and the term
+// g = rho_ij grad h_{o_i q_j}(d) - eps_ij grad s_{o_i q_j}(d) enters F_C with
+// a minus sign and F_B with a plus sign.  On-site blocks do not depend on
+// positions, and a pair farther apart than r_cut has no block.
 //
 // One thread per column walks its projection rows, sums the terms of each
 // neighbour atom (its rows are consecutive) and adds them, and the total of
@@ -66,7 +72,8 @@ __global__ __launch_bounds__(FORCE_T) void k_zero_f64(int64_t n, double *x) {
 
 __global__ __launch_bounds__(FORCE_T) void k_band_force(int64_t n_cols, int64_t n_atoms, const double *xyz,
                                                         sgf_tb_params p, const int64_t *cols, const int64_t *proj_off,
-                                                        const int32_t *proj_row, const double *rho, double *F) {
+                                                        const int32_t *proj_row, const double *rho, const double *eps,
+                                                        double *F) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_cols) return;
     const int64_t j = cols[c];
@@ -80,18 +87,31 @@ __global__ __launch_bounds__(FORCE_T) void k_band_force(int64_t n_cols, int64_t 
         const int32_t i = proj_row[t];
         const int64_t B = i >> 2;
         if (B == C || B < 0 || B >= n_atoms) continue;
+        const double d0 = rc0 - xyz[3 * B], d1 = rc1 - xyz[3 * B + 1], d2 = rc2 - xyz[3 * B + 2];
+        const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+        if (r2 > p.r_cut * p.r_cut) continue;  // no block beyond the cut
         if (B != cur) {
             if (cur >= 0) add3(F, cur, nb, 1.0);
             cur = B;
             nb[0] = nb[1] = nb[2] = 0.0;
         }
         double g[3];
-        sk_elem_grad(p, rc0 - xyz[3 * B], rc1 - xyz[3 * B + 1], rc2 - xyz[3 * B + 2], i & 3, q, g);
+        sk_elem_grad(p, d0, d1, d2, i & 3, q, g);
         const double w = rho[t];
 #pragma unroll
+        for (int k = 0; k < 3; ++k) g[k] *= w;
+        if (eps && (i & 3) == q) {
+            // -eps grad s: grad s = -s(r) d / (s_decay r) on the diagonal of the block
+            const double r = sqrt(r2);
+            const double e = eps[t] * p.s_amp * exp(-(r - p.r0) / p.s_decay) / (p.s_decay * r);
+            g[0] = fma(e, d0, g[0]);
+            g[1] = fma(e, d1, g[1]);
+            g[2] = fma(e, d2, g[2]);
+        }
+#pragma unroll
         for (int k = 0; k < 3; ++k) {
-            nb[k] = fma(w, g[k], nb[k]);
-            own[k] = fma(w, g[k], own[k]);
+            nb[k] += g[k];
+            own[k] += g[k];
         }
     }
     if (cur >= 0) add3(F, cur, nb, 1.0);
@@ -106,16 +126,15 @@ using namespace sgf;
 
 extern "C" sgf_status sgf_band_forces(const sgf_system *sys, const double *d_xyz, const sgf_tb_params *p,
                                       int64_t n_cols, const int64_t *d_cols, const int64_t *d_proj_off,
-                                      const int32_t *d_proj_row, const double *d_rho, double *d_force,
-                                      void *stream) {
+                                      const int32_t *d_proj_row, const double *d_rho, const double *d_eps,
+                                      double *d_force, void *stream) {
     SGF_REQUIRE(sys && d_xyz && p && d_force, "sgf_band_forces: NULL argument");
     SGF_REQUIRE(sys->n_atoms > 0 && n_cols >= 0, "sgf_band_forces: bad sizes");
     SGF_REQUIRE(n_cols == 0 || (d_cols && d_proj_off && d_proj_row && d_rho), "sgf_band_forces: column layout is NULL");
-    SGF_REQUIRE(p->r0 > 0.0, "sgf_band_forces: r0 must be positive");
-    if (sys->s) {
-        set_error("sgf_band_forces: forces are built for an orthogonal basis (S = I)");
-        return SGF_EUNSUPPORTED;
-    }
+    SGF_REQUIRE(p->r0 > 0.0 && p->r_cut > 0.0, "sgf_band_forces: r0 and r_cut must be positive");
+    SGF_REQUIRE(!sys->s == !p->overlap, "sgf_band_forces: the parameters' overlap flag does not match the system");
+    SGF_REQUIRE(!sys->s || p->s_decay > 0.0, "sgf_band_forces: s_decay must be positive");
+    SGF_REQUIRE(!sys->s || n_cols == 0 || d_eps, "sgf_band_forces: an overlap needs the energy-density matrix");
     hipStream_t st = as_stream(stream);
     const int64_t nf = 3 * sys->n_atoms;
     const unsigned gz = (unsigned)((nf + FORCE_T - 1) / FORCE_T < 65536 ? (nf + FORCE_T - 1) / FORCE_T : 65536);
@@ -123,7 +142,8 @@ extern "C" sgf_status sgf_band_forces(const sgf_system *sys, const double *d_xyz
     SGF_LAUNCHED();
     if (n_cols > 0) {
         k_band_force<<<(unsigned)((n_cols + FORCE_T - 1) / FORCE_T), FORCE_T, 0, st>>>(
-            n_cols, sys->n_atoms, d_xyz, *p, d_cols, d_proj_off, d_proj_row, d_rho, d_force);
+            n_cols, sys->n_atoms, d_xyz, *p, d_cols, d_proj_off, d_proj_row, d_rho, sys->s ? d_eps : nullptr,
+            d_force);
         SGF_LAUNCHED();
     }
     return SGF_OK;

@@ -1,6 +1,6 @@
 // trace.hip -- traces of the projected Green's function over the solved
 // columns, and what follows from them after rho in an order-N energy step:
-// electron count, band energy and the Fermi level.
+// electron count, band energy, the Fermi level and the energy-density matrix.
 //
 // Row j of the restricted equations (z S_L - H_L) x = e_j couples j only to
 // orbitals that share a stored block with it, and those are the projection
@@ -13,6 +13,13 @@
 //   E_band = -(1/pi) sum_k Im(w_k U_k) = tr(rho H)
 // over the solved columns.  The same row gives z_k T_k - U_k = (number of
 // columns) up to the solve's residuals, which the tests use as a pin.
+//
+// The energy-density matrix, which the forces need when S != I, is the same
+// quadrature as rho with the weight w_k z_k:
+//   eps_ij = -(1/pi) sum_k Im(w_k z_k G_ij(z_k)),
+// one value per projection row.  Because (z S - H) G = I, it satisfies
+// sum_{i in P(j)} eps_ij S_ji = sum_{i in P(j)} rho_ij H_ji per column for
+// real weights.
 #include "common.hpp"
 
 namespace sgf {
@@ -54,6 +61,40 @@ __global__ void k_trace_coef(int64_t n_cols, int64_t n_orb, const int64_t *cols,
             }
             coef[r] = make_double2(sv, hv);
         }
+    }
+}
+
+constexpr int ED_T = 256;   // threads per workgroup of the energy-density pass
+constexpr int ED_MAXK = 8;  // shifts per lane (512 / 64)
+constexpr int ED_NB = 8192; // workgroups (grid-stride over rows)
+
+// eps_t = -(1/pi) sum_k Im(w_k z_k G_t(z_k)): one wavefront per projection
+// row (grid-stride), lane l reading shifts l, l + 64, ... of the row, so each
+// load of a wavefront is 1 KiB of contiguous G.  The weights w_k z_k of a
+// lane's shifts stay in registers.  Fixed summation order.
+__global__ __launch_bounds__(ED_T) void k_energy_density(int64_t n_rows, int32_t ns, const double2 *z,
+                                                         const double2 *w, const double2 *G, double *eps) {
+    const int lane = threadIdx.x & 63;
+    double2 c[ED_MAXK];
+#pragma unroll
+    for (int u = 0; u < ED_MAXK; ++u) {
+        const int k = lane + 64 * u;
+        c[u] = k < ns ? cmul(w[k], z[k]) : make_double2(0.0, 0.0);
+    }
+    const int64_t nw = ((int64_t)gridDim.x * ED_T) >> 6;
+    for (int64_t r = ((int64_t)blockIdx.x * ED_T + threadIdx.x) >> 6; r < n_rows; r += nw) {
+        const double2 *g = G + r * ns;
+        double2 v[ED_MAXK];
+#pragma unroll
+        for (int u = 0; u < ED_MAXK; ++u) {
+            const int k = lane + 64 * u;
+            v[u] = (64 * u < ns && k < ns) ? g[k] : make_double2(0.0, 0.0);
+        }
+        double t = 0.0;
+#pragma unroll
+        for (int u = 0; u < ED_MAXK; ++u) t = fma(c[u].x, v[u].y, fma(c[u].y, v[u].x, t));
+        t = wave_reduce(t);
+        if (lane == 0) eps[r] = -t * INV_PI_D;
     }
 }
 
@@ -281,5 +322,22 @@ extern "C" sgf_status sgf_fermi_level(int32_t n_shifts, const double *z, const d
     }
     *mu = z[2 * lo];
     *n_e = count(lo, e_band);
+    return SGF_OK;
+}
+
+extern "C" sgf_status sgf_energy_density(int64_t total_rows, int32_t n_shifts, const double *d_z, const double *d_w,
+                                         const double *d_G, double *d_eps, void *stream) {
+    SGF_REQUIRE(total_rows >= 0 && n_shifts >= 1, "sgf_energy_density: bad sizes");
+    if (n_shifts > 64 * ED_MAXK) {
+        set_error("sgf_energy_density: %d shifts (limit %d)", n_shifts, 64 * ED_MAXK);
+        return SGF_EUNSUPPORTED;
+    }
+    if (total_rows == 0) return SGF_OK;
+    SGF_REQUIRE(d_z && d_w && d_G && d_eps, "sgf_energy_density: NULL argument");
+    const int64_t wgs = (total_rows + ED_T / 64 - 1) / (ED_T / 64);
+    k_energy_density<<<(unsigned)(wgs < ED_NB ? wgs : ED_NB), ED_T, 0, as_stream(stream)>>>(
+        total_rows, n_shifts, reinterpret_cast<const double2 *>(d_z), reinterpret_cast<const double2 *>(d_w),
+        reinterpret_cast<const double2 *>(d_G), d_eps);
+    SGF_LAUNCHED();
     return SGF_OK;
 }

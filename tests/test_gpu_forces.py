@@ -1,9 +1,12 @@
-"""GPU tests of the band forces F = -dE_band/dR at fixed rho (S = I).
+"""GPU tests of the band forces F = -dE_band/dR at fixed rho (S = I) and,
+with an overlap, of the energy-density matrix and its term in the forces.
 
-Bar: the forces sum rho-weighted block gradients, so the GPU and oracle
-forces differ by the rho difference of the two solves (<= 1e-10 relative
-per column) propagated through those sums: 1e-9 relative to the largest
-force.  At full size, an atom's force depends only on its own columns and
+Bar: the forces sum rho- (and eps-) weighted block gradients, so the GPU and
+oracle forces differ by the rho and eps differences of the two solves
+(<= 1e-10 relative per column) propagated through those sums: 1e-9 relative
+to the largest force.  The energy-density matrix is compared per column,
+1e-9 relative to the column's largest entry; from the GPU's own G it must
+match the oracle's quadrature to rounding (1e-13).  At full size, an atom's force depends only on its own columns and
 those of the atoms sharing a block with it, so the oracle solves just those
 for a few sampled atoms.
 """
@@ -76,10 +79,97 @@ def test_forces_full_bundle_sampled(sgf, O):
     torch.cuda.empty_cache()
 
 
-def test_forces_need_an_orthogonal_basis(sgf):
+def overlap_case(sgf):
     wl = W.bundle_workload(2, 1, 14, overlap=True, config_no=120)
+    cols = np.arange(wl.n_orb)
     s = sgf.system_for(wl)
-    prep = sgf.prepare(s, wl.columns[:8], radius=1.0)
+    prep = sgf.prepare(s, cols, radius=1.0, prune=True)
     res = sgf.solve_prepared(prep, wl.z, wl.w, tol=1e-12)
+    return wl, cols, prep, res
+
+
+def col_rel(a, b, off):
+    return max(np.abs(a[off[c]:off[c + 1]] - b[off[c]:off[c + 1]]).max() / np.abs(b[off[c]:off[c + 1]]).max()
+               for c in range(off.size - 1))
+
+
+def test_energy_density_vs_oracle_small(sgf, O):
+    O, fo = O
+    wl, cols, prep, res = overlap_case(sgf)
+    eps = sgf.energy_density(res, wl.z, wl.w)
+    eps2 = sgf.energy_density(res, wl.z, wl.w)
+    got = res.numpy()
+    e, e2 = eps.cpu().numpy(), eps2.cpu().numpy()
+    np.testing.assert_array_equal(e, e2)  # fixed summation order
+    own = fo.energy_density(got, wl.z, wl.w)  # the oracle's quadrature of the GPU's G
+    ref = O.shifted_solve(O.system_for(wl), wl.xyz, cols, wl.z, wl.w, tol=1e-12, radius=1.0, prune=True, threads=8)
+    eref = fo.energy_density(ref, wl.z, wl.w)
+    off = got.proj_off
+    np.testing.assert_array_equal(off, ref.proj_ptr)
+    np.testing.assert_array_equal(got.proj_row, ref.proj_row)
+    r_own, r_ref = col_rel(e, own, off), col_rel(e, eref, off)
+    print(f"  eps vs own G {r_own:.2e}, vs oracle solve {r_ref:.2e}", flush=True)
+    assert r_own < 1e-13 and r_ref < 1e-9
+    # sum_{i in P(j)} eps_ij S_ji = sum_{i in P(j)} rho_ij H_ji (real weights)
+    b = O.system_for(wl)
+    H, S = b.dense("h"), b.dense("s")
+    for c, j in enumerate(cols):
+        rows = got.proj_row[off[c]:off[c + 1]]
+        assert abs(e[off[c]:off[c + 1]] @ S[j, rows] - got.rho[off[c]:off[c + 1]] @ H[j, rows]) < 1e-10
+
+
+def test_overlap_forces_vs_oracle_small(sgf, O):
+    O, fo = O
+    wl, cols, prep, res = overlap_case(sgf)
+    eps = sgf.energy_density(res, wl.z, wl.w)
+    F = sgf.band_forces(prep, res, wl.tb, eps=eps).cpu().numpy()
+    ref = O.shifted_solve(O.system_for(wl), wl.xyz, cols, wl.z, wl.w, tol=1e-12, radius=1.0, prune=True, threads=8)
+    Fr = fo.band_forces(wl.xyz, wl.tb, ref, cols, wl.n_atoms, eps=fo.energy_density(ref, wl.z, wl.w))
+    F0 = fo.band_forces(wl.xyz, wl.tb, ref, cols, wl.n_atoms, eps=np.zeros(ref.rho.size))
+    err = np.abs(F - Fr).max() / np.abs(Fr).max()
+    print(f"  max |F| {np.abs(Fr).max():.3f} eV/nm, eps term {np.abs(Fr - F0).max():.3f}, rel err {err:.2e}")
+    assert err < 1e-9
+    assert np.abs(Fr - F0).max() > 1e-3 * np.abs(Fr).max()  # the eps term is there
+    assert np.abs(F.sum(axis=0)).max() <= 1e-12 * np.abs(F).sum()
+
+
+def test_overlap_forces_argument_errors(sgf):
+    import dataclasses
+    wl, cols, prep, res = overlap_case(sgf)
     with pytest.raises(sgf.SgfError):
-        sgf.band_forces(prep, res, wl.tb)
+        sgf.band_forces(prep, res, wl.tb)  # no eps with an overlap
+    eps = sgf.energy_density(res, wl.z, wl.w)
+    with pytest.raises(sgf.SgfError):
+        sgf.band_forces(prep, res, dataclasses.replace(wl.tb, overlap=0), eps=eps)  # flag does not match
+    with pytest.raises(ValueError):
+        sgf.energy_density(res, wl.z[:-1], wl.w[:-1])
+
+
+def test_overlap_forces_full_bundle_sampled(sgf, O):
+    """The overlap bundle (118,300 atoms, per-column radius U[0.6, 1.4] nm,
+    256 shifts): eps from the kept G, forces with the eps term; three
+    sampled atoms against the oracle, which solves only their own and their
+    neighbours' columns."""
+    import torch
+    O, fo = O
+    wl = W.config_bundle_overlap()
+    s = sgf.system_for(wl)
+    prep = sgf.prepare(s, wl.columns, radius_per_col=wl.radius_per_col)
+    res = sgf.solve_prepared(prep, wl.z, wl.w, tol=wl.tol)
+    eps = sgf.energy_density(res, wl.z, wl.w)
+    F = sgf.band_forces(prep, res, wl.tb, eps=eps).cpu().numpy()
+    st = res.status.cpu().numpy()
+    scale = np.abs(F).max()
+    print(f"  {wl.n_atoms} atoms: max |F| {scale:.3f} eV/nm, |sum F| {np.abs(F.sum(0)).max():.2e}", flush=True)
+    assert np.all(st == sgf.CONVERGED)
+    assert np.abs(F.sum(axis=0)).max() <= 1e-11 * np.abs(F).sum()
+    b = O.system_for(wl)
+    for A in np.random.default_rng(12).choice(wl.n_atoms, 3, replace=False):
+        nbr = b.col[b.row_ptr[A]:b.row_ptr[A + 1]]
+        cols = (4 * nbr[:, None] + np.arange(4)[None, :]).ravel().astype(np.int64)
+        ref = O.solve_workload(wl, bsr=b, cols=cols, threads=8)
+        Fr = fo.band_forces(wl.xyz, wl.tb, ref, cols, wl.n_atoms, eps=fo.energy_density(ref, wl.z, wl.w))[A]
+        print(f"  atom {A}: {F[A]} vs {Fr}", flush=True)
+        assert np.abs(F[A] - Fr).max() <= 1e-9 * scale
+    del res, eps
+    torch.cuda.empty_cache()
