@@ -512,7 +512,8 @@ sgf_status sgf_wp_terms(double a_tau, double tol, int32_t *n_terms);
  * spectrum (sgf_wp_bounds); n_terms >= 3 (sgf_wp_terms).  Per term one
  * pass over H in HBM fused with the recurrence and the accumulation of the
  * series; d_ws (sgf_wp_workspace bytes) holds the two other Chebyshev
- * vectors.  SGF_EUNSUPPORTED when the system has an overlap S.
+ * vectors.  sys->h, d_psi and d_ws must be 16-byte aligned (SGF_EINVAL
+ * otherwise).  SGF_EUNSUPPORTED when the system has an overlap S.
  * Asynchronous on the stream. */
 sgf_status sgf_wp_propagate(const sgf_system *sys, int32_t n_rhs, double *d_psi, double h_fs, int32_t n_steps,
                             double e_min, double e_max, int32_t n_terms, void *d_ws, size_t ws_bytes, void *stream);

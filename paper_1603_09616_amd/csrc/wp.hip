@@ -8,10 +8,13 @@
 // and T_k(X) Psi from T_{k+1} = 2 X T_k - T_{k-1}.
 //
 // Each term is one pass over H in HBM fused with the recurrence and the
-// accumulation of the series: thread (orbital row i, packet r), packets
-// fastest, forms entry (i, r) of H T_k (the n_rhs threads of a row share its
-// loads of H through the cache, and every vector access is contiguous
-// across the wavefront), then
+// accumulation of the series.  One packet: thread per orbital row i forms
+// entry i of H T_k.  Several packets: thread per (atom A, packet r), packets
+// fastest, forms the four entries of A's rows for packet r from whole 4 x 4
+// blocks, so a block of H and a neighbour's four entries of T_k are each
+// read once per thread (the n_rhs threads of an atom share the block's loads
+// through the cache; a thread per orbital row read every entry of T_k four
+// times over).  Then
 // T_{k+1} = (2/a)(H T_k - b T_k) - T_{k-1} and acc += c_{k+1} T_{k+1}.
 // T_{k+1} overwrites T_{k-1} in place (only this thread reads that entry),
 // and the last term writes the finished step, acc + c_{K-1} T_{K-1}, there
@@ -80,6 +83,61 @@ __global__ __launch_bounds__(WP_T) void k_cheb_term(int64_t n_atoms, const int32
     }
 }
 
+// The same term with a thread per (atom, packet): the four rows of atom A
+// for packet r.  Each row sums its products in the order of the row
+// variant, so both give the same bits.
+template <int NRHS, int MODE>
+__global__ __launch_bounds__(WP_T) void k_cheb_term_atom(int64_t n_atoms, const int32_t *__restrict__ row_ptr,
+                                                         const int32_t *__restrict__ col,
+                                                         const double *__restrict__ h, double scale, double shift,
+                                                         double2 c_new, double2 c_0, const double2 *__restrict__ x,
+                                                         double2 *__restrict__ z, double2 *__restrict__ acc) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t A = gid / NRHS;
+    const int r = (int)(gid % NRHS);
+    if (A >= n_atoms) return;
+    double hx[4] = {0.0, 0.0, 0.0, 0.0}, hy[4] = {0.0, 0.0, 0.0, 0.0};
+    const int t0 = row_ptr[A], t1 = row_ptr[A + 1];
+    for (int t = t0; t < t1; ++t) {
+        const int64_t B = col[t];
+        const double2 *hb = reinterpret_cast<const double2 *>(h + 16 * (int64_t)t);
+        double2 hv[8];  // row o of the block: hv[2 o] = (h_o0, h_o1), hv[2 o + 1] = (h_o2, h_o3)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) hv[k] = hb[k];
+        const double2 *xb = x + 4 * B * NRHS + r;
+        double2 v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = xb[q * NRHS];
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            const double hr[4] = {hv[2 * o].x, hv[2 * o].y, hv[2 * o + 1].x, hv[2 * o + 1].y};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                hx[o] = fma(hr[q], v[q].x, hx[o]);
+                hy[o] = fma(hr[q], v[q].y, hy[o]);
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+        const int64_t e = (4 * A + o) * NRHS + r;
+        const double2 xi = x[e];
+        double2 tn = make_double2(scale * fma(-shift, xi.x, hx[o]), scale * fma(-shift, xi.y, hy[o]));
+        if (MODE != TERM_FIRST) tn = csub(tn, z[e]);
+        double2 s;
+        if (MODE == TERM_FIRST)
+            s = cfma(c_0, xi, cmul(c_new, tn));
+        else
+            s = cfma(c_new, tn, acc[e]);
+        if (MODE == TERM_LAST) {
+            z[e] = s;
+        } else {
+            z[e] = tn;
+            acc[e] = s;
+        }
+    }
+}
+
 // Gershgorin discs per orbital row: per-workgroup min of H_ii - R_i and max
 // of H_ii + R_i, R_i = sum_{j != i} |H_ij|.
 __global__ __launch_bounds__(WP_T) void k_gershgorin(int64_t n_atoms, const int32_t *__restrict__ row_ptr,
@@ -118,13 +176,16 @@ __global__ __launch_bounds__(WP_T) void k_gershgorin(int64_t n_atoms, const int3
 }
 
 template <int MODE>
-void launch_term(int n_rhs, dim3 grid, hipStream_t st, const sgf_system *sys, double scale, double shift,
-                 double2 c_new, double2 c_0, const double2 *x, double2 *z, double2 *acc) {
+void launch_term(int n_rhs, hipStream_t st, const sgf_system *sys, double scale, double shift, double2 c_new,
+                 double2 c_0, const double2 *x, double2 *z, double2 *acc) {
+    const int64_t n = sys->n_atoms;
+    const dim3 rows((unsigned)((4 * n + WP_T - 1) / WP_T));
+    const dim3 atoms((unsigned)((n * n_rhs + WP_T - 1) / WP_T));
     switch (n_rhs) {
-        case 1: k_cheb_term<1, MODE><<<grid, WP_T, 0, st>>>(sys->n_atoms, sys->row_ptr, sys->col, sys->h, scale, shift, c_new, c_0, x, z, acc); break;
-        case 2: k_cheb_term<2, MODE><<<grid, WP_T, 0, st>>>(sys->n_atoms, sys->row_ptr, sys->col, sys->h, scale, shift, c_new, c_0, x, z, acc); break;
-        case 4: k_cheb_term<4, MODE><<<grid, WP_T, 0, st>>>(sys->n_atoms, sys->row_ptr, sys->col, sys->h, scale, shift, c_new, c_0, x, z, acc); break;
-        default: k_cheb_term<8, MODE><<<grid, WP_T, 0, st>>>(sys->n_atoms, sys->row_ptr, sys->col, sys->h, scale, shift, c_new, c_0, x, z, acc); break;
+        case 1: k_cheb_term<1, MODE><<<rows, WP_T, 0, st>>>(n, sys->row_ptr, sys->col, sys->h, scale, shift, c_new, c_0, x, z, acc); break;
+        case 2: k_cheb_term_atom<2, MODE><<<atoms, WP_T, 0, st>>>(n, sys->row_ptr, sys->col, sys->h, scale, shift, c_new, c_0, x, z, acc); break;
+        case 4: k_cheb_term_atom<4, MODE><<<atoms, WP_T, 0, st>>>(n, sys->row_ptr, sys->col, sys->h, scale, shift, c_new, c_0, x, z, acc); break;
+        default: k_cheb_term_atom<8, MODE><<<atoms, WP_T, 0, st>>>(n, sys->row_ptr, sys->col, sys->h, scale, shift, c_new, c_0, x, z, acc); break;
     }
 }
 
@@ -199,6 +260,8 @@ extern "C" sgf_status sgf_wp_propagate(const sgf_system *sys, int32_t n_rhs, dou
         return SGF_EUNSUPPORTED;
     }
     SGF_REQUIRE(n_rhs == 1 || n_rhs == 2 || n_rhs == 4 || n_rhs == 8, "sgf_wp_propagate: n_rhs must be 1, 2, 4 or 8");
+    SGF_REQUIRE(((uintptr_t)sys->h & 15) == 0 && ((uintptr_t)d_psi & 15) == 0 && ((uintptr_t)d_ws & 15) == 0,
+                "sgf_wp_propagate: h, psi and the workspace must be 16-byte aligned");
     SGF_REQUIRE(n_steps >= 0 && n_terms >= 3 && n_terms <= 100000, "sgf_wp_propagate: need n_steps >= 0, n_terms >= 3");
     SGF_REQUIRE(std::isfinite(h_fs) && std::isfinite(e_min) && std::isfinite(e_max) && e_max > e_min,
                 "sgf_wp_propagate: need finite h and e_max > e_min");
@@ -226,22 +289,21 @@ extern "C" sgf_status sgf_wp_propagate(const sgf_system *sys, int32_t n_rhs, dou
     const size_t vec = align_up((size_t)4 * sys->n_atoms * n_rhs * 16);
     double2 *bufs[3] = {reinterpret_cast<double2 *>(d_psi), static_cast<double2 *>(d_ws),
                         reinterpret_cast<double2 *>(static_cast<char *>(d_ws) + vec)};
-    const dim3 grid((unsigned)((4 * sys->n_atoms * n_rhs + WP_T - 1) / WP_T));
     hipStream_t st = as_stream(stream);
     int cur = 0;  // buffer holding Psi at the start of the step
     for (int step = 0; step < n_steps; ++step) {
         const int acc = (cur + 2) % 3;
         int x = cur, z = (cur + 1) % 3;
         // T_1 into z, c_0 T_0 + c_1 T_1 into acc
-        launch_term<TERM_FIRST>(n_rhs, grid, st, sys, 1.0 / a, b, c[1], c[0], bufs[x], bufs[z], bufs[acc]);
+        launch_term<TERM_FIRST>(n_rhs, st, sys, 1.0 / a, b, c[1], c[0], bufs[x], bufs[z], bufs[acc]);
         SGF_LAUNCHED();
         // x = T_1, z = T_0: T_{k+1} replaces T_{k-1}
         int xx = z, zz = x;
         for (int k = 2; k < n_terms; ++k) {
             if (k + 1 < n_terms)
-                launch_term<TERM_MID>(n_rhs, grid, st, sys, 2.0 / a, b, c[k], c[0], bufs[xx], bufs[zz], bufs[acc]);
+                launch_term<TERM_MID>(n_rhs, st, sys, 2.0 / a, b, c[k], c[0], bufs[xx], bufs[zz], bufs[acc]);
             else
-                launch_term<TERM_LAST>(n_rhs, grid, st, sys, 2.0 / a, b, c[k], c[0], bufs[xx], bufs[zz], bufs[acc]);
+                launch_term<TERM_LAST>(n_rhs, st, sys, 2.0 / a, b, c[k], c[0], bufs[xx], bufs[zz], bufs[acc]);
             SGF_LAUNCHED();
             const int t = xx;
             xx = zz;
