@@ -196,7 +196,7 @@ def wp_stream(sgf, W, dev, steps=10):
                             "norm_drift": float(np.abs(norm - 1).max())}
         log(f"[bench] wavepacket x{k}: {ms:.2f} ms per 0.1 fs step ({K} terms), {nbytes / ms / 1e6:.0f} GB/s")
         del psi, psi0
-    return {"kernel": "k_cheb_term", "workload": "wavepacket steps of 0.1 fs on the 1,000,300-atom bundle share "
+    return {"kernel": "k_cheb_term (1 packet), k_cheb_term_atom (8 packets)", "workload": "wavepacket steps of 0.1 fs on the 1,000,300-atom bundle share "
             f"({s.n_atoms} block rows, {s.nnzb} 4x4 blocks), Gershgorin bounds [{lo:.2f}, {hi:.2f}] eV",
             "peak_GBps": PEAK_HBM_GBS, "steps": steps, "cases": cases}
 
