@@ -239,6 +239,11 @@ typedef struct {
                               k) exceeds g_tol max_k |G_jj(z_k)| gets SGF_DRIFT; 0: 5e-7 */
     int64_t queue_len;     /* > 0: take only d_order[0 .. queue_len) from the work queue (the other
                               columns' outputs are left untouched); 0: every column */
+    double *eps_out;       /* NULL, or device double [projection rows] (the layout of d_rho): the
+                              shift pass also writes the energy-density matrix
+                              eps_t = -(1/pi) sum_k Im(w_k z_k G_t(z_k)) that the forces need when
+                              S != I (sgf_band_forces), without G being kept.  Needs w; FP64 path
+                              only (precision 1 returns SGF_EUNSUPPORTED) */
 } sgf_solve_opts;
 
 /* Output offsets: d_proj_off[c+1] - d_proj_off[c] = 4 * |P(plan of column c)|

@@ -68,7 +68,7 @@ class SolveOptsC(ctypes.Structure):
     _fields_ = [("precision", i32), ("tol", dbl), ("max_iter", i32), ("seed_index", i32), ("monitor_every", i32),
                 ("stage_lds", i32), ("grid", i32), ("profile", i32), ("batch_cols", i64),
                 ("shifts_per_lane", i32), ("shifts_staged", i32), ("drift_tol", dbl), ("g_tol", dbl),
-                ("queue_len", i64)]
+                ("queue_len", i64), ("eps_out", P)]
 
 
 _lib = None
@@ -385,8 +385,11 @@ def _cplx_host(a) -> Optional[np.ndarray]:
 def solve_prepared(prep: Prepared, z, w=None, tol=1e-10, precision="fp64", max_iter=0, seed_index=-1,
                    g_out=True, order=None, batch_cols=0, stage_lds=-1, grid=0, monitor_every=50, out=None,
                    profile=False, shift_iters=False, shifts_per_lane=0, drift_tol=0.0, g_tol=0.0, queue_len=0,
-                   fallback=True, fallback_tol=1e-9, shifts_staged=False, stream=None) -> Result:
+                   fallback=True, fallback_tol=1e-9, shifts_staged=False, eps_out=False, stream=None) -> Result:
     """Shifted COCG on every prepared column (asynchronous on the stream).
+
+    eps_out: also form the energy-density matrix on the projection rows in
+    the shift pass (``Result.eps``; FP64 only, needs w).
 
     precision "mixed" builds the FP32 shadow of H first if the system has
     none; with ``fallback`` the columns the mixed path does not accept
@@ -419,6 +422,10 @@ def solve_prepared(prep: Prepared, z, w=None, tol=1e-10, precision="fp64", max_i
             "resid": torch.empty((max(n, 1), ns), dtype=torch.float64, device=dev),
             "nk": torch.empty((max(n, 1), ns), dtype=torch.int32, device=dev) if shift_iters else None,
         }
+    if eps_out and out.get("eps") is None:
+        out["eps"] = torch.empty(max(prep.n_rows, 1), dtype=torch.float64, device=dev)
+    if eps_out:
+        opts.eps_out = _ptr(out["eps"])
     d_order = None if order is None else _dev(order, torch.int32, dev)
     out["order"] = d_order
     _call("sgf_shifted_solve", ctypes.byref(sc), ctypes.byref(pc), ctypes.byref(prep.plan.totals), n,
@@ -445,6 +452,7 @@ def solve_prepared(prep: Prepared, z, w=None, tol=1e-10, precision="fp64", max_i
                  out["resid"][:n])
     res.n_fallback = n_fallback
     res.shift_iters = None if out.get("nk") is None else out["nk"][:n]
+    res.eps = out["eps"][:prep.n_rows] if eps_out else None
     res._out = out  # keep buffers alive with the result
     return res
 

@@ -1122,6 +1122,31 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MS == 1 && 
         for (int v = 0; v < nwv; ++v) acc += rpart[r * 8 + v];
         a.rho[out0 + r] = -acc * INV_PI;
     }
+    if (a.eps) {  // uniform: the energy-density matrix, eps_i = -(1/pi) sum_k Im(w_k z_k G_i(z_k))
+#pragma unroll
+        for (int u = 0; u < MS; ++u)
+            if (kof[u] >= 0) wk[u] = cmul(wk[u], a.z[kof[u]]);
+        __syncthreads();  // rpart is reused
+#pragma unroll
+        for (int r = 0; r < 4 * NPA; ++r) {
+            if (r >= nrow) continue;  // uniform
+            double t = 0.0;
+#pragma unroll
+            for (int u = 0; u < MS; ++u) {
+                if (kof[u] < 0) continue;
+                const double2 Gr = nk[u] > 0 ? cmul(y0[u], S[u][r]) : zero;
+                t = fma(wk[u].x, Gr.y, fma(wk[u].y, Gr.x, t));
+            }
+            t = wave_reduce(t);
+            if (lane == 0) rpart[r * 8 + wv] = t;
+        }
+        __syncthreads();
+        for (int r = tid; r < nrow; r += T) {
+            double acc = 0.0;
+            for (int v = 0; v < nwv; ++v) acc += rpart[r * 8 + v];
+            a.eps[out0 + r] = -acc * INV_PI;
+        }
+    }
 }
 
 __global__ void k_zero_ticket(int64_t *t) {
@@ -1287,6 +1312,11 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
     SGF_REQUIRE(z, "sgf_shifted_solve: z is NULL");
     SGF_REQUIRE(opts->tol > 0, "sgf_shifted_solve: tol must be positive");
     SGF_REQUIRE(opts->precision == 0 || opts->precision == 1, "sgf_shifted_solve: precision must be 0 or 1");
+    if (opts->eps_out && opts->precision != 0) {
+        set_error("sgf_shifted_solve: the energy-density output is formed by the FP64 shift pass only");
+        return SGF_EUNSUPPORTED;
+    }
+    SGF_REQUIRE(!opts->eps_out || w, "sgf_shifted_solve: the energy-density output needs the weights w");
     SGF_REQUIRE(opts->max_iter >= 0, "sgf_shifted_solve: max_iter must be >= 0");
     const int seed = opts->seed_index < 0 ? n_shifts / 2 : opts->seed_index;
     SGF_REQUIRE(seed < n_shifts, "sgf_shifted_solve: seed_index %d >= n_shifts %d", seed, n_shifts);
@@ -1378,6 +1408,7 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
     a.proj_off = d_proj_off;
     a.G = d_G;
     a.rho = d_rho;
+    a.eps = opts->eps_out;
     a.resid = d_resid;
     a.iters = d_iters;
     a.status = d_status;

@@ -49,6 +49,7 @@ struct SolveArgs {
     // outputs
     const int64_t *proj_off;
     double *G, *rho, *resid;
+    double *eps;        // energy-density matrix on the projection rows (nullable)
     int32_t *iters, *status, *shift_iters;
     // history (per batch slot)
     int cap;            // recorded iterations per slot (max_iter of the batch)

@@ -56,7 +56,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(sgf.SystemC) == 9 * 8
     assert ctypes.sizeof(sgf.PlanC) == 12 * 8
     assert ctypes.sizeof(sgf.PlanTotalsC) == 3 * 8 + 4 * 4
-    assert ctypes.sizeof(sgf.SolveOptsC) == 80
+    assert ctypes.sizeof(sgf.SolveOptsC) == 88
 
 
 def test_product_path_has_no_oracle_dependency():

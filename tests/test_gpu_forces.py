@@ -133,6 +133,30 @@ def test_overlap_forces_vs_oracle_small(sgf, O):
     assert np.abs(F.sum(axis=0)).max() <= 1e-12 * np.abs(F).sum()
 
 
+def test_energy_density_from_the_shift_pass(sgf, O):
+    """The shift pass's eps output (no G needed) against the stream over the
+    kept G (same quadrature, other summation order: 1e-13) and the oracle;
+    the forces from it without G match those from the stream."""
+    O, fo = O
+    wl, cols, prep, res = overlap_case(sgf)
+    eps_g = sgf.energy_density(res, wl.z, wl.w).cpu().numpy()
+    r2 = sgf.solve_prepared(prep, wl.z, wl.w, tol=1e-12, g_out=False, eps_out=True)
+    e2 = r2.eps.cpu().numpy()
+    np.testing.assert_array_equal(r2.rho.cpu().numpy(), res.rho.cpu().numpy())
+    off = res.proj_off.cpu().numpy()
+    ref = O.shifted_solve(O.system_for(wl), wl.xyz, cols, wl.z, wl.w, tol=1e-12, radius=1.0, prune=True, threads=8)
+    r_g, r_o = col_rel(e2, eps_g, off), col_rel(e2, fo.energy_density(ref, wl.z, wl.w), off)
+    print(f"  shift-pass eps vs G stream {r_g:.2e}, vs oracle {r_o:.2e}", flush=True)
+    assert r_g < 1e-13 and r_o < 1e-9
+    F1 = sgf.band_forces(prep, res, wl.tb, eps=sgf.energy_density(res, wl.z, wl.w)).cpu().numpy()
+    F2 = sgf.band_forces(prep, r2, wl.tb, eps=r2.eps).cpu().numpy()
+    assert np.abs(F1 - F2).max() <= 1e-12 * np.abs(F1).max()
+    with pytest.raises(sgf.SgfError):
+        sgf.solve_prepared(prep, wl.z, None, tol=1e-12, eps_out=True)  # needs weights
+    with pytest.raises(sgf.SgfError):
+        sgf.solve_prepared(prep, wl.z, wl.w, tol=1e-12, precision="mixed", eps_out=True, fallback=False)
+
+
 def test_overlap_forces_argument_errors(sgf):
     import dataclasses
     wl, cols, prep, res = overlap_case(sgf)
