@@ -940,6 +940,326 @@ __global__ __launch_bounds__(SEED_T) void k_seed_gen(SolveArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// S != I seed pass with two wavefronts per column, for subspaces of 17 to 32
+// atoms: thread t owns row t, so the product with the packed inverse and the
+// block product are split over 128 threads, and the LDS that holds one
+// column's inverse feeds two wavefronts instead of one.  The iteration is
+// that of k_seed_gen with the packed triangle; the sums of an iteration go
+// through a wavefront reduction and then the two wavefronts' totals, added in
+// wavefront order, so every thread holds the same scalars and every branch on
+// them is uniform over the workgroup.  Four barriers per iteration: after
+// mu, after the update of s, after rho' and ||s||^2, and the vote on the
+// running shifts.
+// ---------------------------------------------------------------------------
+constexpr int GEN2_T = 128;
+
+// sum over the workgroup of NV values per thread, the same in every thread
+template <int NV>
+__device__ __forceinline__ void gen2_sum(const double (&v)[NV], double (*red)[NV], double (&out)[NV]) {
+    const int wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        const double t = wave_reduce(v[i]);
+        if ((threadIdx.x & 63) == 0) red[wv][i] = t;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) out[i] = red[0][i] + red[1][i];
+}
+
+template <int M, int BMAX>
+__global__ __launch_bounds__(GEN2_T) void k_seed_gen2(SolveArgs a) {
+    extern __shared__ double4 lds4[];
+    char *lds = reinterpret_cast<char *>(lds4);
+    double2 *vp = reinterpret_cast<double2 *>(lds + a.off_p);
+    double2 *vs = reinterpret_cast<double2 *>(lds + a.off_s);
+    double2 *vw = reinterpret_cast<double2 *>(lds + a.off_w);
+    double2 *vq = reinterpret_cast<double2 *>(lds + a.off_q);
+    double2 *vr = reinterpret_cast<double2 *>(lds + a.off_r);
+    double *Si = reinterpret_cast<double *>(lds + a.off_sinv);  // packed lower triangle, tri(nl) doubles
+    __shared__ double red_mu[2][2], red_rs[2][3];
+    __shared__ int64_t sh_ticket;
+    const int tid = threadIdx.x;
+    const double2 zs = a.z[a.seed];
+    double2 sigma[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int k = tid + GEN2_T * m;
+        sigma[m] = k < a.ns ? csub(a.z[k], zs) : make_double2(0.0, 0.0);
+    }
+    const double tol2 = a.tol * a.tol;
+    const double2 zero = make_double2(0.0, 0.0);
+    constexpr int NBR = BMAX > 0 ? BMAX : 1;
+
+    for (;;) {
+        if (tid == 0) sh_ticket = (int64_t)atomicAdd(reinterpret_cast<unsigned long long *>(a.ticket), 1ull);
+        __syncthreads();
+        int64_t ticket = sh_ticket;
+        __syncthreads();  // sh_ticket is read by all before the next column writes it
+        if (ticket >= a.batch_end - a.batch_begin) break;
+        const int64_t slot = ticket;
+        ticket += a.batch_begin;
+        const int64_t c = a.order ? (int64_t)a.order[ticket] : ticket;
+        if (c < 0 || c >= a.n_cols) continue;  // reported by the launch of the other class
+        const int64_t j = a.cols[c];
+        const int32_t pl = a.col_plan[c];
+        bool bad = pl < 0 || pl >= a.n_plans || j < 0;
+        int64_t a0 = 0, b0 = 0, p0 = 0;
+        int n_loc = 0, nblk = 0, npa = 0, cl = 0;
+        if (!bad) {
+            a0 = a.atom_off[pl];
+            n_loc = (int)(a.atom_off[pl + 1] - a0);
+            b0 = a.blk_off[pl];
+            nblk = (int)(a.blk_off[pl + 1] - b0);
+            p0 = a.pa_off[pl];
+            npa = (int)(a.pa_off[pl + 1] - p0);
+            cl = a.center_loc[pl];
+            bad = n_loc < 1 || n_loc > 32 || n_loc > a.max_loc_atoms || npa < 1 || 4 * npa > a.rmax || cl < 0 ||
+                  cl >= n_loc || a.loc_atom[a0 + cl] != (int32_t)(j >> 2);
+        }
+        // this launch takes the good columns of its size class only
+        if (bad || n_loc < a.loc_lo || n_loc > a.loc_hi) continue;
+        const int nl = 4 * n_loc;
+        const int i = tid;  // this thread's row
+        const bool row = i < nl;
+        int bcol[NBR];
+        double hrow[NBR][4];
+        int wide = 0;
+        {
+            const int A = i >> 2, o = i & 3;
+            int t0 = 0, nb = 0;
+            if (row) {
+                t0 = a.lrow[a0 + A];
+                nb = (A + 1 < n_loc ? a.lrow[a0 + A + 1] : nblk) - t0;
+            }
+            wide = nb > BMAX ? 1 : 0;
+#pragma unroll
+            for (int b = 0; b < NBR; ++b) {
+                bcol[b] = 0;
+                hrow[b][0] = hrow[b][1] = hrow[b][2] = hrow[b][3] = 0.0;
+                if (b < nb) {
+                    const int32_t *lb = &a.lblk[2 * (b0 + t0 + b)];
+                    bcol[b] = lb[0];
+                    const double *hb = &a.h[16 * (int64_t)lb[1] + 4 * o];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) hrow[b][q] = hb[q];
+                }
+            }
+        }
+        if (__syncthreads_or(wide)) {
+            if (tid == 0) {
+                a.meta[slot] = ColMeta{-1, 0, 0, SGF_BADCOLUMN};
+                a.iters[c] = 0;
+                a.status[c] = SGF_BADCOLUMN;
+            }
+            continue;
+        }
+        const int jl = 4 * cl + (int)(j & 3);
+        const int nprow = 4 * npa;
+        const int prow = tid < nprow ? 4 * a.pa_loc[p0 + (tid >> 2)] + (tid & 3) : 0;
+        double2 *hab = a.hab + (size_t)slot * a.cap * 2;
+        double2 *hr = a.hr + (size_t)slot * (a.cap + 1) * a.rmax;
+
+        // S_L packed, then the sweep in place (after the last pivot the
+        // triangle holds -S_L^{-1}); v = column k of the pivot lives in vw
+        for (int e = tid; e < tri(nl); e += GEN2_T) Si[e] = 0.0;
+        __syncthreads();
+        for (int A = tid; A < n_loc; A += GEN2_T) {
+            const int t0 = a.lrow[a0 + A], t1 = A + 1 < n_loc ? a.lrow[a0 + A + 1] : nblk;
+            for (int t = t0; t < t1; ++t) {
+                const int B = a.lblk[2 * (b0 + t)];
+                if (B > A) continue;  // the upper blocks mirror the lower ones
+                const double *sb = &a.s[16 * (int64_t)a.lblk[2 * (b0 + t) + 1]];
+                for (int o = 0; o < 4; ++o)
+                    for (int q = 0; q < 4; ++q)
+                        if (4 * B + q <= 4 * A + o) Si[tri(4 * A + o) + 4 * B + q] = sb[4 * o + q];
+            }
+        }
+        __syncthreads();
+        {
+            double *v = reinterpret_cast<double *>(vw);
+            double *rw = &Si[tri(row ? i : 0)];
+            for (int kk = 0; kk < nl; ++kk) {
+                if (row) v[i] = i >= kk ? Si[tri(i) + kk] : Si[tri(kk) + i];
+                __syncthreads();
+                const double id = 1.0 / v[kk];
+                if (row && i != kk) {
+                    const double ci = v[i] * id;
+                    for (int jj = 0; jj <= i; ++jj) rw[jj] = fma(-ci, v[jj], rw[jj]);
+                    if (kk <= i) rw[kk] = ci;
+                } else if (row) {
+                    for (int jj = 0; jj < kk; ++jj) rw[jj] = v[jj] * id;
+                    rw[kk] = -id;
+                }
+                __syncthreads();
+            }
+        }
+
+        // start: s_0 = q_0 = e_jl, r_0 = p_0 = S^{-1} e_jl, rho_0 = r_0^T s_0
+        if (row) {
+            const double2 sv = make_double2(i == jl ? 1.0 : 0.0, 0.0);
+            const double2 rv = make_double2(-(i >= jl ? Si[tri(i) + jl] : Si[tri(jl) + i]), 0.0);
+            vs[i] = sv;
+            vq[i] = sv;
+            vr[i] = rv;
+            vp[i] = rv;
+        }
+        __syncthreads();
+        if (tid < nprow) hr[tid] = vr[prow];
+
+        double2 pc[M], po[M];
+        bool act[M];
+        int nkm[M];
+        double res[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            pc[m] = po[m] = make_double2(1.0, 0.0);
+            act[m] = tid + GEN2_T * m < a.ns;
+            nkm[m] = 0;
+            res[m] = 1.0;
+        }
+        double2 rho = make_double2(-Si[tri(jl) + jl], 0.0);
+        double2 alpha_old = make_double2(1.0, 0.0), beta_old = zero;
+        int status = SGF_MAXITER, iters = 0, applied = 0;
+        double snorm2 = 1.0;
+        const int max_iter = a.max_iter > 0 ? a.max_iter : 10 * nl;
+        const int c0 = row ? i : nl - 1;  // row read by the product (clamped)
+        const int b0t = tri(c0);
+
+        for (int it = 0; it < max_iter; ++it) {
+            // w = z_s q - H p ; mu = p^T w
+            double2 mu;
+            {
+                double m0 = 0.0, m1 = 0.0;
+                if (row) {
+                    double ax = 0.0, ay = 0.0;
+#pragma unroll
+                    for (int b = 0; b < BMAX; ++b) {
+                        const double2 *pb = &vp[4 * bcol[b]];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            ax = fma(hrow[b][q], pb[q].x, ax);
+                            ay = fma(hrow[b][q], pb[q].y, ay);
+                        }
+                    }
+                    const double2 pi_ = vp[i], qi = vq[i];
+                    const double2 wi = make_double2(zs.x * qi.x - zs.y * qi.y - ax, zs.x * qi.y + zs.y * qi.x - ay);
+                    vw[i] = wi;
+                    m0 = fma(pi_.x, wi.x, -pi_.y * wi.y);
+                    m1 = fma(pi_.x, wi.y, pi_.y * wi.x);
+                }
+                const double v[2] = {m0, m1};
+                double sum[2];
+                gen2_sum<2>(v, red_mu, sum);
+                mu = make_double2(sum[0], sum[1]);
+            }
+            iters = it + 1;
+            if (!cfinite(mu) || !cfinite(rho)) { status = SGF_NONFINITE; break; }
+            if (mu.x == 0.0 && mu.y == 0.0) { status = SGF_BREAKDOWN; break; }
+            const double2 alpha = cdiv(rho, mu);
+
+            // s -= alpha w
+            double2 si = zero;
+            if (row) {
+                si = csub(vs[i], cmul(alpha, vw[i]));
+                vs[i] = si;
+            }
+            __syncthreads();
+            // r = S^{-1} s (the triangle holds -S^{-1}: row i's own entries,
+            // then column i of the rows below it, negated) ; rho' = r^T s ; ||s||^2
+            double2 rho_new;
+            {
+                double rr[3] = {0.0, 0.0, 0.0};
+                if (row) {
+                    double ax[4] = {0.0, 0.0, 0.0, 0.0}, ay[4] = {0.0, 0.0, 0.0, 0.0};
+                    int tj = 0;  // tri(jj)
+                    for (int jj = 0; jj < nl; jj += 4) {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int jn = jj + u;
+                            const double2 sj = vs[jn];
+                            const double av = Si[jn <= c0 ? b0t + jn : tj + c0];
+                            tj += jn + 1;
+                            ax[u] = fma(av, sj.x, ax[u]);
+                            ay[u] = fma(av, sj.y, ay[u]);
+                        }
+                    }
+                    const double rxs = -((ax[0] + ax[1]) + (ax[2] + ax[3]));
+                    const double rys = -((ay[0] + ay[1]) + (ay[2] + ay[3]));
+                    vr[i] = make_double2(rxs, rys);
+                    rr[0] = fma(rxs, si.x, -rys * si.y);
+                    rr[1] = fma(rxs, si.y, rys * si.x);
+                    rr[2] = fma(si.x, si.x, si.y * si.y);
+                }
+                double sum[3];
+                gen2_sum<3>(rr, red_rs, sum);
+                rho_new = make_double2(sum[0], sum[1]);
+                snorm2 = sum[2];
+            }
+            const double2 ia = crcp(alpha);
+            const double2 beta = cmul(rho_new, crcp(rho));
+            if (row) {
+                vp[i] = cfma(beta, vp[i], vr[i]);
+                vq[i] = cfma(beta, vq[i], si);
+            }
+            if (tid == 0) {
+                hab[2 * it] = ia;
+                hab[2 * it + 1] = cmul(beta, ia);
+            }
+            if (tid < nprow) hr[(size_t)(it + 1) * a.rmax + tid] = vr[prow];
+
+            const double2 coup = cmul(cmul(alpha, beta_old), crcp(alpha_old));
+            int alive = 0;
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                if (!act[m]) continue;
+                const double2 pn = cadd(cmul(cfma(alpha, sigma[m], make_double2(1.0, 0.0)), pc[m]),
+                                        cmul(coup, csub(pc[m], po[m])));
+                po[m] = pc[m];
+                pc[m] = pn;
+                const double pn2 = fma(pn.x, pn.x, pn.y * pn.y);
+                if (snorm2 <= tol2 * pn2) {
+                    act[m] = false;
+                    nkm[m] = it + 1;
+                    res[m] = sqrt(snorm2 / pn2);
+                } else {
+                    alive = 1;
+                }
+            }
+            applied = it + 1;
+            alpha_old = alpha;
+            beta_old = beta;
+            rho = rho_new;
+            // the vote is also the barrier that ends the iteration (p is in vp)
+            const bool any_alive = __syncthreads_or(alive) != 0;
+            if (!any_alive || snorm2 == 0.0) { status = SGF_CONVERGED; break; }
+            if (rho_new.x == 0.0 && rho_new.y == 0.0) { status = SGF_BREAKDOWN; break; }
+            if (!cfinite(rho_new) || !isfinite(snorm2)) { status = SGF_NONFINITE; break; }
+        }
+
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int k = tid + GEN2_T * m;
+            if (k >= a.ns) continue;
+            if (act[m]) {
+                nkm[m] = applied;
+                const double pn2 = fma(pc[m].x, pc[m].x, pc[m].y * pc[m].y);
+                res[m] = applied > 0 ? sqrt(snorm2 / pn2) : 1.0;
+            }
+            a.nk[(size_t)slot * a.ns_pad + k] = nkm[m];
+            if (a.resid) a.resid[c * a.ns + k] = res[m];
+            if (a.shift_iters) a.shift_iters[c * a.ns + k] = nkm[m];
+        }
+        if (tid == 0) {
+            a.meta[slot] = ColMeta{(int32_t)c, iters, npa, status};
+            a.iters[c] = iters;
+            a.status[c] = status;
+        }
+        __syncthreads();  // LDS reuse by the next column
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Shift pass
 // ---------------------------------------------------------------------------
 
@@ -1252,6 +1572,20 @@ static KernelFn pick_seed_gen(int M, int bmax, bool packed) {
     return packed ? pick_seed_gen_p<true>(M, bmax) : pick_seed_gen_p<false>(M, bmax);
 }
 
+// two wavefronts per column; M2 shifts per thread (128 threads), rows of at
+// most bmax <= 8 blocks
+template <int BMAX>
+static KernelFn pick_seed_gen2_m(int M2) {
+    switch (M2) {
+        case 1: return k_seed_gen2<1, BMAX>;
+        case 2: return k_seed_gen2<2, BMAX>;
+        default: return k_seed_gen2<4, BMAX>;
+    }
+}
+static KernelFn pick_seed_gen2(int M2, int bmax) {
+    return bmax <= 5 ? pick_seed_gen2_m<5>(M2) : bmax <= 6 ? pick_seed_gen2_m<6>(M2) : pick_seed_gen2_m<8>(M2);
+}
+
 template <int MS>
 static KernelFn pick_shift_ms(int npa) {
     switch (npa) {
@@ -1462,12 +1796,19 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
     // second launch with the packed triangle (half the LDS, so twice the
     // wavefronts per compute unit).  stage_lds = 0: one launch, dense;
     // stage_lds = 1: one launch, packed.
-    const bool gen_split = gen && !ovl && !mixed && opts->stage_lds < 0 && totals->max_loc_atoms > 16;
+    // stage_lds = 2: the same split, with one wavefront per column in the
+    // second launch too.  Otherwise the second launch (17 to 32 atoms, rows of
+    // at most 8 blocks) runs two wavefronts per column (k_seed_gen2).
+    const bool gen_split = gen && !ovl && !mixed && (opts->stage_lds < 0 || opts->stage_lds == 2) &&
+                           totals->max_loc_atoms > 16;
+    const bool gen2 = gen_split && opts->stage_lds < 0 && totals->max_loc_atoms <= 32 && totals->max_row_blocks <= 8;
     const bool gen_packed = gen_split || (gen && opts->stage_lds == 1);
     KernelFn seed_fn = mixed ? pick_seed_mx(M, totals->max_row_blocks)
                        : ovl ? pick_seed_ovl(1, M, totals->max_row_blocks)
+                       : gen2 ? pick_seed_gen2((hs.ns_pad + GEN2_T - 1) / GEN2_T, totals->max_row_blocks)
                        : gen ? pick_seed_gen(M, totals->max_row_blocks, gen_packed)
                              : (r1 ? pick_seed_r1(M, totals->max_row_blocks) : pick_seed(stage, M));
+    const int seed_threads = gen2 ? GEN2_T : SEED_T;
     KernelFn seed_fn2 = ovl2 ? pick_seed_ovl(2, (hs.ns_pad + 127) / 128, totals->max_row_blocks) : nullptr;
     size_t seed_lds = (r1 || mixed || ovl) ? 0 : lds;
     // S != I: p, s, w, q, r and the dense inverse of the local overlap, laid
@@ -1512,8 +1853,8 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
     SGF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(seed_fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)seed_lds));
     int per_cu = 0;
-    SGF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(seed_fn), SEED_T,
-                                                         seed_lds));
+    SGF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(seed_fn),
+                                                         seed_threads, seed_lds));
     if (per_cu < 1) {
         set_error("sgf_shifted_solve: seed kernel does not fit a compute unit (LDS %zu)", lds);
         return SGF_EUNSUPPORTED;
@@ -1579,7 +1920,7 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
             k_zero_ticket<<<1, 64, 0, st>>>(L.ticket);
             SGF_LAUNCHED();
         }
-        hipLaunchKernelGGL(seed_fn, dim3((unsigned)grid), dim3(SEED_T), seed_lds, st, a);
+        hipLaunchKernelGGL(seed_fn, dim3((unsigned)grid), dim3(seed_threads), seed_lds, st, a);
         SGF_LAUNCHED();
         if (ovl2) {
             // the same tickets again for the columns of 17 to 22 atoms
