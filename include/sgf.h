@@ -222,8 +222,9 @@ typedef struct {
                               1 LDS-staged operator; 0 operator read from global.
                               S != I: -1 auto (subspaces of <= 16 atoms in a launch with the dense
                               overlap inverse, larger ones in a second launch with its packed
-                              triangle, two wavefronts per column when they have <= 32 atoms and
-                              rows of <= 8 blocks); 0 one launch, dense; 1 one launch, packed;
+                              triangle; both with two wavefronts per column when every subspace
+                              has <= 32 atoms and rows of <= 8 blocks); 0 one launch, dense; 1 one
+                              launch, packed;
                               2 the split of -1 with one wavefront per column throughout (S = I
                               treats 2 as 0) */
     int32_t grid;          /* seed-pass persistent workgroups; 0: fill the device */

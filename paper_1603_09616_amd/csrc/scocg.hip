@@ -1260,6 +1260,320 @@ __global__ __launch_bounds__(GEN2_T) void k_seed_gen2(SolveArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// S != I seed pass with two wavefronts per column for subspaces of at most 16
+// atoms (nl <= 64) and the dense inverse: lane l of wavefront h works on row
+// l and on the columns of the inverse that belong to the first ceil(n_loc/2)
+// atoms (h = 0) or to the others (h = 1), so each row's product and each
+// row's elimination step are split between the two wavefronts; the two
+// halves of a row's product are added in wavefront order.  Wavefront 0 forms
+// the block product of H and the vector updates.
+// The Gauss-Jordan elimination is that of k_seed_gen (the same bits); the
+// iteration sums run over the workgroup as in k_seed_gen2.
+// ---------------------------------------------------------------------------
+template <int M, int BMAX>
+__global__ __launch_bounds__(GEN2_T) void k_seed_gen2s(SolveArgs a) {
+    extern __shared__ double4 lds4[];
+    char *lds = reinterpret_cast<char *>(lds4);
+    double2 *vp = reinterpret_cast<double2 *>(lds + a.off_p);
+    double2 *vs = reinterpret_cast<double2 *>(lds + a.off_s);
+    double2 *vw = reinterpret_cast<double2 *>(lds + a.off_w);
+    double2 *vq = reinterpret_cast<double2 *>(lds + a.off_q);
+    double2 *vr = reinterpret_cast<double2 *>(lds + a.off_r);
+    double *Si = reinterpret_cast<double *>(lds + a.off_sinv);  // dense, row stride sinv_ld(nl)
+    __shared__ double red_mu[2][2], red_rs[2][3];
+    __shared__ double2 half1[64];  // wavefront 1's half of each row's product
+    __shared__ int64_t sh_ticket;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, h = tid >> 6;
+    const double2 zs = a.z[a.seed];
+    double2 sigma[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int k = tid + GEN2_T * m;
+        sigma[m] = k < a.ns ? csub(a.z[k], zs) : make_double2(0.0, 0.0);
+    }
+    const double tol2 = a.tol * a.tol;
+    const double2 zero = make_double2(0.0, 0.0);
+    constexpr int NBR = BMAX > 0 ? BMAX : 1;
+
+    for (;;) {
+        if (tid == 0) sh_ticket = (int64_t)atomicAdd(reinterpret_cast<unsigned long long *>(a.ticket), 1ull);
+        __syncthreads();
+        int64_t ticket = sh_ticket;
+        __syncthreads();
+        if (ticket >= a.batch_end - a.batch_begin) break;
+        const int64_t slot = ticket;
+        ticket += a.batch_begin;
+        const int64_t c = a.order ? (int64_t)a.order[ticket] : ticket;
+        if (c < 0 || c >= a.n_cols) {
+            if (tid == 0) a.meta[slot] = ColMeta{-1, 0, 0, SGF_BADCOLUMN};
+            continue;
+        }
+        const int64_t j = a.cols[c];
+        const int32_t pl = a.col_plan[c];
+        bool bad = pl < 0 || pl >= a.n_plans || j < 0;
+        int64_t a0 = 0, b0 = 0, p0 = 0;
+        int n_loc = 0, nblk = 0, npa = 0, cl = 0;
+        if (!bad) {
+            a0 = a.atom_off[pl];
+            n_loc = (int)(a.atom_off[pl + 1] - a0);
+            b0 = a.blk_off[pl];
+            nblk = (int)(a.blk_off[pl + 1] - b0);
+            p0 = a.pa_off[pl];
+            npa = (int)(a.pa_off[pl + 1] - p0);
+            cl = a.center_loc[pl];
+            bad = n_loc < 1 || n_loc > 32 || n_loc > a.max_loc_atoms || npa < 1 || 4 * npa > a.rmax || cl < 0 ||
+                  cl >= n_loc || a.loc_atom[a0 + cl] != (int32_t)(j >> 2);
+        }
+        // this launch takes the columns of up to loc_hi (<= 16) atoms and
+        // reports the unsolvable ones
+        if (!bad && n_loc > a.loc_hi) continue;
+        const int nl = 4 * n_loc;
+        const int i = lane;  // this thread's row
+        const bool row = !bad && i < nl;
+        int bcol[NBR];
+        double hrow[NBR][4];
+        int wide = 0;
+        {
+            const int A = i >> 2, o = i & 3;
+            int t0 = 0, nb = 0;
+            if (row) {
+                t0 = a.lrow[a0 + A];
+                nb = (A + 1 < n_loc ? a.lrow[a0 + A + 1] : nblk) - t0;
+            }
+            wide = nb > BMAX ? 1 : 0;
+#pragma unroll
+            for (int b = 0; b < NBR; ++b) {
+                bcol[b] = 0;
+                hrow[b][0] = hrow[b][1] = hrow[b][2] = hrow[b][3] = 0.0;
+                if (b < nb) {
+                    const int32_t *lb = &a.lblk[2 * (b0 + t0 + b)];
+                    bcol[b] = lb[0];
+                    const double *hb = &a.h[16 * (int64_t)lb[1] + 4 * o];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) hrow[b][q] = hb[q];
+                }
+            }
+        }
+        if (__syncthreads_or(bad || wide)) {
+            if (tid == 0) {
+                a.meta[slot] = ColMeta{-1, 0, 0, SGF_BADCOLUMN};
+                a.iters[c] = 0;
+                a.status[c] = SGF_BADCOLUMN;
+            }
+            continue;
+        }
+        const int jl = 4 * cl + (int)(j & 3);
+        const int nprow = 4 * npa;
+        const int prow = tid < nprow ? 4 * a.pa_loc[p0 + (tid >> 2)] + (tid & 3) : 0;
+        double2 *hab = a.hab + (size_t)slot * a.cap * 2;
+        double2 *hr = a.hr + (size_t)slot * (a.cap + 1) * a.rmax;
+        const int ld = sinv_ld(nl);
+        // this thread's columns: the first ceil(n_loc / 2) atoms for wavefront
+        // 0, the rest for wavefront 1, so both ranges are whole multiples of 4
+        const int hw = 4 * ((n_loc + 1) >> 1);
+        const int j0 = h == 0 ? 0 : hw, j1 = h == 0 ? hw : nl;
+
+        // dense S_L, then its inverse in place (Gauss-Jordan without pivoting)
+        for (int e = tid; e < nl * ld; e += GEN2_T) Si[e] = 0.0;
+        __syncthreads();
+        for (int A = tid; A < n_loc; A += GEN2_T) {
+            const int t0 = a.lrow[a0 + A], t1 = A + 1 < n_loc ? a.lrow[a0 + A + 1] : nblk;
+            for (int t = t0; t < t1; ++t) {
+                const int B = a.lblk[2 * (b0 + t)];
+                const double *sb = &a.s[16 * (int64_t)a.lblk[2 * (b0 + t) + 1]];
+                for (int o = 0; o < 4; ++o)
+                    for (int q = 0; q < 4; ++q) Si[(4 * A + o) * ld + 4 * B + q] = sb[4 * o + q];
+            }
+        }
+        __syncthreads();
+        {
+            double *w0 = &Si[(row ? i : 0) * ld];
+            for (int kk = 0; kk < nl; ++kk) {
+                const double piv = 1.0 / Si[kk * ld + kk];
+                // multiplier of this row, read before any thread changes column kk
+                const double f0 = (row && i != kk) ? w0[kk] : 0.0;
+                __syncthreads();
+                for (int jj = tid; jj < nl; jj += GEN2_T) Si[kk * ld + jj] = (jj == kk) ? piv : Si[kk * ld + jj] * piv;
+                __syncthreads();
+                if (row && i != kk) {
+                    const double *pr = &Si[kk * ld];
+                    for (int jj = j0; jj < j1; jj += 4) {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) w0[jj + u] = fma(-f0, pr[jj + u], w0[jj + u]);
+                    }
+                    if (kk >= j0 && kk < j1) w0[kk] = -f0 * piv;
+                }
+                __syncthreads();
+            }
+        }
+
+        // start: s_0 = q_0 = e_jl, r_0 = p_0 = S^{-1} e_jl, rho_0 = r_0^T s_0
+        if (h == 0 && row) {
+            const double2 sv = make_double2(i == jl ? 1.0 : 0.0, 0.0);
+            const double2 rv = make_double2(Si[i * ld + jl], 0.0);
+            vs[i] = sv;
+            vq[i] = sv;
+            vr[i] = rv;
+            vp[i] = rv;
+        }
+        __syncthreads();
+        if (tid < nprow) hr[tid] = vr[prow];
+
+        double2 pc[M], po[M];
+        bool act[M];
+        int nkm[M];
+        double res[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            pc[m] = po[m] = make_double2(1.0, 0.0);
+            act[m] = tid + GEN2_T * m < a.ns;
+            nkm[m] = 0;
+            res[m] = 1.0;
+        }
+        double2 rho = make_double2(Si[jl * ld + jl], 0.0);
+        double2 alpha_old = make_double2(1.0, 0.0), beta_old = zero;
+        int status = SGF_MAXITER, iters = 0, applied = 0;
+        double snorm2 = 1.0;
+        const int max_iter = a.max_iter > 0 ? a.max_iter : 10 * nl;
+        const double *srow = &Si[(row ? i : 0) * ld];
+
+        for (int it = 0; it < max_iter; ++it) {
+            // w = z_s q - H p ; mu = p^T w (wavefront 0)
+            double2 mu;
+            {
+                double m0 = 0.0, m1 = 0.0;
+                if (h == 0 && row) {
+                    double ax = 0.0, ay = 0.0;
+#pragma unroll
+                    for (int b = 0; b < BMAX; ++b) {
+                        const double2 *pb = &vp[4 * bcol[b]];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            ax = fma(hrow[b][q], pb[q].x, ax);
+                            ay = fma(hrow[b][q], pb[q].y, ay);
+                        }
+                    }
+                    const double2 pi_ = vp[i], qi = vq[i];
+                    const double2 wi = make_double2(zs.x * qi.x - zs.y * qi.y - ax, zs.x * qi.y + zs.y * qi.x - ay);
+                    vw[i] = wi;
+                    m0 = fma(pi_.x, wi.x, -pi_.y * wi.y);
+                    m1 = fma(pi_.x, wi.y, pi_.y * wi.x);
+                }
+                const double v[2] = {m0, m1};
+                double sum[2];
+                gen2_sum<2>(v, red_mu, sum);
+                mu = make_double2(sum[0], sum[1]);
+            }
+            iters = it + 1;
+            if (!cfinite(mu) || !cfinite(rho)) { status = SGF_NONFINITE; break; }
+            if (mu.x == 0.0 && mu.y == 0.0) { status = SGF_BREAKDOWN; break; }
+            const double2 alpha = cdiv(rho, mu);
+
+            // s -= alpha w (wavefront 0)
+            double2 si = zero;
+            if (h == 0 && row) {
+                si = csub(vs[i], cmul(alpha, vw[i]));
+                vs[i] = si;
+            }
+            __syncthreads();
+            // r = S^{-1} s: each wavefront one half of the row, four partial sums
+            double2 part = zero;
+            if (row) {
+                double ax[4] = {0.0, 0.0, 0.0, 0.0}, ay[4] = {0.0, 0.0, 0.0, 0.0};
+                for (int jj = j0; jj < j1; jj += 4) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const double2 sj = vs[jj + u];
+                        const double av = srow[jj + u];
+                        ax[u] = fma(av, sj.x, ax[u]);
+                        ay[u] = fma(av, sj.y, ay[u]);
+                    }
+                }
+                part = make_double2((ax[0] + ax[1]) + (ax[2] + ax[3]), (ay[0] + ay[1]) + (ay[2] + ay[3]));
+                if (h == 1) half1[i] = part;
+            }
+            __syncthreads();
+            // rho' = r^T s ; ||s||^2 (wavefront 0)
+            double2 rho_new;
+            {
+                double rr[3] = {0.0, 0.0, 0.0};
+                if (h == 0 && row) {
+                    const double2 o1 = half1[i];
+                    const double rxs = part.x + o1.x, rys = part.y + o1.y;
+                    vr[i] = make_double2(rxs, rys);
+                    rr[0] = fma(rxs, si.x, -rys * si.y);
+                    rr[1] = fma(rxs, si.y, rys * si.x);
+                    rr[2] = fma(si.x, si.x, si.y * si.y);
+                }
+                double sum[3];
+                gen2_sum<3>(rr, red_rs, sum);
+                rho_new = make_double2(sum[0], sum[1]);
+                snorm2 = sum[2];
+            }
+            const double2 ia = crcp(alpha);
+            const double2 beta = cmul(rho_new, crcp(rho));
+            if (h == 0 && row) {
+                vp[i] = cfma(beta, vp[i], vr[i]);
+                vq[i] = cfma(beta, vq[i], si);
+            }
+            if (tid == 0) {
+                hab[2 * it] = ia;
+                hab[2 * it + 1] = cmul(beta, ia);
+            }
+            if (tid < nprow) hr[(size_t)(it + 1) * a.rmax + tid] = vr[prow];
+
+            const double2 coup = cmul(cmul(alpha, beta_old), crcp(alpha_old));
+            int alive = 0;
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                if (!act[m]) continue;
+                const double2 pn = cadd(cmul(cfma(alpha, sigma[m], make_double2(1.0, 0.0)), pc[m]),
+                                        cmul(coup, csub(pc[m], po[m])));
+                po[m] = pc[m];
+                pc[m] = pn;
+                const double pn2 = fma(pn.x, pn.x, pn.y * pn.y);
+                if (snorm2 <= tol2 * pn2) {
+                    act[m] = false;
+                    nkm[m] = it + 1;
+                    res[m] = sqrt(snorm2 / pn2);
+                } else {
+                    alive = 1;
+                }
+            }
+            applied = it + 1;
+            alpha_old = alpha;
+            beta_old = beta;
+            rho = rho_new;
+            const bool any_alive = __syncthreads_or(alive) != 0;
+            if (!any_alive || snorm2 == 0.0) { status = SGF_CONVERGED; break; }
+            if (rho_new.x == 0.0 && rho_new.y == 0.0) { status = SGF_BREAKDOWN; break; }
+            if (!cfinite(rho_new) || !isfinite(snorm2)) { status = SGF_NONFINITE; break; }
+        }
+
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int k = tid + GEN2_T * m;
+            if (k >= a.ns) continue;
+            if (act[m]) {
+                nkm[m] = applied;
+                const double pn2 = fma(pc[m].x, pc[m].x, pc[m].y * pc[m].y);
+                res[m] = applied > 0 ? sqrt(snorm2 / pn2) : 1.0;
+            }
+            a.nk[(size_t)slot * a.ns_pad + k] = nkm[m];
+            if (a.resid) a.resid[c * a.ns + k] = res[m];
+            if (a.shift_iters) a.shift_iters[c * a.ns + k] = nkm[m];
+        }
+        if (tid == 0) {
+            a.meta[slot] = ColMeta{(int32_t)c, iters, npa, status};
+            a.iters[c] = iters;
+            a.status[c] = status;
+        }
+        __syncthreads();  // LDS reuse by the next column
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Shift pass
 // ---------------------------------------------------------------------------
 
@@ -1585,6 +1899,17 @@ static KernelFn pick_seed_gen2_m(int M2) {
 static KernelFn pick_seed_gen2(int M2, int bmax) {
     return bmax <= 5 ? pick_seed_gen2_m<5>(M2) : bmax <= 6 ? pick_seed_gen2_m<6>(M2) : pick_seed_gen2_m<8>(M2);
 }
+template <int BMAX>
+static KernelFn pick_seed_gen2s_m(int M2) {
+    switch (M2) {
+        case 1: return k_seed_gen2s<1, BMAX>;
+        case 2: return k_seed_gen2s<2, BMAX>;
+        default: return k_seed_gen2s<4, BMAX>;
+    }
+}
+static KernelFn pick_seed_gen2s(int M2, int bmax) {
+    return bmax <= 5 ? pick_seed_gen2s_m<5>(M2) : bmax <= 6 ? pick_seed_gen2s_m<6>(M2) : pick_seed_gen2s_m<8>(M2);
+}
 
 template <int MS>
 static KernelFn pick_shift_ms(int npa) {
@@ -1826,7 +2151,12 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
     };
     // the launch for subspaces of up to 16 atoms (gen_split)
     SolveArgs a_small{};
-    KernelFn seed_fn_small = gen_split ? pick_seed_gen(M, totals->max_row_blocks, false) : nullptr;
+    // with gen2, the small class also runs two wavefronts per column (each
+    // row's product split between them by column halves)
+    KernelFn seed_fn_small = !gen_split ? nullptr
+                             : gen2    ? pick_seed_gen2s((hs.ns_pad + GEN2_T - 1) / GEN2_T, totals->max_row_blocks)
+                                       : pick_seed_gen(M, totals->max_row_blocks, false);
+    const int small_threads = gen2 ? GEN2_T : SEED_T;
     size_t lds_small = 0;
     if (gen && !ovl) {
         seed_lds = gen_layout(a, nl, gen_packed);
@@ -1884,7 +2214,7 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
         SGF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(seed_fn_small),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_small));
         SGF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_s, reinterpret_cast<const void *>(seed_fn_small),
-                                                             SEED_T, lds_small));
+                                                             small_threads, lds_small));
         if (per_cu_s < 1) {
             set_error("sgf_shifted_solve: seed kernel does not fit a compute unit (LDS %zu)", lds_small);
             return SGF_EUNSUPPORTED;
@@ -1915,7 +2245,7 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
             a_small.batch_begin = b0;
             a_small.batch_end = b1;
             const int64_t gs = seed_grid_small < b1 - b0 ? seed_grid_small : b1 - b0;
-            hipLaunchKernelGGL(seed_fn_small, dim3((unsigned)gs), dim3(SEED_T), lds_small, st, a_small);
+            hipLaunchKernelGGL(seed_fn_small, dim3((unsigned)gs), dim3(small_threads), lds_small, st, a_small);
             SGF_LAUNCHED();
             k_zero_ticket<<<1, 64, 0, st>>>(L.ticket);
             SGF_LAUNCHED();

@@ -326,13 +326,13 @@ def test_overlap_workload_sampled(sgf, O):
 def test_overlap_size_classes_bitwise(sgf):
     """S != I: the default seed pass runs subspaces of <= 16 atoms in a launch
     with the dense overlap inverse, and the larger ones in a second launch with
-    its packed triangle and two wavefronts per column.  stage_lds 2 makes the
-    same split with one wavefront per column throughout; each of its classes
+    its packed triangle, both with two wavefronts per column.  stage_lds 2
+    makes the same split with one wavefront per column; each of its classes
     gives the same bits as one launch with that class's layout (stage_lds 0:
-    dense, 1: packed).  The default's small class equals them bit for bit; its
-    two-wavefront class sums in another order and agrees within the parity
-    bar, as do the two layouts (two exact inverses of the same S_L).  Repeated
-    default solves are bitwise equal."""
+    dense, 1: packed).  The two-wavefront kernels form the same inverses but
+    sum in another order, and agree with those within the parity bar, as do
+    the two layouts (two exact inverses of the same S_L).  Repeated default
+    solves are bitwise equal."""
     wl = W.config_bundle_overlap(n_columns=4096)
     s = sgf.system_for(wl)
     prep = sgf.prepare(s, wl.columns, radius_per_col=wl.radius_per_col)
@@ -355,19 +355,14 @@ def test_overlap_size_classes_bitwise(sgf):
         np.testing.assert_array_equal(split1.G[rows], ref.G[rows])
         np.testing.assert_array_equal(split1.rho[rows], ref.rho[rows])
         assert split1.iters[c] == ref.iters[c]
-        if n_loc[c] <= 16:
-            np.testing.assert_array_equal(auto.G[rows], ref.G[rows])
-            np.testing.assert_array_equal(auto.rho[rows], ref.rho[rows])
-        else:
-            worst2 = max(worst2, np.abs(auto.G[rows] - ref.G[rows]).max() / np.abs(ref.G[rows]).max(),
-                         np.abs(auto.rho[rows] - ref.rho[rows]).max() / np.abs(ref.rho[rows]).max())
+        worst2 = max(worst2, np.abs(auto.G[rows] - ref.G[rows]).max() / np.abs(ref.G[rows]).max(),
+                     np.abs(auto.rho[rows] - ref.rho[rows]).max() / np.abs(ref.rho[rows]).max())
         if c % 5 == 0:
             worst = max(worst, np.abs(dense.G[rows] - packed.G[rows]).max() / np.abs(dense.G[rows]).max())
-    big = n_loc > 16
     print(f"  dense vs packed inverse: G {worst:.2e}; two wavefronts vs one: {worst2:.2e}, "
-          f"iterations {auto.iters[big].mean():.1f} vs {packed.iters[big].mean():.1f}", flush=True)
+          f"iterations {auto.iters.mean():.1f} vs {split1.iters.mean():.1f}", flush=True)
     assert worst < 1e-10 and worst2 < 1e-10
-    assert abs(auto.iters[big].mean() - packed.iters[big].mean()) <= 0.1 * packed.iters[big].mean() + 2
+    assert abs(auto.iters.mean() - split1.iters.mean()) <= 0.1 * split1.iters.mean() + 2
 
 
 @pytest.mark.skip(reason="the register-tile S != I seed pass did not finish on the GPU (small overlap bundle, "
