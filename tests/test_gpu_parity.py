@@ -365,6 +365,38 @@ def test_overlap_size_classes_bitwise(sgf):
     assert abs(auto.iters.mean() - split1.iters.mean()) <= 0.1 * split1.iters.mean() + 2
 
 
+@pytest.mark.parametrize("n_shifts", [64, 320])
+def test_overlap_two_wavefront_shift_counts(sgf, O, n_shifts):
+    """The two-wavefront S != I seed passes hold one shift per thread at 64
+    shifts and three (of four slots) at 320: both against the oracle on
+    sampled columns of both size classes, and against the one-wavefront split
+    (stage_lds 2) within the parity bar."""
+    wl = W.config_bundle_overlap(n_columns=1536, n_shifts=n_shifts, config_no=31)
+    s = sgf.system_for(wl)
+    prep = sgf.prepare(s, wl.columns, radius_per_col=wl.radius_per_col)
+    n_loc = np.diff(prep.plan.atom_off.cpu().numpy())[prep.col_plan.cpu().numpy()]
+    assert n_loc.min() <= 16 < n_loc.max()
+    got = sgf.solve_prepared(prep, wl.z, wl.w, tol=wl.tol).numpy()
+    one = sgf.solve_prepared(prep, wl.z, wl.w, tol=wl.tol, stage_lds=2).numpy()
+    assert np.all(got.status == sgf.CONVERGED) and np.all(one.status == sgf.CONVERGED)
+    one.proj_ptr = one.proj_off
+    e_g, e_r = col_rel_err(got, one), rho_rel_err(got, one)
+    print(f"  {n_shifts} shifts: two wavefronts vs one: G {e_g:.2e}, rho {e_r:.2e}", flush=True)
+    assert e_g < FP64_RTOL and e_r < FP64_RTOL
+    small, big = np.nonzero(n_loc <= 16)[0][:12], np.nonzero(n_loc > 16)[0][:12]
+    pick = np.sort(np.concatenate([small, big]))
+    ref = O.solve_workload(wl, cols=wl.columns[pick], threads=8)
+
+    class Sub:
+        pass
+    sub = Sub()
+    rows = np.concatenate([np.arange(got.proj_off[c], got.proj_off[c + 1]) for c in pick])
+    sub.proj_off = np.concatenate([[0], np.cumsum(got.proj_off[pick + 1] - got.proj_off[pick])])
+    sub.proj_row, sub.G, sub.rho = got.proj_row[rows], got.G[rows], got.rho[rows]
+    sub.status, sub.iters = got.status[pick], got.iters[pick]
+    compare(sub, ref)
+
+
 @pytest.mark.skip(reason="the register-tile S != I seed pass did not finish on the GPU (small overlap bundle, "
                          "one wavefront per column); cause not found, so the path is switched off in the library")
 def test_overlap_register_tiles_match_dense_inverse(sgf):
