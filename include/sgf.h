@@ -548,7 +548,8 @@ sgf_status sgf_wp_propagate(const sgf_system *sys, int32_t n_rhs, double *d_psi,
  * included.
  * d_xyz: positions (nm, [n_atoms][3]); d_cols, d_proj_off, d_proj_row and
  * d_rho: the columns and projected density matrix of a solve; d_eps: the
- * energy-density matrix on the same rows, required when the system has an
+ * energy-density matrix on the same rows (sgf_energy_density from a kept G,
+ * or the solve's sgf_solve_opts.eps_out), required when the system has an
  * overlap and ignored (may be NULL) when it has none.  p->overlap must match
  * the system.  Writes d_force [n_atoms][3] (eV/nm), cleared first.  FP64
  * atomics add the terms, in no fixed order: repeated runs agree to
