@@ -157,6 +157,21 @@ def test_energy_density_from_the_shift_pass(sgf, O):
         sgf.solve_prepared(prep, wl.z, wl.w, tol=1e-12, precision="mixed", eps_out=True, fallback=False)
 
 
+def test_energy_density_output_under_batching(sgf):
+    """The shift pass writes eps at each column's own output rows: small
+    launches (37 columns) and a learned-order-like permutation give the same
+    bits as one launch in natural order."""
+    wl, cols, prep, res = overlap_case(sgf)
+    one = sgf.solve_prepared(prep, wl.z, wl.w, tol=1e-12, g_out=False, eps_out=True)
+    many = sgf.solve_prepared(prep, wl.z, wl.w, tol=1e-12, g_out=False, eps_out=True, batch_cols=37)
+    perm = np.random.default_rng(4).permutation(cols.size).astype(np.int32)
+    perm_res = sgf.solve_prepared(prep, wl.z, wl.w, tol=1e-12, g_out=False, eps_out=True, order=perm)
+    e1 = one.eps.cpu().numpy()
+    np.testing.assert_array_equal(many.eps.cpu().numpy(), e1)
+    np.testing.assert_array_equal(perm_res.eps.cpu().numpy(), e1)
+    np.testing.assert_array_equal(perm_res.rho.cpu().numpy(), one.rho.cpu().numpy())
+
+
 def test_overlap_forces_argument_errors(sgf):
     import dataclasses
     wl, cols, prep, res = overlap_case(sgf)
