@@ -2111,7 +2111,7 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
     // Switched off: on a small S != I bundle (subspaces of 8 to 15 atoms, one
     // wavefront per column) the register-tile seed pass never finished on the
     // GPU, and no cause has been found in its source or its generated code.
-    // Until one is, every S != I solve takes the dense-LDS seed pass.
+    // Until one is, every S != I solve takes the LDS seed passes below.
     constexpr bool kRegisterTileOverlapSeed = false;
     const bool ovl = kRegisterTileOverlapSeed && gen && !mixed && opts->stage_lds < 0 &&
                      totals->max_loc_atoms <= 22 && totals->max_row_blocks <= 8 && hs.ns_pad <= 256;
