@@ -2127,13 +2127,18 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
     const bool gen_split = gen && !ovl && !mixed && (opts->stage_lds < 0 || opts->stage_lds == 2) &&
                            totals->max_loc_atoms > 16;
     const bool gen2 = gen_split && opts->stage_lds < 0 && totals->max_loc_atoms <= 32 && totals->max_row_blocks <= 8;
+    // every subspace of at most 16 atoms: one launch of the two-wavefront
+    // dense kernel of the small class
+    const bool gen2_one = gen && !ovl && !mixed && opts->stage_lds < 0 && !gen_split &&
+                          totals->max_loc_atoms <= 16 && totals->max_row_blocks <= 8;
     const bool gen_packed = gen_split || (gen && opts->stage_lds == 1);
     KernelFn seed_fn = mixed ? pick_seed_mx(M, totals->max_row_blocks)
                        : ovl ? pick_seed_ovl(1, M, totals->max_row_blocks)
                        : gen2 ? pick_seed_gen2((hs.ns_pad + GEN2_T - 1) / GEN2_T, totals->max_row_blocks)
+                       : gen2_one ? pick_seed_gen2s((hs.ns_pad + GEN2_T - 1) / GEN2_T, totals->max_row_blocks)
                        : gen ? pick_seed_gen(M, totals->max_row_blocks, gen_packed)
                              : (r1 ? pick_seed_r1(M, totals->max_row_blocks) : pick_seed(stage, M));
-    const int seed_threads = gen2 ? GEN2_T : SEED_T;
+    const int seed_threads = (gen2 || gen2_one) ? GEN2_T : SEED_T;
     KernelFn seed_fn2 = ovl2 ? pick_seed_ovl(2, (hs.ns_pad + 127) / 128, totals->max_row_blocks) : nullptr;
     size_t seed_lds = (r1 || mixed || ovl) ? 0 : lds;
     // S != I: p, s, w, q, r and the dense inverse of the local overlap, laid
@@ -2170,6 +2175,10 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
     if (gen_split) {
         a.loc_lo = 17;
         a.loc_hi = totals->max_loc_atoms;
+    }
+    if (gen2_one) {
+        a.loc_lo = 0;
+        a.loc_hi = 16;
     }
     const int ms = mixed ? 1 : shift_ms(totals->max_proj_atoms, opts->shifts_per_lane);
     KernelFn shift_fn = mixed ? shift_mx_kernel() : pick_shift(totals->max_proj_atoms, ms);
