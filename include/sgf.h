@@ -478,8 +478,9 @@ sgf_status sgf_fermi_level(int32_t n_shifts, const double *z, const double *T, c
  * For real weights, (z S - H) G = I gives sum_{i in P(j)} eps_ij S_ji =
  * sum_{i in P(j)} rho_ij H_ji for every column.  d_z, d_w: device complex
  * [n_shifts] (interleaved re, im; the solve's shifts and weights); d_G:
- * complex [total_rows][n_shifts] as sgf_shifted_solve wrote it.  Sums in a
- * fixed order (bitwise repeatable).  SGF_EUNSUPPORTED above 512 shifts.
+ * complex [total_rows][n_shifts] as sgf_shifted_solve wrote it (the rows of
+ * a column the solve rejected hold no G, so their eps means nothing).  Sums
+ * in a fixed order (bitwise repeatable).  SGF_EUNSUPPORTED above 512 shifts.
  * Asynchronous on the stream. */
 sgf_status sgf_energy_density(int64_t total_rows, int32_t n_shifts, const double *d_z, const double *d_w,
                               const double *d_G, double *d_eps, void *stream);
@@ -550,13 +551,15 @@ sgf_status sgf_wp_propagate(const sgf_system *sys, int32_t n_rhs, double *d_psi,
  * d_rho: the columns and projected density matrix of a solve; d_eps: the
  * energy-density matrix on the same rows (sgf_energy_density from a kept G,
  * or the solve's sgf_solve_opts.eps_out), required when the system has an
- * overlap and ignored (may be NULL) when it has none.  p->overlap must match
- * the system.  Writes d_force [n_atoms][3] (eV/nm), cleared first.  FP64
+ * overlap and ignored (may be NULL) when it has none; d_status [n_cols]
+ * (nullable): with it, only SGF_CONVERGED columns count (a column the solve
+ * rejected holds no rho).  p->overlap must match the system.  Writes d_force [n_atoms][3] (eV/nm), cleared first.  FP64
  * atomics add the terms, in no fixed order: repeated runs agree to
  * rounding.  Asynchronous on the stream. */
 sgf_status sgf_band_forces(const sgf_system *sys, const double *d_xyz, const sgf_tb_params *p, int64_t n_cols,
                            const int64_t *d_cols, const int64_t *d_proj_off, const int32_t *d_proj_row,
-                           const double *d_rho, const double *d_eps, double *d_force, void *stream);
+                           const int32_t *d_status, const double *d_rho, const double *d_eps, double *d_force,
+                           void *stream);
 
 #ifdef __cplusplus
 }

@@ -115,7 +115,7 @@ def lib():
             "sgf_wp_bounds": [P, P, szt, P, P, P],
             "sgf_wp_terms": [dbl, dbl, P],
             "sgf_wp_propagate": [P, i32, P, dbl, i32, dbl, dbl, i32, P, szt, P],
-            "sgf_band_forces": [P, P, P, i64, P, P, P, P, P, P, P],
+            "sgf_band_forces": [P, P, P, i64, P, P, P, P, P, P, P, P],
             "sgf_energy_density": [i64, i32, P, P, P, P, P],
         }
         for name, args in sigs.items():
@@ -748,7 +748,7 @@ def wp_propagate(system: System, psi, h_fs: float, n_steps: int, e_min: float, e
 
 # --- band-structure forces ---------------------------------------------------------
 
-def band_forces(prep: Prepared, res: Result, params, xyz=None, eps=None, stream=None):
+def band_forces(prep: Prepared, res: Result, params, xyz=None, eps=None, converged_only=True, stream=None):
     """Band forces at fixed rho (and, with an overlap, fixed energy-density
     matrix ``eps``, one value per projection row, e.g. from
     energy_density): float64 [n_atoms, 3] on the device (eV/nm).  params:
@@ -760,8 +760,10 @@ def band_forces(prep: Prepared, res: Result, params, xyz=None, eps=None, stream=
     F = torch.empty((prep.system.n_atoms, 3), dtype=torch.float64, device=dev)
     sc = prep.system.c()
     tb = _tb_c(params)
+    status = res.status if converged_only else None
     _call("sgf_band_forces", ctypes.byref(sc), _ptr(d_xyz), ctypes.byref(tb), int(prep.cols.numel()), _ptr(prep.cols),
-          _ptr(prep.proj_off), _ptr(prep.proj_row), _ptr(res.rho), _ptr(eps), _ptr(F), _stream(stream))
+          _ptr(prep.proj_off), _ptr(prep.proj_row), _ptr(status), _ptr(res.rho), _ptr(eps), _ptr(F),
+          _stream(stream))
     return F
 
 

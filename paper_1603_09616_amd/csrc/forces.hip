@@ -72,10 +72,11 @@ __global__ __launch_bounds__(FORCE_T) void k_zero_f64(int64_t n, double *x) {
 
 __global__ __launch_bounds__(FORCE_T) void k_band_force(int64_t n_cols, int64_t n_atoms, const double *xyz,
                                                         sgf_tb_params p, const int64_t *cols, const int64_t *proj_off,
-                                                        const int32_t *proj_row, const double *rho, const double *eps,
-                                                        double *F) {
+                                                        const int32_t *proj_row, const int32_t *status, const double *rho,
+                                                        const double *eps, double *F) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_cols) return;
+    if (status && status[c] != SGF_CONVERGED) return;  // a rejected column holds no rho
     const int64_t j = cols[c];
     const int64_t C = j >> 2;
     if (j < 0 || C >= n_atoms) return;
@@ -126,8 +127,8 @@ using namespace sgf;
 
 extern "C" sgf_status sgf_band_forces(const sgf_system *sys, const double *d_xyz, const sgf_tb_params *p,
                                       int64_t n_cols, const int64_t *d_cols, const int64_t *d_proj_off,
-                                      const int32_t *d_proj_row, const double *d_rho, const double *d_eps,
-                                      double *d_force, void *stream) {
+                                      const int32_t *d_proj_row, const int32_t *d_status, const double *d_rho,
+                                      const double *d_eps, double *d_force, void *stream) {
     SGF_REQUIRE(sys && d_xyz && p && d_force, "sgf_band_forces: NULL argument");
     SGF_REQUIRE(sys->n_atoms > 0 && n_cols >= 0, "sgf_band_forces: bad sizes");
     SGF_REQUIRE(n_cols == 0 || (d_cols && d_proj_off && d_proj_row && d_rho), "sgf_band_forces: column layout is NULL");
@@ -142,8 +143,8 @@ extern "C" sgf_status sgf_band_forces(const sgf_system *sys, const double *d_xyz
     SGF_LAUNCHED();
     if (n_cols > 0) {
         k_band_force<<<(unsigned)((n_cols + FORCE_T - 1) / FORCE_T), FORCE_T, 0, st>>>(
-            n_cols, sys->n_atoms, d_xyz, *p, d_cols, d_proj_off, d_proj_row, d_rho, sys->s ? d_eps : nullptr,
-            d_force);
+            n_cols, sys->n_atoms, d_xyz, *p, d_cols, d_proj_off, d_proj_row, d_status, d_rho,
+            sys->s ? d_eps : nullptr, d_force);
         SGF_LAUNCHED();
     }
     return SGF_OK;

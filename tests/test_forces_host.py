@@ -41,7 +41,7 @@ def test_band_forces_arguments(sgf):
 
     def call(sys, p, n_cols=8, eps=FAKE, force=FAKE, xyz=FAKE):
         return L.sgf_band_forces(None if sys is None else ctypes.byref(sys), P(xyz), ctypes.byref(p), n_cols,
-                                 P(FAKE), P(FAKE), P(FAKE), P(FAKE), None if eps is None else P(eps),
+                                 P(FAKE), P(FAKE), P(FAKE), None, P(FAKE), None if eps is None else P(eps),
                                  None if force is None else P(force), None)
 
     assert call(None, tb) == sgf.SGF_EINVAL
