@@ -489,7 +489,7 @@ sgf_status sgf_energy_density(int64_t total_rows, int32_t n_shifts, const double
 /* Wavepacket propagation                                                     */
 /* ------------------------------------------------------------------------ */
 
-/* The wavepacket dynamics of Sec. 5 (Fig. 5) integrate d/dt Psi = -i H Psi
+/* The wavepacket dynamics of Sec. 3 (Fig. 2) integrate d/dt Psi = -i H Psi
  * / hbar (H in eV, t in fs, hbar = 0.6582119569509066 eV fs) in steps of
  * h (0.1 fs in the paper) with the tight-binding H in an orthogonal basis
  * (S = I).  One step applies exp(-i tau H), tau = h / hbar, as the Chebyshev

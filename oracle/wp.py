@@ -1,6 +1,6 @@
 """Oracle for the wavepacket step: time propagation of a hole wavepacket by
 the time-dependent Schroedinger equation with the tight-binding Hamiltonian
-(Sec. 5 of the paper, Fig. 5: d/dt Psi = -i H_WP Psi, time step 0.1 fs).
+(Sec. 3 of the paper, transport with wavepacket dynamics, Fig. 2: d/dt Psi = -i H_WP Psi, time step 0.1 fs).
 
 TEST INFRASTRUCTURE ONLY, under the same rule as the rest of ``oracle``: only
 ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of

@@ -1,5 +1,5 @@
 // wp.hip -- time propagation of wavepackets with the tight-binding H
-// (Sec. 5 of the paper: d/dt Psi = -i H Psi / hbar, steps of 0.1 fs), by the
+// (Sec. 3 of the paper, Fig. 2: d/dt Psi = -i H Psi / hbar, steps of 0.1 fs), by the
 // Chebyshev expansion of the step operator (Tal-Ezer and Kosloff 1984):
 // with H = a X + b (spectrum of X in [-1, 1], a and b from Gershgorin
 // bounds) and tau = h / hbar,
