@@ -212,3 +212,53 @@ def test_overlap_forces_full_bundle_sampled(sgf, O):
         assert np.abs(F[A] - Fr).max() <= 1e-9 * scale
     del res, eps
     torch.cuda.empty_cache()
+
+
+def test_forces_skip_unconverged_columns(sgf, O):
+    """With a small max_iter some columns stop at SGF_MAXITER.  The default
+    status filter leaves them out: the forces equal the oracle's over the
+    columns the GPU solve converged (the oracle's fully converged rho on
+    those; which columns converge within max_iter is decided by the
+    residual, and the two sides may freeze a column an iteration apart, so
+    the mask is the GPU's).  Without the filter the stopped columns count
+    too: the difference of the two force arrays is the oracle's force sum
+    over the stopped columns, taken on the GPU's rho of those columns (an
+    unconverged iterate near a resonance depends on rounding, so its rho is
+    the GPU's own)."""
+    O, fo = O
+    wl = W.bundle_workload(2, 1, 14, config_no=121)
+    cols = np.arange(wl.n_orb)
+    s = sgf.system_for(wl)
+    prep = sgf.prepare(s, cols, radius=1.0, prune=True)
+    res = sgf.solve_prepared(prep, wl.z, wl.w, tol=1e-12, max_iter=52)
+    st = res.status.cpu().numpy()
+    n_bad = int(np.sum(st != sgf.CONVERGED))
+    print(f"  {n_bad} of {cols.size} columns stopped at max_iter", flush=True)
+    assert 0 < n_bad < cols.size and np.all((st == sgf.CONVERGED) | (st == sgf.MAXITER))
+    F = sgf.band_forces(prep, res, wl.tb).cpu().numpy()
+    F_all = sgf.band_forces(prep, res, wl.tb, converged_only=False).cpu().numpy()
+    b = O.system_for(wl)
+    ref = O.shifted_solve(b, wl.xyz, cols, wl.z, wl.w, tol=1e-12, radius=1.0, prune=True, threads=8)
+    assert np.all(ref.status == 0)
+    off = res.proj_off.cpu().numpy()
+    np.testing.assert_array_equal(off, ref.proj_ptr)
+
+    class Part:
+        pass
+
+    def part_of(sel, rho):
+        p = Part()
+        rows = np.concatenate([np.arange(off[c], off[c + 1]) for c in sel])
+        p.proj_ptr = np.concatenate([[0], np.cumsum(off[sel + 1] - off[sel])])
+        p.proj_row, p.rho = ref.proj_row[rows], rho[rows]
+        return p
+
+    ok, bad = np.nonzero(st == sgf.CONVERGED)[0], np.nonzero(st != sgf.CONVERGED)[0]
+    Fr = fo.band_forces(wl.xyz, wl.tb, part_of(ok, ref.rho), cols[ok], wl.n_atoms)
+    Fr_bad = fo.band_forces(wl.xyz, wl.tb, part_of(bad, res.rho.cpu().numpy()), cols[bad], wl.n_atoms)
+    scale = np.abs(F_all).max()
+    e = np.abs(F - Fr).max() / np.abs(Fr).max()
+    e_all = np.abs((F_all - F) - Fr_bad).max() / scale
+    print(f"  converged only: rel err {e:.2e}; stopped columns' share: {e_all:.2e}", flush=True)
+    assert e < 1e-9 and e_all < 1e-12
+    assert np.abs(Fr_bad).max() > 1e-3 * scale

@@ -1,0 +1,182 @@
+"""GPU parity at full workload sizes and per shift.
+
+* The 1,000,300-atom share (256 shifts, FP64, S = I, R = 1.0 nm pruned): all
+  4,001,200 columns in the streamed launches the benchmark times (density
+  matrix only), and a seeded subset with G kept; sampled columns are
+  recomputed by the oracle.  At 256 shifts the seed pass holds four shifts
+  per lane and the shift pass sees the share's largest projection sets.
+* Per-shift accuracy of the diagonal element: |dG_jj(z_k)| / |G_jj(z_k)|
+  for every shift, against the oracle and against the dense restricted
+  solve (the plain definition).  At tol 1e-12 the solver meets 1e-10
+  normwise per column; the per-shift bar of 1e-10 needs tol 1e-13 (a shift
+  frozen at tol carries an absolute error up to tol/eta, which is large
+  relative to a small |G_jj| at energies where the column has little
+  weight).
+* The unpruned bundle (~126-atom subspaces, ~505 orbitals) at the headline
+  tol 1e-12, in the benchmark's launch shape.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64_RTOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def sgf():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1603_09616_amd as sgf
+    sgf.lib()
+    return sgf
+
+
+@pytest.fixture(scope="module")
+def O():
+    import oracle
+    oracle.build(force=False)
+    return oracle
+
+
+class Sub:
+    """Outputs of a subset of columns, in the oracle's layout."""
+
+    def __init__(self, res, pick, with_g=True):
+        import torch
+        off = res.proj_off.cpu().numpy()
+        rows = np.concatenate([np.arange(off[c], off[c + 1]) for c in pick])
+        idx = torch.as_tensor(rows, device=res.rho.device)
+        self.proj_off = np.concatenate([[0], np.cumsum(off[pick + 1] - off[pick])])
+        self.proj_row = res.proj_row[idx].cpu().numpy()
+        self.G = res.G[idx].cpu().numpy() if with_g else None
+        self.rho = res.rho[idx].cpu().numpy()
+        self.status = res.status.cpu().numpy()[pick]
+        self.iters = res.iters.cpu().numpy()[pick]
+
+
+def per_column_errors(got, ref):
+    """(G normwise per column, G_jj worst shift, rho normwise per column)."""
+    e_g = e_jj = e_rho = 0.0
+    for c in range(ref.proj_ptr.size - 1):
+        a, b = ref.proj_ptr[c], ref.proj_ptr[c + 1]
+        e_rho = max(e_rho, np.abs(got.rho[a:b] - ref.rho[a:b]).max() / max(np.abs(ref.rho[a:b]).max(), 1e-300))
+        if got.G is None:
+            continue
+        e_g = max(e_g, np.abs(got.G[a:b] - ref.G[a:b]).max() / np.abs(ref.G[a:b]).max())
+        j = a + int(np.nonzero(ref.proj_row[a:b] == ref._cols[c])[0][0])
+        e_jj = max(e_jj, float((np.abs(got.G[j] - ref.G[j]) / np.abs(ref.G[j])).max()))
+    return e_g, e_jj, e_rho
+
+
+def check_layout(got, ref):
+    np.testing.assert_array_equal(got.proj_off, ref.proj_ptr)
+    np.testing.assert_array_equal(got.proj_row, ref.proj_row)
+    np.testing.assert_array_equal(got.status, ref.status)
+
+
+def test_large_share_256_shifts(sgf, O):
+    """All 4,001,200 columns of the 1,000,300-atom share in streamed launches
+    (rho only, a 64 GiB workspace as in the benchmark), then 30,000 seeded
+    columns with G kept; 200 sampled columns of each against the oracle."""
+    import torch
+    torch.cuda.empty_cache()
+    wl = W.config_large()
+    assert wl.z.size == 256 and wl.n_atoms == 1000300
+    s = sgf.system_for(wl)
+    prep = sgf.prepare(s, wl.columns, radius=wl.radius, prune=True)
+    t = prep.plan.totals
+    print(f"  plans: <= {t.max_loc_atoms} local atoms, <= {t.max_row_blocks} blocks per row, "
+          f"<= {t.max_proj_atoms} projection atoms", flush=True)
+    batch = sgf.batch_limit(prep, wl.z.size, 64 << 30)
+    res = sgf.solve_prepared(prep, wl.z, wl.w, tol=wl.tol, g_out=False, batch_cols=batch)
+    torch.cuda.synchronize()
+    st = res.status.cpu().numpy()
+    assert np.all(st == sgf.CONVERGED)
+    b = O.system_for(wl)
+    pick = np.sort(np.random.default_rng(55).choice(wl.columns.size, 200, replace=False))
+    ref = O.solve_workload(wl, b, cols=wl.columns[pick], threads=8)
+    ref._cols = wl.columns[pick]
+    got = Sub(res, pick, with_g=False)
+    check_layout(got, ref)
+    _, _, e_rho = per_column_errors(got, ref)
+    print(f"  all columns, {res.proj_off.numel() - 1} solved in {wl.columns.size // batch + 1} launches: "
+          f"rho {e_rho:.2e}", flush=True)
+    assert e_rho < FP64_RTOL
+    del res, prep
+    torch.cuda.empty_cache()
+
+    sub = W.config_large(n_columns=30000)
+    prep = sgf.prepare(s, sub.columns, radius=sub.radius, prune=True)
+    res = sgf.solve_prepared(prep, sub.z, sub.w, tol=sub.tol)
+    pick = np.sort(np.random.default_rng(56).choice(sub.columns.size, 200, replace=False))
+    ref = O.solve_workload(sub, b, cols=sub.columns[pick], threads=8)
+    ref._cols = sub.columns[pick]
+    got = Sub(res, pick)
+    check_layout(got, ref)
+    e_g, e_jj, e_rho = per_column_errors(got, ref)
+    print(f"  30,000-column subset: G {e_g:.2e}, G_jj worst shift {e_jj:.2e}, rho {e_rho:.2e}", flush=True)
+    assert e_g < FP64_RTOL and e_rho < FP64_RTOL
+    assert e_jj < 1e-9   # per shift at tol 1e-12 (see the module docstring)
+    del res, prep, s
+    torch.cuda.empty_cache()
+
+
+def test_per_shift_g_jj_at_tol_1e13(sgf, O):
+    """At tol 1e-13 every shift's G_jj is within 1e-10 (relative, per shift)
+    of the oracle's and of the dense restricted solve, on every column of a
+    small bundle (all four orbitals of 60 atoms, 128 shifts)."""
+    wl = W.bundle_workload(3, 3, 60, n_shifts=128, config_no=91, tol=1e-13)
+    cols = wl.columns[:240]
+    got = sgf.solve_workload(wl, cols=cols).numpy()
+    b = O.system_for(wl)
+    ref = O.solve_workload(wl, b, cols=cols, threads=8)
+    ref._cols = cols
+    check_layout(got, ref)
+    e_g, e_jj, e_rho = per_column_errors(got, ref)
+    worst_exact = 0.0
+    for c in range(0, cols.size, 3):
+        j = int(cols[c])
+        full = O.solve_full(b, wl.xyz, j, wl.z[:1], radius=wl.radius, prune=True, max_iter=1)
+        H, S, idx = O.local_dense(b, full.loc_atoms)
+        x = O.exact_columns(H, S, int(np.nonzero(idx == j)[0][0]), wl.z)[int(np.nonzero(idx == j)[0][0])]
+        a, bb = got.proj_off[c], got.proj_off[c + 1]
+        d = a + int(np.nonzero(got.proj_row[a:bb] == j)[0][0])
+        worst_exact = max(worst_exact, float((np.abs(got.G[d] - x) / np.abs(x)).max()))
+    print(f"  tol 1e-13: G {e_g:.2e}, G_jj worst shift vs oracle {e_jj:.2e}, vs dense solve {worst_exact:.2e}, "
+          f"rho {e_rho:.2e}", flush=True)
+    assert e_jj < FP64_RTOL and worst_exact < FP64_RTOL
+    assert e_g < FP64_RTOL and e_rho < FP64_RTOL
+
+
+def test_bundle_unpruned_headline_tol(sgf, O):
+    """The full bundle geometry without pruning (~126-atom, ~505-orbital
+    subspaces), 4096 seeded columns at tol 1e-12 in the benchmark's launch
+    shape (as many columns per launch as a 112 GiB workspace holds); 48
+    sampled columns against the oracle at the 1e-10 bar."""
+    import torch
+    torch.cuda.empty_cache()
+    wl = W.config_bundle(n_columns=4096)
+    s = sgf.system_for(wl)
+    prep = sgf.prepare(s, wl.columns, radius=wl.radius, prune=False)
+    t = prep.plan.totals
+    assert t.max_loc_atoms > 64
+    batch = sgf.batch_limit(prep, wl.z.size, 112 << 30)
+    res = sgf.solve_prepared(prep, wl.z, wl.w, tol=wl.tol, batch_cols=batch)
+    torch.cuda.synchronize()
+    assert np.all(res.status.cpu().numpy() == sgf.CONVERGED)
+    pick = np.sort(np.random.default_rng(57).choice(wl.columns.size, 48, replace=False))
+    ref = O.solve_workload(wl, cols=wl.columns[pick], prune=False, threads=8)
+    ref._cols = wl.columns[pick]
+    got = Sub(res, pick)
+    check_layout(got, ref)
+    e_g, e_jj, e_rho = per_column_errors(got, ref)
+    print(f"  unpruned, <= {t.max_loc_atoms} local atoms: G {e_g:.2e}, G_jj worst shift {e_jj:.2e}, "
+          f"rho {e_rho:.2e}, iterations {got.iters.mean():.1f} vs {ref.iters.mean():.1f}", flush=True)
+    assert e_g < FP64_RTOL and e_rho < FP64_RTOL
+    assert abs(got.iters.mean() - ref.iters.mean()) <= 0.1 * ref.iters.mean() + 2
+    del res, prep, s
+    torch.cuda.empty_cache()
