@@ -38,20 +38,125 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def pass_flops(nblk, nl, nrow, iters, nk, ns):
-    """Algorithmic FP64 flops of the two passes (per launch set of one solve).
+def model_flops(nblk, nrow, iters, nk):
+    """Algorithmic FP64 flops of the method's two arithmetic steps, per launch
+    set of one solve (the per-unit counts the roofline is stated in):
 
-    Seed pass, per column-iteration: 64 per local 4x4 block (real block x
-    complex vector) + 44 per local orbital (w = z_s p - Hp, mu, s update,
-    rho', ||s||^2, p update); per shift-iteration while the shift is active:
-    28 (pi recurrence and freeze test).
-    Shift pass, per shift-step: 30 (UL pivot: diagonal, one complex product,
-    reciprocal, next multiplier) + 8 per projection row (Horner step).
-    """
+    seed operator w = z_s p - H p: 64 per local 4x4 block per
+    column-iteration (a real block times a complex vector: 16 complex-by-real
+    multiply-adds);
+    projected G updates X^k += alpha^k P^k, P^k = r_P / pi^k + beta^k P^k:
+    16 per projection row per active shift-step (two complex multiply-adds).
+    Returns (seed operator, projected updates)."""
+    a4 = float(np.sum(iters * 64.0 * nblk))
+    a8 = float(np.sum(nk.sum(axis=1).astype(np.float64) * 16.0 * nrow))
+    return a4, a8
+
+
+def executed_flops(nblk, nl, nrow, iters, nk):
+    """FP64 flops the two kernels execute (a fuller count than model_flops).
+
+    Seed pass, per column-iteration: 64 per local 4x4 block + 44 per local
+    orbital (w = z_s p - Hp, mu, s update, rho', ||s||^2, p update); per
+    shift-iteration while the shift is active: 28 (pi recurrence and freeze
+    test).  Shift pass, per shift-step: 30 (UL pivot: diagonal, one complex
+    product, reciprocal, next multiplier) + 8 per projection row (Horner
+    step)."""
     nk_sum = nk.sum(axis=1).astype(np.float64)
     seed = float(np.sum(iters * (64.0 * nblk + 44.0 * nl)) + 28.0 * nk_sum.sum())
     shift = float(np.sum(nk_sum * (30.0 + 8.0 * nrow)))
     return seed, shift
+
+
+def path_bytes(nrow, iters, ns, g_out):
+    """Algorithmic HBM bytes of one solve: the seed pass writes, per
+    column-iteration, 1/alpha and beta/alpha (32 B) and the residual on the
+    projection rows (16 B per row), plus r_0; the shift pass reads that
+    history back once and writes G (16 B per row and shift, when kept), rho
+    (8 B per row) and per shift the residual (8 B) and the step count (4 B)."""
+    hist = float(np.sum(iters * (32.0 + 16.0 * nrow) + 16.0 * nrow))
+    out = float(np.sum(nrow) * (8.0 + (16.0 * ns if g_out else 0.0))) + iters.size * ns * 12.0
+    return 2.0 * hist + out
+
+
+def seed_kernel_name(ns, max_row_blocks):
+    m = (ns + 63) // 64
+    m = {1: 1, 2: 2, 3: 4, 4: 4}.get(m, 8)
+    b = 5 if max_row_blocks <= 5 else 6 if max_row_blocks <= 6 else 8
+    return f"k_seed_r1<{m}, {b}>"
+
+
+def shift_kernel_name(max_proj_atoms):
+    return f"k_shift<{min(max(max_proj_atoms, 1), 8)}, 1>"
+
+
+def solve_figures(prep, res, ns, seed_ms, shift_ms, g_out):
+    """Roofline figures of one S = I solve from its plan and per-column
+    counts: the seed pass against the FP64 vector peak (seed-operator flops
+    only), the whole path (both passes, both flop terms), the kernels'
+    executed count, and the algorithmic HBM bytes of the path."""
+    plan = prep.plan
+    cp = prep.col_plan.cpu().numpy()
+    nl = 4 * np.diff(plan.atom_off.cpu().numpy())[cp]
+    nblk = np.diff(plan.blk_off.cpu().numpy())[cp]
+    nrow = 4 * np.diff(plan.pa_off.cpu().numpy())[cp]
+    iters = res.iters.cpu().numpy().astype(np.float64)
+    nk = res.shift_iters.cpu().numpy()
+    a4, a8 = model_flops(nblk, nrow, iters, nk)
+    e_seed, e_shift = executed_flops(nblk, nl, nrow, iters, nk)
+    nbytes = path_bytes(nrow, iters, ns, g_out)
+    t = plan.totals
+    seed_tf = a4 / (seed_ms * 1e-3) / 1e12
+    whole_tf = (a4 + a8) / ((seed_ms + shift_ms) * 1e-3) / 1e12
+    r1 = t.max_loc_atoms <= 16 and t.max_row_blocks <= 8
+    return {
+        "seed_kernel": seed_kernel_name(ns, t.max_row_blocks) if r1 else "k_seed (LDS-staged or global operator)",
+        "shift_kernel": shift_kernel_name(t.max_proj_atoms),
+        "column_iterations": float(iters.sum()), "active_shift_steps": float(nk.sum()),
+        "mean_local_blocks": float(nblk.mean()), "mean_local_orbitals": float(nl.mean()),
+        "mean_projection_rows": float(nrow.mean()),
+        "seed_pass": {"ms": seed_ms, "tflop": a4 / 1e12, "tflops": seed_tf, "frac": seed_tf / PEAK_FP64_TFLOPS,
+                      "flop_model": "64 per local 4x4 block per column-iteration"},
+        "whole_path": {"ms": seed_ms + shift_ms, "tflop": (a4 + a8) / 1e12, "tflops": whole_tf,
+                       "frac": whole_tf / PEAK_FP64_TFLOPS,
+                       "flop_model": "64 per local block per column-iteration + 16 per projection row per "
+                                     "active shift-step"},
+        "executed": {"seed_tflop": e_seed / 1e12, "shift_tflop": e_shift / 1e12,
+                     "seed_tflops": e_seed / (seed_ms * 1e-3) / 1e12,
+                     "shift_tflops": e_shift / (shift_ms * 1e-3) / 1e12},
+        "hbm_algorithmic": {"bytes": nbytes, "GBps": nbytes / ((seed_ms + shift_ms) * 1e-3) / 1e9,
+                            "frac": nbytes / ((seed_ms + shift_ms) * 1e-3) / 1e9 / PEAK_HBM_GBS},
+    }
+
+
+def roofline_line(fig, seed_ms, shift_ms, launches, traffic_seed, traffic_shift, hbm_counted):
+    """The bench line's roofline object: the longer of the two passes (the
+    dominant kernel) at its algorithmic flop rate (model_flops) against the
+    FP64 vector peak, timed live per launch with HIP events on the solve
+    stream; the whole path and the HBM figures beside it."""
+    seed_dom = seed_ms >= shift_ms
+    if seed_dom:
+        kernel, ms, tflop, model = fig["seed_kernel"], seed_ms, fig["seed_pass"]["tflop"], fig["seed_pass"]["flop_model"]
+        traffic = traffic_seed
+    else:
+        tflop = fig["whole_path"]["tflop"] - fig["seed_pass"]["tflop"]
+        kernel, ms, model = fig["shift_kernel"], shift_ms, "16 per projection row per active shift-step"
+        traffic = traffic_shift
+    achieved = tflop / (ms * 1e-3)   # per launch: (tflop / launches) / (ms / launches)
+    return {
+        "kernel": kernel, "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+        "frac": achieved / PEAK_FP64_TFLOPS,
+        "traffic": traffic,
+        "traffic_source": "recorded FETCH_SIZE + WRITE_SIZE per launch for this kernel source (not measured in "
+                          "this run)" if traffic is not None else "no counter record for this kernel source",
+        "flop_model": model, "launches_per_step": launches, "ms_per_launch": ms / launches,
+        "passes": {"seed": fig["seed_pass"], "shift_ms": shift_ms},
+        "whole_path": fig["whole_path"],
+        "executed_flops": fig["executed"],
+        "hbm": {"algorithmic": fig["hbm_algorithmic"], "counters": hbm_counted},
+        "per_column": {k: fig[k] for k in ("column_iterations", "active_shift_steps", "mean_local_blocks",
+                                            "mean_local_orbitals", "mean_projection_rows")},
+    }
 
 
 def train_scheduler(sgf, W, dev, n_logged=50000):
@@ -201,51 +306,94 @@ def wp_stream(sgf, W, dev, steps=10):
             "peak_GBps": PEAK_HBM_GBS, "steps": steps, "cases": cases}
 
 
-def extra_workloads(sgf, W, dev, ws_gib, check_n):
-    """The other two workloads, one timed solve each after a warm-up:
-    the overlap bundle (S != I, per-column radius U[0.6, 1.4] nm, 256 shifts,
-    all 473,200 columns) and the 1,000,300-atom share (256 shifts, all
-    4,001,200 columns, density matrix only: G alone would be 328 GB), both
-    FP64 in workspace-sized launches.  Returns the timings and, per workload,
-    the outputs of `check_n` seeded columns for the oracle comparison."""
+def extra_workloads(sgf, W, dev, ws_gib, check_n, reps=5, only=None):
+    """The other workloads, each a warm-up solve and then `reps` timed solves
+    (median), with the seed and shift passes timed per launch by HIP events:
+
+    chain: the 2000-site chain, 16 columns on the whole system, 64 shifts;
+    bundle_unpruned: the bundle with unpruned R = 1.0 nm subspaces (~126
+      atoms, ~505 orbitals), all 473,200 columns, 128 shifts;
+    bundle_overlap_uneven: the overlap bundle (S != I, per-column radius
+      U[0.6, 1.4] nm, 256 shifts, all 473,200 columns);
+    large_share: the 1,000,300-atom share (256 shifts, all 4,001,200 columns,
+      density matrix only: G alone would be 328 GB) in streamed launches.
+
+    All FP64 at the workloads' own tolerances, in workspace-sized launches.
+    Returns the timings and, per workload, the outputs of `check_n` seeded
+    columns (all of them for the chain) for the oracle comparison."""
     import torch
     out, keep = {}, {}
-    for name, wl, g_out in (("bundle_overlap_uneven", W.config_bundle_overlap(), True),
-                            ("large_share", W.config_large(), False)):
+    cases = (("chain", W.config_chain(), True, True, "2000-site chain (S = I, whole system)"),
+             ("bundle_unpruned", W.config_bundle(), True, False,
+              "bundle, R = 1.0 nm unpruned subspaces (S = I)"),
+             ("bundle_overlap_uneven", W.config_bundle_overlap(), True, True,
+              "bundle (S != I, radius per column U[0.6, 1.4] nm)"),
+             ("large_share", W.config_large(), False, True, "bundle (1,000,300 atoms)"))
+    for name, wl, g_out, prune, what in cases:
+        if only is not None and name not in only:
+            continue
         s = sgf.system_for(wl)
-        prep = sgf.prepare(s, wl.columns, radius=wl.radius, radius_per_col=wl.radius_per_col, prune=True)
+        prep = sgf.prepare(s, wl.columns, radius=wl.radius, radius_per_col=wl.radius_per_col, prune=prune)
         ns = wl.z.size
         batch = sgf.batch_limit(prep, ns, int(ws_gib * (1 << 30)))
         buf = None
-        for rep in range(2):
+        n_reps = reps if name != "bundle_unpruned" else max(2, reps // 2)
+        times, seeds, shifts = [], [], []
+        for rep in range(n_reps + 1):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             res = sgf.solve_prepared(prep, wl.z, wl.w, tol=wl.tol, g_out=g_out, batch_cols=batch, out=buf,
-                                     profile=rep == 1)
-            prof = sgf.solve_profile() if rep == 1 else None
+                                     profile=True, shift_iters=True)
+            prof = sgf.solve_profile()
             torch.cuda.synchronize()
             ms = (time.perf_counter() - t0) * 1e3
             buf = res._out
+            if rep:
+                times.append(ms)
+                seeds.append(prof[0])
+                shifts.append(prof[1])
+            log(f"[bench] {name}: {'warm-up' if rep == 0 else f'rep {rep}/{n_reps}'} {ms:.1f} ms")
+        ms, seed_ms, shift_ms = (float(np.median(v)) for v in (times, seeds, shifts))
         st = res.status.cpu().numpy()
         conv = int(np.sum(res.resid.cpu().numpy() <= wl.tol))
         t = prep.plan.totals
-        out[name] = {"workload": wl.name + (" (S != I, radius per column U[0.6, 1.4] nm)" if wl.tb.overlap else
-                                            " (1,000,300 atoms)"),
-                     "atoms": int(s.n_atoms), "columns": int(wl.columns.size), "shifts": int(ns), "tol": wl.tol,
-                     "outputs": "G and rho" if g_out else "rho only", "ms": ms, "solves_per_s": conv / (ms * 1e-3),
-                     "seed_ms": prof[0], "shift_ms": prof[1], "launches": prof[2], "batch_cols": int(batch),
+        out[name] = {"workload": wl.name + " " + what if wl.kind != "chain" else what,
+                     "atoms": int(wl.n_orb if wl.kind == "chain" else wl.n_atoms), "columns": int(wl.columns.size), "shifts": int(ns), "tol": wl.tol,
+                     "pruned": prune, "outputs": "G and rho" if g_out else "rho only", "reps": n_reps,
+                     "ms": ms, "ms_all_reps": times, "solves_per_s": conv / (ms * 1e-3),
+                     "seed_ms": seed_ms, "shift_ms": shift_ms, "launches": prof[2], "batch_cols": int(batch),
                      "columns_not_converged": int(np.sum(st != 0)),
                      "iters_mean": float(res.iters.float().mean()), "max_loc_atoms": int(t.max_loc_atoms)}
-        log(f"[bench] {name}: {wl.columns.size} columns x {ns} shifts in {ms:.1f} ms "
-            f"({conv / (ms * 1e-3):.3g} solves/s, {prof[2]} launches)")
-        if wl.tb.overlap:
+        if not wl.tb or not wl.tb.overlap:
+            fig = solve_figures(prep, res, ns, seed_ms, shift_ms, g_out)
+            out[name]["roofline"] = {"kernel": fig["seed_kernel"] if seed_ms >= shift_ms else fig["shift_kernel"],
+                                     "seed_pass": fig["seed_pass"], "whole_path": fig["whole_path"],
+                                     "hbm_algorithmic": fig["hbm_algorithmic"], "executed": fig["executed"]}
+        else:
+            cp = prep.col_plan.cpu().numpy()
+            nl = 4 * np.diff(prep.plan.atom_off.cpu().numpy())[cp].astype(np.float64)
+            nblk = np.diff(prep.plan.blk_off.cpu().numpy())[cp].astype(np.float64)
+            it = res.iters.cpu().numpy().astype(np.float64)
+            # H p and S p (64 each per block) and the dense S_L^{-1} s (4 per entry) per column-iteration
+            f = float(np.sum(it * (128.0 * nblk + 4.0 * nl * nl)))
+            out[name]["roofline"] = {"seed_pass": {"ms": seed_ms, "tflop": f / 1e12,
+                                                   "tflops": f / (seed_ms * 1e-3) / 1e12,
+                                                   "frac": f / (seed_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+                                                   "flop_model": "128 per local block (H p, S p) + 4 n_L^2 "
+                                                                 "(dense S_L^-1 s) per column-iteration"}}
+        log(f"[bench] {name}: {wl.columns.size} columns x {ns} shifts in {ms:.1f} ms (median of {n_reps}; "
+            f"{conv / (ms * 1e-3):.3g} solves/s, {prof[2]} launches)")
+        if wl.tb and wl.tb.overlap:
             out[name]["after_rho"] = overlap_forces(sgf, prep, res, wl)
-        pick = np.sort(np.random.default_rng(1603).choice(wl.columns.size, check_n, replace=False))
+        n_check = wl.columns.size if name == "chain" else min(check_n, wl.columns.size)
+        pick = np.sort(np.random.default_rng(1603).choice(wl.columns.size, n_check, replace=False))
+        if name == "bundle_unpruned":
+            pick = pick[:64]
         off = prep.proj_off.cpu().numpy()
         rows = np.concatenate([np.arange(off[c], off[c + 1]) for c in pick])
         idx = torch.as_tensor(rows, device=dev)
         keep[name] = (wl, pick, None if res.G is None else res.G[idx].cpu().numpy(), res.rho[idx].cpu().numpy(),
-                      st[pick])
+                      st[pick], prune)
         del res, buf, prep, s
         torch.cuda.empty_cache()
     return out, keep
@@ -295,24 +443,26 @@ def check_extra(keep):
     import oracle
     threads = min(len(os.sched_getaffinity(0)), int(os.environ.get("OMP_NUM_THREADS", 1 << 30)))
     acc = {}
-    for name, (wl, pick, G, rho, st) in keep.items():
+    for name, (wl, pick, G, rho, st, prune) in keep.items():
         b = oracle.system_for(wl)
         t0 = time.perf_counter()
-        rpc = None if wl.radius_per_col is None else wl.radius_per_col[pick]
-        ref = oracle.shifted_solve(b, wl.xyz, wl.columns[pick], wl.z, wl.w, tol=wl.tol, radius=wl.radius,
-                                   radius_per_col=rpc, prune=True, threads=threads)
+        ref = oracle.solve_workload(wl, b, cols=wl.columns[pick], prune=prune, threads=threads)
         dt = time.perf_counter() - t0
         a = {"columns": int(pick.size), "oracle_s": dt, "oracle_threads": threads}
-        e_rho = e_g = 0.0
+        e_rho = e_g = e_jj = 0.0
         for i in range(pick.size):
             lo, hi = ref.proj_ptr[i], ref.proj_ptr[i + 1]
             e_rho = max(e_rho, np.abs(rho[lo:hi] - ref.rho[lo:hi]).max() / max(np.abs(ref.rho[lo:hi]).max(), 1e-300))
             if G is not None:
                 e_g = max(e_g, np.abs(G[lo:hi] - ref.G[lo:hi]).max() / np.abs(ref.G[lo:hi]).max())
+                d = lo + int(np.nonzero(ref.proj_row[lo:hi] == wl.columns[pick[i]])[0][0])
+                e_jj = max(e_jj, float((np.abs(G[d] - ref.G[d]) / np.abs(ref.G[d])).max()))
         a["rho_normwise"] = e_rho
         if G is not None:
             a["G_rows_normwise"] = e_g
+            a["G_jj_worst_shift"] = e_jj
         a["not_converged"] = int(np.sum(st != 0))
+        a["status_equal"] = bool(np.array_equal(st, ref.status))
         acc[name] = a
         log(f"[bench] {name}: oracle on {pick.size} columns in {dt:.1f} s; rho err {e_rho:.2e}")
     return acc
@@ -395,6 +545,8 @@ def main(argv=None):
     ap.add_argument("--spmv-only", action="store_true",
                     help="only the operator-apply measurement and a 1 GiB copy (for counter passes)")
     ap.add_argument("--wp-only", action="store_true", help="only the wavepacket-propagation measurement")
+    ap.add_argument("--only", default="", help="comma-separated subset of the extra workloads (chain, "
+                    "bundle_unpruned, bundle_overlap_uneven, large_share)")
     ap.add_argument("--extra-only", action="store_true",
                     help="only the overlap and 1,000,300-atom workloads (one timed solve each)")
     args = ap.parse_args(argv)
@@ -407,6 +559,7 @@ def main(argv=None):
     import torch
     import paper_1603_09616_amd as sgf
     import workloads as W
+    only = set(x for x in args.only.split(",") if x) or None
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
@@ -418,7 +571,7 @@ def main(argv=None):
         print(json.dumps({"wavepacket": wp_stream(sgf, W, dev)}), flush=True)
         return 0
     if args.extra_only:
-        extra, _ = extra_workloads(sgf, W, dev, min(args.ws_gib, 64.0), 1)
+        extra, _ = extra_workloads(sgf, W, dev, min(args.ws_gib, 64.0), 1, only=only)
         print(json.dumps({"other_workloads": extra}), flush=True)
         return 0
     wl = W.config_bundle()
@@ -506,20 +659,19 @@ def main(argv=None):
     iters = res.iters.cpu().numpy().astype(np.float64)
     status = res.status.cpu().numpy()
     resid = res.resid.cpu().numpy()
-    nk = res.shift_iters.cpu().numpy()
     converged = int(np.sum(resid <= wl.tol))
-    plan = prep.plan
-    cp = prep.col_plan.cpu().numpy()
-    nl = 4 * np.diff(plan.atom_off.cpu().numpy())[cp]
-    nblk = np.diff(plan.blk_off.cpu().numpy())[cp]
-    nrow = 4 * np.diff(plan.pa_off.cpu().numpy())[cp]
-    f_seed, f_shift = pass_flops(nblk, nl, nrow, iters, nk, ns)
     value = converged / (ms_step * 1e-3)
-    seed_tf = f_seed / (seed_ms * 1e-3) / 1e12
-    shift_tf = f_shift / (shift_ms * 1e-3) / 1e12
-    dominant = "k_shift" if shift_ms >= seed_ms else "k_seed"
-    dom_ms, dom_f = (shift_ms, f_shift) if dominant == "k_shift" else (seed_ms, f_seed)
-    achieved = dom_f / (dom_ms * 1e-3) / 1e12
+    fig = solve_figures(prep, res, ns, seed_ms, shift_ms, not args.no_g)
+    traffic_seed = recorded_traffic(fig["seed_kernel"], "seed")
+    traffic_shift = recorded_traffic(fig["shift_kernel"], "shift")
+    hbm_counted = None
+    if traffic_seed is not None and traffic_shift is not None:
+        tb = traffic_seed + traffic_shift
+        hbm_counted = {"bytes": tb, "GBps": tb / ((seed_ms + shift_ms) * 1e-3) / 1e9,
+                       "frac": tb / ((seed_ms + shift_ms) * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                       "source": "FETCH_SIZE and WRITE_SIZE of both passes recorded by rocprofv3 for this kernel "
+                                 "source (profiles/pmc_traffic.json), scaled by a 1 GiB copy; not measured in "
+                                 "this run"}
     variants = {"fp64_batched_learned": {"ms_per_step": ms_step, "solves_per_s": value, "seed_ms": seed_ms,
                                          "shift_ms": shift_ms, "launches": launches, "batch_cols": batch,
                                          "order": "learned", "tol": wl.tol, "launch": launch}}
@@ -535,6 +687,8 @@ def main(argv=None):
         mixed_batch = args.batch or sgf.batch_limit(p_probe, ns, int(args.ws_gib * (1 << 30)), precision="mixed")
         specs = [("fp64_batched", "natural", batch, "fp64", wl.tol, launch),
                  ("fp64_plain", "natural", args.plain_batch, "fp64", wl.tol, None),
+                 ("fp64_plain_learned", "learned", args.plain_batch, "fp64", wl.tol, None),
+                 ("fp64_batched_learned_tol1e-13", "learned", batch, "fp64", 1e-13, launch),
                  ("mixed_batched_learned", "learned", mixed_batch, "mixed", 1e-5, None),
                  ("fp64_batched_learned_tol1e-8", "learned", batch, "fp64", 1e-8, launch),
                  ("fp64_plain_tol1e-8", "natural", args.plain_batch, "fp64", 1e-8, None)]
@@ -555,6 +709,8 @@ def main(argv=None):
         plain_eq = variants["fp64_plain_tol1e-8"]["ms_per_step"]
         variants["speedup_vs_fp64_plain"] = variants["fp64_plain"]["ms_per_step"] / ms_step
         variants["learned_gain_vs_natural_order"] = variants["fp64_batched"]["ms_per_step"] / ms_step
+        variants["learned_gain_vs_natural_order_plain_launches"] = (variants["fp64_plain"]["ms_per_step"] /
+                                                                    variants["fp64_plain_learned"]["ms_per_step"])
         variants["speedup_mixed_vs_fp64_plain_equal_accuracy"] = plain_eq / variants["mixed_batched_learned"][
             "ms_per_step"]
         variants["speedup_fp64_batched_learned_vs_plain_equal_accuracy"] = plain_eq / variants[
@@ -570,7 +726,7 @@ def main(argv=None):
     extra, extra_keep = None, None
     if not args.no_extra:
         torch.cuda.empty_cache()
-        extra, extra_keep = extra_workloads(sgf, W, dev, min(args.ws_gib, 64.0), 1000)
+        extra, extra_keep = extra_workloads(sgf, W, dev, min(args.ws_gib, 64.0), 1000, only=only)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -578,8 +734,16 @@ def main(argv=None):
         if extra:
             for name, a in check_extra(extra_keep).items():
                 extra[name]["accuracy_vs_oracle"] = a
+        ref13 = None
         for name, (G, rho, st) in samples.items():
-            variants.setdefault(name, {})["accuracy_vs_oracle"] = accuracy(wl, check_cols, ref, G, rho, st)
+            r = ref
+            if name.endswith("tol1e-13"):
+                if ref13 is None:
+                    import oracle
+                    ref13 = oracle.solve_workload(wl, cols=wl.columns[check_cols], tol=1e-13,
+                                                  threads=cpu["cores"])
+                r = ref13
+            variants.setdefault(name, {})["accuracy_vs_oracle"] = accuracy(wl, check_cols, r, G, rho, st)
 
     line = {
         "metric": "converged (column x shift) solves/s at tol 1e-12",
@@ -601,21 +765,7 @@ def main(argv=None):
             "step": "build_hamiltonian + plan + features + MLP prediction + order + shifted_solve "
                     "(seed pass + shift pass)",
         },
-        "roofline": {
-            "kernel": dominant,
-            "bound": "alu",
-            "achieved": achieved,
-            "peak": PEAK_FP64_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64_TFLOPS,
-            "traffic": recorded_traffic("k_seed_r1<2, 5>" if dominant == "k_seed" else "k_shift<5, 1>",
-                                        "seed" if dominant == "k_seed" else "shift"),
-            "launches_per_step": launches,
-            "passes": {
-                "k_seed": {"ms_per_step": seed_ms, "tflop_per_step": f_seed / 1e12, "tflops": seed_tf},
-                "k_shift": {"ms_per_step": shift_ms, "tflop_per_step": f_shift / 1e12, "tflops": shift_tf},
-            },
-        },
+        "roofline": roofline_line(fig, seed_ms, shift_ms, launches, traffic_seed, traffic_shift, hbm_counted),
         "cpu_baseline": cpu,
         "hbm_stream": hbm,
         "after_rho": post,
@@ -636,30 +786,43 @@ def baseline_sample(wl):
     return np.random.default_rng(1603).permutation(wl.columns.size)
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(wl, seconds):
-    """The FP64 oracle on a seeded sample of the same columns, for ~`seconds`.
-    Also returns the oracle's results for the first chunk (1024 columns),
+    """The FP64 oracle on a seeded sample of the same columns: a sample sized
+    to about seconds/3 of oracle time, run three times (median rate).  Also
+    returns the oracle's results for the first 1024 columns of the sample,
     against which the GPU variants' outputs are checked."""
     import oracle
     threads = len(os.sched_getaffinity(0))
     threads = min(threads, int(os.environ.get("OMP_NUM_THREADS", threads)))
     b = oracle.system_for(wl)
     order = baseline_sample(wl)
-    done = conv = 0
-    chunk = 1024
-    first = None
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds and done < order.size:
-        pick = order[done:done + chunk]
-        r = oracle.solve_workload(wl, b, cols=wl.columns[pick], threads=threads)
-        if first is None:
-            first = r
-        conv += int(np.sum(r.resid <= wl.tol))
-        done += pick.size
-    dt = time.perf_counter() - t0
-    log(f"[bench] oracle: {done} columns in {dt:.1f} s on {threads} threads")
-    return ({"value": conv / dt, "unit": "solves/s", "cores": threads, "kind": "oracle",
-             "sample": f"{done} seeded random columns of the same workload (all 128 shifts), {dt:.1f} s wall"},
+    first = oracle.solve_workload(wl, b, cols=wl.columns[order[:1024]], threads=threads)
+    per_col = (time.perf_counter() - t0) / 1024
+    n = int(min(order.size, max(1024, seconds / 3.0 / per_col)))
+    pick = wl.columns[order[:n]]
+    rates, walls = [], []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        r = oracle.solve_workload(wl, b, cols=pick, threads=threads)
+        dt = time.perf_counter() - t0
+        walls.append(dt)
+        rates.append(int(np.sum(r.resid <= wl.tol)) / dt)
+    log(f"[bench] oracle: {n} columns x 3 runs, {np.median(walls):.1f} s median wall on {threads} threads")
+    return ({"value": float(np.median(rates)), "unit": "solves/s", "cores": threads, "kind": "oracle",
+             "cpu_model": cpu_model(), "runs": 3, "rates": rates,
+             "sample": f"{n} seeded random columns of the same workload (all {wl.z.size} shifts), run 3 times, "
+                       f"median of {np.median(walls):.1f} s wall; value = median rate"},
             first)
 
 
