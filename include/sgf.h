@@ -338,6 +338,34 @@ sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *plan, const 
                              double *d_G, double *d_rho, int32_t *d_iters, int32_t *d_status, double *d_resid,
                              int32_t *d_shift_iters, void *stream);
 
+/* Bytes of the static device scratch behind sgf_shifted_solve_static. */
+#define SGF_STATIC_SCRATCH_BYTES ((size_t)256 << 20)
+
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * solve as sgf_shifted_solve (same kernels, same arguments and outputs, the
+ * same bits), with the workspace taken from a static device array of
+ * SGF_STATIC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends; the call itself allocates nothing (no hipMalloc,
+ * no hipFree, no HIP events).  Columns are launched in batches of as many
+ * as that scratch holds (opts->batch_cols can lower it).  z and w are copied
+ * into the scratch on the stream, as sgf_shifted_solve copies them into its
+ * workspace; opts->shifts_staged = 1 reuses the z and w a previous
+ * sgf_shifted_solve_static call with the same n_shifts left there.
+ * Errors: as sgf_shifted_solve; SGF_EINVAL for opts->profile = 1;
+ * SGF_EUNSUPPORTED when one column's history (max_iter and n_shifts) does
+ * not fit the scratch.  Every call on one GPU uses that GPU's single
+ * scratch array: calls that overlap in time on one GPU (two streams, two
+ * threads) race and corrupt each other's results; serialise them.  The
+ * array keeps the last call's contents; the call clears what must start at
+ * zero (its work-queue ticket) itself. */
+sgf_status sgf_shifted_solve_static(const sgf_system *sys, const sgf_plan *plan, const sgf_plan_totals *totals,
+                                    int64_t n_cols, const int64_t *d_cols, const int32_t *d_col_plan,
+                                    const int32_t *d_order, int32_t n_shifts, const double *z, const double *w,
+                                    const sgf_solve_opts *opts, const int64_t *d_proj_off, double *d_G,
+                                    double *d_rho, int32_t *d_iters, int32_t *d_status, double *d_resid,
+                                    int32_t *d_shift_iters, void *stream);
+
 /* Copy z (and w, nullable) into the workspace of later sgf_shifted_solve
  * calls with opts->shifts_staged = 1 and the same n_shifts: they sit at the
  * start of the workspace, ahead of every per-column slot.  Asynchronous on

@@ -28,9 +28,10 @@ EXPORTED = (
     "sgf_mlp_forward", "sgf_mlp_train_step", "sgf_mlp_gradient", "sgf_order_workspace", "sgf_order_by_prediction",
     "sgf_bsr_apply", "sgf_solve_stage_shifts", "sgf_trace_workspace", "sgf_traces", "sgf_occupation",
     "sgf_fermi_level", "sgf_wp_workspace", "sgf_wp_bounds", "sgf_wp_terms", "sgf_wp_propagate",
-    "sgf_band_forces", "sgf_energy_density",
+    "sgf_band_forces", "sgf_energy_density", "sgf_shifted_solve_static",
 )
 MLP_NFEAT, MLP_NPARAM, MLP_BATCH = 5, 4619, 128
+STATIC_SCRATCH_BYTES = 256 << 20   # SGF_STATIC_SCRATCH_BYTES
 
 
 class SgfError(RuntimeError):
@@ -99,6 +100,7 @@ def lib():
             "sgf_proj_rows": [P, i64, P, P, P, P],
             "sgf_solve_workspace": [P, P, i64, i32, P, P],
             "sgf_shifted_solve": [P, P, P, i64, P, P, P, i32, P, P, P, P, szt, P, P, P, P, P, P, P, P],
+            "sgf_shifted_solve_static": [P, P, P, i64, P, P, P, i32, P, P, P, P, P, P, P, P, P, P, P],
             "sgf_solve_profile": [P, P, P],
             "sgf_features": [P, P, i64, P, P, P, P],
             "sgf_mlp_normalize": [P, P, i64, P],
@@ -454,6 +456,48 @@ def solve_prepared(prep: Prepared, z, w=None, tol=1e-10, precision="fp64", max_i
     res.shift_iters = None if out.get("nk") is None else out["nk"][:n]
     res.eps = out["eps"][:prep.n_rows] if eps_out else None
     res._out = out  # keep buffers alive with the result
+    return res
+
+
+def shifted_solve_static(prep: Prepared, z, w=None, tol=1e-10, max_iter=0, seed_index=-1, g_out=True, order=None,
+                         batch_cols=0, stage_lds=-1, grid=0, shifts_per_lane=0, shifts_staged=False, out=None,
+                         shift_iters=False, stream=None) -> Result:
+    """FP64 shifted COCG through sgf_shifted_solve_static: the library's
+    static device scratch serves as the workspace, so the C call allocates
+    nothing.  Output tensors are allocated here unless ``out`` (a dict with
+    "G", "rho", "iters", "status", "resid" and optionally "nk") is given."""
+    torch = _torch()
+    dev = prep.cols.device
+    n = prep.cols.numel()
+    zh = _cplx_host(z)
+    wh = _cplx_host(w)
+    ns = zh.size // 2
+    opts = SolveOptsC(0, float(tol), int(max_iter), int(seed_index), 0, int(stage_lds), int(grid), 0,
+                      int(batch_cols), int(shifts_per_lane), int(bool(shifts_staged)), 0.0, 0.0, 0)
+    if out is None:
+        out = {
+            "G": torch.empty((max(prep.n_rows, 1), ns), dtype=torch.complex128, device=dev) if g_out else None,
+            "rho": torch.empty(max(prep.n_rows, 1), dtype=torch.float64, device=dev),
+            "iters": torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+            "status": torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+            "resid": torch.empty((max(n, 1), ns), dtype=torch.float64, device=dev),
+            "nk": torch.empty((max(n, 1), ns), dtype=torch.int32, device=dev) if shift_iters else None,
+        }
+    d_order = None if order is None else _dev(order, torch.int32, dev)
+    sc = prep.system.c()
+    pc = prep.plan.c()
+    _call("sgf_shifted_solve_static", ctypes.byref(sc), ctypes.byref(pc), ctypes.byref(prep.plan.totals), n,
+          _ptr(prep.cols), _ptr(prep.col_plan), _ptr(d_order), ns, zh.ctypes.data_as(P),
+          None if wh is None else wh.ctypes.data_as(P), ctypes.byref(opts), _ptr(prep.proj_off), _ptr(out["G"]),
+          _ptr(out["rho"]), _ptr(out["iters"]), _ptr(out["status"]), _ptr(out["resid"]), _ptr(out.get("nk")),
+          _stream(stream))
+    G = None if out["G"] is None else out["G"][:prep.n_rows]
+    res = Result(prep.proj_off, prep.proj_row, G, out["rho"][:prep.n_rows], out["iters"][:n], out["status"][:n],
+                 out["resid"][:n])
+    res.n_fallback = 0
+    res.shift_iters = None if out.get("nk") is None else out["nk"][:n]
+    res.eps = None
+    res._out = out
     return res
 
 

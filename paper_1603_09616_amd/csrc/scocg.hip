@@ -22,6 +22,7 @@
 // and has no barriers, so the shift work streams at FP64 ALU rate.
 #include "scocg.hpp"
 
+#include <mutex>
 #include <vector>
 
 namespace sgf {
@@ -1948,13 +1949,18 @@ extern "C" sgf_status sgf_solve_workspace(const sgf_system *sys, const sgf_plan_
     return SGF_OK;
 }
 
-extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *plan, const sgf_plan_totals *totals,
-                                        int64_t n_cols, const int64_t *d_cols, const int32_t *d_col_plan,
-                                        const int32_t *d_order, int32_t n_shifts, const double *z, const double *w,
-                                        const sgf_solve_opts *opts, void *d_ws, size_t ws_bytes,
-                                        const int64_t *d_proj_off, double *d_G, double *d_rho, int32_t *d_iters,
-                                        int32_t *d_status, double *d_resid, int32_t *d_shift_iters,
-                                        void *stream) {
+// The body of sgf_shifted_solve and of its allocation-free variant: the
+// workspace is the caller's (from_scratch false) or the library's static
+// scratch array (from_scratch true; then profiling, which creates HIP events,
+// is refused, and a workspace that cannot hold one column is an unsupported
+// size rather than an invalid argument).
+static sgf_status shifted_solve_in(const sgf_system *sys, const sgf_plan *plan, const sgf_plan_totals *totals,
+                                   int64_t n_cols, const int64_t *d_cols, const int32_t *d_col_plan,
+                                   const int32_t *d_order, int32_t n_shifts, const double *z, const double *w,
+                                   const sgf_solve_opts *opts, void *d_ws, size_t ws_bytes,
+                                   const int64_t *d_proj_off, double *d_G, double *d_rho, int32_t *d_iters,
+                                   int32_t *d_status, double *d_resid, int32_t *d_shift_iters, void *stream,
+                                   bool from_scratch) {
     SGF_REQUIRE(sys && plan && totals && opts, "sgf_shifted_solve: NULL system, plan, totals or options");
     SGF_REQUIRE(sys->row_ptr && sys->col && sys->h && sys->n_atoms > 0, "sgf_shifted_solve: system incomplete");
     SGF_REQUIRE(plan->atom_off && plan->blk_off && plan->pa_off && plan->loc_atom && plan->lrow && plan->lblk &&
@@ -2012,6 +2018,16 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
     SGF_REQUIRE(d_ws, "sgf_shifted_solve: workspace is NULL");
     const HistoryShape hs = history_shape(*totals, n_shifts, *opts);
     const SolveLayout L1 = solve_layout(hs, n_shifts, 1, nullptr, 0);
+    if (from_scratch) {
+        SGF_REQUIRE(!opts->profile, "sgf_shifted_solve_static: profile = 1 records HIP events, which this entry "
+                                    "point does not create");
+        if (L1.bytes > ws_bytes) {
+            set_error("sgf_shifted_solve_static: one column of this solve needs %zu bytes of history (max_iter "
+                      "%d, %d shifts), more than the %zu-byte static scratch; use sgf_shifted_solve with a "
+                      "workspace", L1.bytes, hs.cap, n_shifts, ws_bytes);
+            return SGF_EUNSUPPORTED;
+        }
+    }
     SGF_REQUIRE(L1.bytes <= ws_bytes, "sgf_shifted_solve: workspace %zu bytes < %zu (one column)", ws_bytes, L1.bytes);
     if (n_cols == 0) return SGF_OK;
     // columns per launch: batch_cols (0: all), at most as many history slots
@@ -2275,6 +2291,64 @@ extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *p
         if (timed) SGF_HIP(hipEventRecord(e2, st));
     }
     return SGF_OK;
+}
+
+extern "C" sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *plan, const sgf_plan_totals *totals,
+                                        int64_t n_cols, const int64_t *d_cols, const int32_t *d_col_plan,
+                                        const int32_t *d_order, int32_t n_shifts, const double *z, const double *w,
+                                        const sgf_solve_opts *opts, void *d_ws, size_t ws_bytes,
+                                        const int64_t *d_proj_off, double *d_G, double *d_rho, int32_t *d_iters,
+                                        int32_t *d_status, double *d_resid, int32_t *d_shift_iters,
+                                        void *stream) {
+    return shifted_solve_in(sys, plan, totals, n_cols, d_cols, d_col_plan, d_order, n_shifts, z, w, opts, d_ws,
+                            ws_bytes, d_proj_off, d_G, d_rho, d_iters, d_status, d_resid, d_shift_iters, stream,
+                            false);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free solve: the workspace is a static device array of the
+// library.  Each GPU the library runs on holds its own copy from the moment
+// the code object is loaded there until the process ends.  In host code the
+// array's name stands for a host-side shadow, not for device memory, so its
+// device address is looked up once per device (with that device current) and
+// only that address is ever handed to kernels or copies.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[SGF_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+static sgf_status scratch_address(void **out) {
+    int dev = 0;
+    SGF_HIP(hipGetDevice(&dev));
+    SGF_REQUIRE(dev >= 0 && dev < kMaxDevices, "sgf_shifted_solve_static: device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        SGF_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        SGF_REQUIRE(p, "sgf_shifted_solve_static: no device address for the static scratch on device %d", dev);
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SGF_OK;
+}
+
+extern "C" sgf_status sgf_shifted_solve_static(const sgf_system *sys, const sgf_plan *plan,
+                                               const sgf_plan_totals *totals, int64_t n_cols, const int64_t *d_cols,
+                                               const int32_t *d_col_plan, const int32_t *d_order, int32_t n_shifts,
+                                               const double *z, const double *w, const sgf_solve_opts *opts,
+                                               const int64_t *d_proj_off, double *d_G, double *d_rho,
+                                               int32_t *d_iters, int32_t *d_status, double *d_resid,
+                                               int32_t *d_shift_iters, void *stream) {
+    void *ws = nullptr;
+    const sgf_status r = scratch_address(&ws);
+    if (r != SGF_OK) return r;
+    return shifted_solve_in(sys, plan, totals, n_cols, d_cols, d_col_plan, d_order, n_shifts, z, w, opts, ws,
+                            SGF_STATIC_SCRATCH_BYTES, d_proj_off, d_G, d_rho, d_iters, d_status, d_resid,
+                            d_shift_iters, stream, true);
 }
 
 extern "C" sgf_status sgf_solve_stage_shifts(int32_t n_shifts, const double *z, const double *w, void *d_ws,
