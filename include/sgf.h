@@ -58,7 +58,10 @@ typedef enum {
     SGF_BREAKDOWN = 2,  /* mu = p^T (z_s S - H) p or rho = r^T s vanished with s != 0 */
     SGF_NONFINITE = 3,  /* a recurrence scalar became Inf/NaN */
     SGF_DRIFT = 4,      /* mixed path: recursive and FP64 true residual disagree */
-    SGF_BADCOLUMN = 5   /* column, plan index or plan sizes inconsistent; nothing computed */
+    SGF_BADCOLUMN = 5,  /* column, plan index or plan sizes inconsistent; nothing computed */
+    SGF_DIAG_ONLY = 6   /* mixed path: G_jj and rho_jj are certified (a-posteriori bound within g_tol);
+                           the other projection rows hold the complex-FP32 Krylov values, so the
+                           traces and forces, which read those rows, leave the column out */
 } sgf_col_status;
 
 /* Thread-local text of the last non-OK status returned on this thread. */
@@ -98,6 +101,34 @@ typedef struct {
     const double *xyz;
 } sgf_system;
 
+/* A caller-built block-sparse matrix (for example from another tight-binding
+ * code), all pointers device and caller-owned: the BSR layout above with
+ * n_atoms block rows, nnzb blocks, FP64 values h (and s, NULL for S = I)
+ * and optional FP32 shadows h32 / s32. */
+typedef struct {
+    int64_t n_atoms;
+    int64_t nnzb;
+    const int32_t *row_ptr;
+    const int32_t *col;
+    const double *h;
+    const double *s;
+    const float *h32;
+    const float *s32;
+} sgf_bsr;
+
+/* The system of the shifted equations (z S - H) x = b of the Introduction,
+ * built around a caller's matrix: *out receives a HOST descriptor (allocated
+ * with malloc, released by sgf_system_destroy) that borrows m's device
+ * arrays and d_xyz (device, nm, [n_atoms][3]; NULL when every local subspace
+ * is the whole system).  Checks the host-visible fields only (sizes >= 1,
+ * nnzb >= n_atoms for the diagonal blocks, non-NULL row_ptr, col and h);
+ * the arrays themselves are read by the later calls.  EINVAL otherwise. */
+sgf_status sgf_system_from_bsr(const sgf_bsr *m, const double *d_xyz, sgf_system **out);
+
+/* Release a descriptor from sgf_system_from_bsr (NULL is allowed).  The
+ * device arrays it borrowed stay the caller's. */
+void sgf_system_destroy(sgf_system *sys);
+
 /* Bytes of scratch needed by sgf_build_pattern for n_atoms atoms. */
 sgf_status sgf_build_workspace(int64_t n_atoms, size_t *ws_bytes);
 
@@ -110,6 +141,15 @@ sgf_status sgf_build_workspace(int64_t n_atoms, size_t *ws_bytes);
  * pointers or ws_bytes below sgf_build_workspace. */
 sgf_status sgf_build_pattern(int64_t n_atoms, const double *d_xyz, double r_cut, void *d_ws, size_t ws_bytes,
                              int32_t *d_row_ptr, int64_t *nnzb, void *stream);
+
+/* Block count of the Hamiltonian that sgf_build_hamiltonian would build for
+ * these positions and parameters (bonds within p->r_cut plus the diagonal
+ * blocks), so that the caller can size col / h / s first: the neighbour
+ * search of sgf_build_pattern without writing row_ptr.  d_ws: a workspace of
+ * sgf_build_workspace(n_atoms) bytes (left holding the spatial hash).
+ * SYNCHRONOUS.  EINVAL / EUNSUPPORTED as sgf_build_pattern. */
+sgf_status sgf_hamiltonian_size(int64_t n_atoms, const double *d_xyz, const sgf_tb_params *p, void *d_ws,
+                                size_t ws_bytes, int64_t *nnzb, void *stream);
 
 /* Tight-binding H (and S when p->overlap) on the pattern from
  * sgf_build_pattern (same d_ws, not modified in between).  Fills d_col
@@ -248,6 +288,10 @@ typedef struct {
                               eps_t = -(1/pi) sum_k Im(w_k z_k G_t(z_k)) that the forces need when
                               S != I (sgf_band_forces), without G being kept.  Needs w; FP64 path
                               only (precision 1 returns SGF_EUNSUPPORTED) */
+    double *g_diag_out;    /* NULL, or device complex [n_cols][n_shifts]: the shift pass also writes the
+                              diagonal element G_jj(z_k) of every column (the same values as its row in
+                              d_G).  With d_G NULL this is the "diagonal only" output, 16 n_shifts bytes
+                              per column instead of 64 |P| n_shifts */
 } sgf_solve_opts;
 
 /* Output offsets: d_proj_off[c+1] - d_proj_off[c] = 4 * |P(plan of column c)|
@@ -326,9 +370,12 @@ sgf_status sgf_solve_workspace(const sgf_system *sys, const sgf_plan_totals *tot
  * r_k of the full iterate (written to d_resid instead of the recursive
  * residual) the shift pass bounds the error of the estimate rigorously,
  * |G_jj - G~_jj| <= ||r_k||^2 / Im z_k, and sets SGF_DRIFT on a column
- * whose bound exceeds opts->g_tol max_k |G~_jj|.  A caller that needs every
- * column re-solves the non-converged ones in FP64 with queue_len (the Python
- * binding does so).  The workspace holds the full residual history:
+ * whose bound exceeds opts->g_tol max_k |G~_jj|.  A column whose bound
+ * holds ends with SGF_DIAG_ONLY, not SGF_CONVERGED: its G_jj and rho_jj are
+ * certified, its other rows are not.  A caller that needs every column
+ * re-solves the others (DRIFT, MAXITER, ...) in FP64 with queue_len (the
+ * Python binding does so; a caller that needs certified off-diagonal rows
+ * re-solves the SGF_DIAG_ONLY columns too).  The workspace holds the full residual history:
  * (max_iter + 1) x 512 bytes per column.
  */
 sgf_status sgf_shifted_solve(const sgf_system *sys, const sgf_plan *plan, const sgf_plan_totals *totals,
@@ -474,7 +521,8 @@ sgf_status sgf_trace_workspace(int64_t total_rows, int32_t n_shifts, size_t *ws_
 /* Traces of one solve's outputs (device arrays as sgf_shifted_solve wrote
  * them): d_cols[n_cols], d_proj_off[n_cols+1], d_proj_row[total_rows],
  * d_status[n_cols] (nullable: with it, only SGF_CONVERGED columns count;
- * a column the solve rejected holds no G or rho), d_G complex
+ * a column the solve rejected holds no G or rho, and an SGF_DIAG_ONLY
+ * column of the mixed path has uncertified off-diagonal rows), d_G complex
  * [total_rows][n_shifts] (nullable), d_rho [total_rows] (nullable; one of
  * the two is required).  Writes d_T and d_U (complex [n_shifts], needed
  * with d_G) and d_rho_tr (double[2]: tr(rho S), tr(rho H) at the solve's
@@ -581,7 +629,8 @@ sgf_status sgf_wp_propagate(const sgf_system *sys, int32_t n_rhs, double *d_psi,
  * or the solve's sgf_solve_opts.eps_out), required when the system has an
  * overlap and ignored (may be NULL) when it has none; d_status [n_cols]
  * (nullable): with it, only SGF_CONVERGED columns count (a column the solve
- * rejected holds no rho).  p->overlap must match the system.  Writes d_force [n_atoms][3] (eV/nm), cleared first.  FP64
+ * rejected holds no rho; an SGF_DIAG_ONLY column of the mixed path holds
+ * uncertified off-diagonal rows).  p->overlap must match the system.  Writes d_force [n_atoms][3] (eV/nm), cleared first.  FP64
  * atomics add the terms, in no fixed order: repeated runs agree to
  * rounding.  Asynchronous on the stream. */
 sgf_status sgf_band_forces(const sgf_system *sys, const double *d_xyz, const sgf_tb_params *p, int64_t n_cols,

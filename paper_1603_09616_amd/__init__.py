@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsgf.so")
 
 SGF_OK, SGF_EINVAL, SGF_ENOMEM, SGF_EHIP, SGF_EUNSUPPORTED = 0, -1, -2, -3, -4
-CONVERGED, MAXITER, BREAKDOWN, NONFINITE, DRIFT, BADCOLUMN = 0, 1, 2, 3, 4, 5
+CONVERGED, MAXITER, BREAKDOWN, NONFINITE, DRIFT, BADCOLUMN, DIAG_ONLY = 0, 1, 2, 3, 4, 5, 6
 
 EXPORTED = (
     "sgf_last_error", "sgf_version", "sgf_build_workspace", "sgf_build_pattern", "sgf_build_hamiltonian",
@@ -28,7 +28,8 @@ EXPORTED = (
     "sgf_mlp_forward", "sgf_mlp_train_step", "sgf_mlp_gradient", "sgf_order_workspace", "sgf_order_by_prediction",
     "sgf_bsr_apply", "sgf_solve_stage_shifts", "sgf_trace_workspace", "sgf_traces", "sgf_occupation",
     "sgf_fermi_level", "sgf_wp_workspace", "sgf_wp_bounds", "sgf_wp_terms", "sgf_wp_propagate",
-    "sgf_band_forces", "sgf_energy_density", "sgf_shifted_solve_static",
+    "sgf_band_forces", "sgf_energy_density", "sgf_shifted_solve_static", "sgf_hamiltonian_size",
+    "sgf_system_from_bsr", "sgf_system_destroy",
 )
 MLP_NFEAT, MLP_NPARAM, MLP_BATCH = 5, 4619, 128
 STATIC_SCRATCH_BYTES = 256 << 20   # SGF_STATIC_SCRATCH_BYTES
@@ -69,7 +70,12 @@ class SolveOptsC(ctypes.Structure):
     _fields_ = [("precision", i32), ("tol", dbl), ("max_iter", i32), ("seed_index", i32), ("monitor_every", i32),
                 ("stage_lds", i32), ("grid", i32), ("profile", i32), ("batch_cols", i64),
                 ("shifts_per_lane", i32), ("shifts_staged", i32), ("drift_tol", dbl), ("g_tol", dbl),
-                ("queue_len", i64), ("eps_out", P)]
+                ("queue_len", i64), ("eps_out", P), ("g_diag_out", P)]
+
+
+class BsrC(ctypes.Structure):
+    _fields_ = [("n_atoms", i64), ("nnzb", i64), ("row_ptr", P), ("col", P), ("h", P), ("s", P), ("h32", P),
+                ("s32", P)]
 
 
 _lib = None
@@ -119,11 +125,15 @@ def lib():
             "sgf_wp_propagate": [P, i32, P, dbl, i32, dbl, dbl, i32, P, szt, P],
             "sgf_band_forces": [P, P, P, i64, P, P, P, P, P, P, P, P],
             "sgf_energy_density": [i64, i32, P, P, P, P, P],
+            "sgf_hamiltonian_size": [i64, P, P, P, szt, P, P],
+            "sgf_system_from_bsr": [P, P, P],
         }
         for name, args in sigs.items():
             f = getattr(L, name)
             f.restype = ctypes.c_int
             f.argtypes = args
+        L.sgf_system_destroy.restype = None
+        L.sgf_system_destroy.argtypes = [P]
         _lib = L
     return _lib
 
@@ -238,6 +248,52 @@ def build_chain(eps, t: float, device="cuda", stream=None) -> System:
     return System(nb, nnzb, row_ptr, col, h)
 
 
+def hamiltonian_size(xyz, params, device="cuda", stream=None) -> int:
+    """Block count of the Hamiltonian build_hamiltonian would build (bonds
+    within params.r_cut plus the diagonal blocks), from a GPU neighbour
+    search."""
+    torch = _torch()
+    d_xyz = _dev(xyz, torch.float64, device)
+    n = d_xyz.shape[0]
+    ws = ctypes.c_size_t()
+    _call("sgf_build_workspace", n, ctypes.byref(ws))
+    d_ws = _bytes(ws.value, device)
+    nnzb = ctypes.c_int64()
+    tb = _tb_c(params)
+    _call("sgf_hamiltonian_size", n, _ptr(d_xyz), ctypes.byref(tb), _ptr(d_ws), ws.value, ctypes.byref(nnzb),
+          _stream(stream))
+    return nnzb.value
+
+
+def system_from_bsr(row_ptr, col, h, s=None, xyz=None, h32=None, s32=None, hash_cell=0.3, stream=None) -> System:
+    """A System around a caller's block-sparse matrix (device tensors:
+    row_ptr int32 [n+1], col int32 [nnzb], h (and s) float64 [nnzb, 4, 4];
+    xyz float64 [n, 3] in nm for radius-limited subspaces).  The C call
+    checks the sizes; the tensors are borrowed, not copied.  With xyz, the
+    spatial hash that finds the atoms of a local subspace is built by the
+    library's neighbour search (sgf_hamiltonian_size with cells of
+    hash_cell nm)."""
+    n, nb = int(row_ptr.numel()) - 1, int(col.numel())
+    m = BsrC(n, nb, _ptr(row_ptr), _ptr(col), _ptr(h), _ptr(s), _ptr(h32), _ptr(s32))
+    out = ctypes.c_void_p()
+    _call("sgf_system_from_bsr", ctypes.byref(m), _ptr(xyz), ctypes.byref(out))
+    try:
+        c = SystemC.from_address(out.value)
+        assert c.n_atoms == n and c.nnzb == nb and c.row_ptr == _ptr(row_ptr) and c.h == _ptr(h)
+    finally:
+        lib().sgf_system_destroy(out)
+    build_ws = None
+    if xyz is not None:
+        ws = ctypes.c_size_t()
+        _call("sgf_build_workspace", n, ctypes.byref(ws))
+        build_ws = _bytes(ws.value, row_ptr.device)
+        cnt = ctypes.c_int64()
+        tb = TBParamsC(0, 0, 0, 0, 0, 0, 1.0, 0.0, float(hash_cell), 0, 0.0, 1.0)
+        _call("sgf_hamiltonian_size", n, _ptr(xyz), ctypes.byref(tb), _ptr(build_ws), ws.value, ctypes.byref(cnt),
+              _stream(stream))
+    return System(n, nb, row_ptr, col, h, s, h32, s32, xyz, build_ws)
+
+
 def system_for(wl, device="cuda") -> System:
     """GPU-built system of a workload from ``workloads``."""
     if wl.kind == "chain":
@@ -327,7 +383,7 @@ class Result:
     def numpy(self):
         cv = (lambda t: t.cpu().numpy() if hasattr(t, "cpu") else t)
         r = Result(*(cv(getattr(self, f.name)) for f in dataclasses.fields(self)))
-        for extra in ("n_fallback", "shift_iters"):
+        for extra in ("n_fallback", "shift_iters", "G_diag", "eps"):
             if hasattr(self, extra):
                 setattr(r, extra, cv(getattr(self, extra)))
         return r
@@ -390,6 +446,12 @@ def solve_prepared(prep: Prepared, z, w=None, tol=1e-10, precision="fp64", max_i
                    fallback=True, fallback_tol=1e-9, shifts_staged=False, eps_out=False, stream=None) -> Result:
     """Shifted COCG on every prepared column (asynchronous on the stream).
 
+    g_out: True or "proj" keeps G on every projection row (``Result.G``);
+    "diag" keeps only the diagonal element G_jj(z_k) of every column
+    (``Result.G_diag``, complex [n_cols, n_shifts]; ``Result.G`` is None);
+    False or "none" keeps neither (rho only).  "proj" also fills G_diag when
+    ``out`` holds a "G_diag" buffer.
+
     eps_out: also form the energy-density matrix on the projection rows in
     the shift pass (``Result.eps``; FP64 only, needs w).
 
@@ -406,6 +468,9 @@ def solve_prepared(prep: Prepared, z, w=None, tol=1e-10, precision="fp64", max_i
     ns = zh.size // 2
     if precision == "mixed" and prep.system.h32 is None:
         prep.system.add_f32(stream)
+    if g_out not in (True, False, "proj", "diag", "none"):
+        raise ValueError(f"g_out must be True/'proj', 'diag' or False/'none', not {g_out!r}")
+    keep_g = g_out is True or g_out == "proj"
     opts = SolveOptsC({"fp64": 0, "mixed": 1}[precision], float(tol), int(max_iter), int(seed_index),
                       int(monitor_every), int(stage_lds), int(grid), int(bool(profile)), int(batch_cols),
                       int(shifts_per_lane), int(bool(shifts_staged)), float(drift_tol), float(g_tol), int(queue_len))
@@ -417,13 +482,16 @@ def solve_prepared(prep: Prepared, z, w=None, tol=1e-10, precision="fp64", max_i
     if out is None:
         out = {
             "ws": _bytes(ws.value, dev),
-            "G": torch.empty((max(prep.n_rows, 1), ns), dtype=torch.complex128, device=dev) if g_out else None,
+            "G": torch.empty((max(prep.n_rows, 1), ns), dtype=torch.complex128, device=dev) if keep_g else None,
             "rho": torch.empty(max(prep.n_rows, 1), dtype=torch.float64, device=dev),
             "iters": torch.empty(max(n, 1), dtype=torch.int32, device=dev),
             "status": torch.empty(max(n, 1), dtype=torch.int32, device=dev),
             "resid": torch.empty((max(n, 1), ns), dtype=torch.float64, device=dev),
             "nk": torch.empty((max(n, 1), ns), dtype=torch.int32, device=dev) if shift_iters else None,
+            "G_diag": (torch.empty((max(n, 1), ns), dtype=torch.complex128, device=dev) if g_out == "diag"
+                       else None),
         }
+    opts.g_diag_out = _ptr(out.get("G_diag"))
     if eps_out and out.get("eps") is None:
         out["eps"] = torch.empty(max(prep.n_rows, 1), dtype=torch.float64, device=dev)
     if eps_out:
@@ -438,12 +506,14 @@ def solve_prepared(prep: Prepared, z, w=None, tol=1e-10, precision="fp64", max_i
     n_fallback = 0
     if precision == "mixed" and fallback and n > 0 and queue_len == 0:
         torch.cuda.current_stream(dev).synchronize() if stream is None else stream.synchronize()
-        bad = torch.nonzero(out["status"][:n] != CONVERGED).flatten().to(torch.int32)
+        st_now = out["status"][:n]
+        bad = torch.nonzero((st_now != CONVERGED) & (st_now != DIAG_ONLY)).flatten().to(torch.int32)
         n_fallback = int(bad.numel())
         if n_fallback:
             out["fallback_order"] = bad
             opts64 = SolveOptsC(0, float(fallback_tol), 0, int(seed_index), 0, -1, int(grid), 0, 0,
                                 int(shifts_per_lane), 0, 0.0, 0.0, n_fallback)
+            opts64.g_diag_out = opts.g_diag_out
             _call("sgf_shifted_solve", ctypes.byref(sc), ctypes.byref(pc), ctypes.byref(prep.plan.totals), n,
                   _ptr(prep.cols), _ptr(prep.col_plan), _ptr(bad), ns, zh.ctypes.data_as(P),
                   None if wh is None else wh.ctypes.data_as(P), ctypes.byref(opts64), _ptr(out["ws"]),
@@ -455,6 +525,7 @@ def solve_prepared(prep: Prepared, z, w=None, tol=1e-10, precision="fp64", max_i
     res.n_fallback = n_fallback
     res.shift_iters = None if out.get("nk") is None else out["nk"][:n]
     res.eps = out["eps"][:prep.n_rows] if eps_out else None
+    res.G_diag = None if out.get("G_diag") is None else out["G_diag"][:n]
     res._out = out  # keep buffers alive with the result
     return res
 
@@ -563,14 +634,25 @@ def solve_profile():
 def shifted_solve(system: System, columns, z, w=None, tol=1e-10, radius=0.0, radius_per_col=None, prune=True,
                   precision="fp64", max_iter=0, seed_index=-1, g_out=True, order=None, batch_cols=0, stage_lds=-1,
                   grid=0, max_loc_atoms=2048, shifts_per_lane=0, monitor_every=50, drift_tol=0.0, g_tol=0.0,
-                  fallback=True, stream=None) -> Result:
+                  fallback=True, schedule="natural", model=None, stream=None) -> Result:
     """Green's-function elements and density-matrix entries for many columns.
 
     columns: global orbital indices j; each is solved on the local subspace of
     its atom (radius in nm; <= 0 means the whole system), pruned to the
     connected component when ``prune``.  z, w: complex shifts and weights.
+    g_out: True/"proj" (G on the projection rows), "diag" (G_jj only) or
+    False/"none" (rho only).  schedule: "natural" takes the columns in the
+    given order (or ``order``); "learned" queues them longest-predicted-first
+    from ``model`` (an IterationModel) through sgf_features, sgf_mlp_forward
+    and sgf_order_by_prediction.  The order never changes a result.
     """
     prep = prepare(system, columns, radius, radius_per_col, prune, max_loc_atoms, stream)
+    if schedule == "learned":
+        if model is None:
+            raise ValueError("schedule='learned' needs a trained IterationModel")
+        order = learned_order(prep, model, stream)
+    elif schedule != "natural":
+        raise ValueError(f"schedule must be 'natural' or 'learned', not {schedule!r}")
     return solve_prepared(prep, z, w, tol, precision, max_iter, seed_index, g_out, order, batch_cols, stage_lds,
                           grid, monitor_every=monitor_every, shifts_per_lane=shifts_per_lane, drift_tol=drift_tol,
                           g_tol=g_tol, fallback=fallback, stream=stream)
@@ -731,6 +813,12 @@ class IterationModel:
             hist.append(float(torch.cat(losses).mean()))
         test_mse = float(((self.predict(feat[test]) - target[test]) ** 2).mean()) if n_test else float("nan")
         return hist, test_mse
+
+
+def learned_order(prep: Prepared, model: "IterationModel", stream=None, y_lo=0.0, y_hi=float(np.log(4096.0))):
+    """Work-queue order of the prepared columns, largest predicted iteration
+    count first (features -> network -> counting sort on the device)."""
+    return order_by_prediction(model.predict(features(prep, stream), stream), y_lo, y_hi, stream)
 
 
 def order_by_prediction(pred, y_lo, y_hi, stream=None):

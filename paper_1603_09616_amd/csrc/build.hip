@@ -6,6 +6,8 @@
 // block row lists its bonds plus the diagonal, sorted by column.
 #include "build.hpp"
 
+#include <cstdlib>
+
 namespace sgf {
 
 constexpr int BUILD_T = 256;
@@ -207,10 +209,12 @@ extern "C" sgf_status sgf_build_workspace(int64_t n_atoms, size_t *ws_bytes) {
     return SGF_OK;
 }
 
-extern "C" sgf_status sgf_build_pattern(int64_t n_atoms, const double *d_xyz, double r_cut, void *d_ws, size_t ws_bytes,
-                                        int32_t *d_row_ptr, int64_t *nnzb, void *stream) {
+// The neighbour search behind sgf_build_pattern and sgf_hamiltonian_size;
+// d_row_ptr NULL counts the blocks without writing the row pointers.
+static sgf_status bond_pattern(int64_t n_atoms, const double *d_xyz, double r_cut, void *d_ws, size_t ws_bytes,
+                               int32_t *d_row_ptr, int64_t *nnzb, void *stream) {
     SGF_REQUIRE(n_atoms > 0 && n_atoms < (int64_t)1 << 30, "sgf_build_pattern: n_atoms out of range");
-    SGF_REQUIRE(d_xyz && d_ws && d_row_ptr && nnzb, "sgf_build_pattern: NULL pointer");
+    SGF_REQUIRE(d_xyz && d_ws && nnzb, "sgf_build_pattern: NULL pointer");
     SGF_REQUIRE(r_cut > 0 && r_cut < 1e6, "sgf_build_pattern: r_cut must be positive");
     BuildLayout L = build_layout(n_atoms, d_ws, ws_bytes);
     SGF_REQUIRE(L.bytes <= ws_bytes, "sgf_build_pattern: workspace %zu bytes < %zu", ws_bytes, L.bytes);
@@ -229,8 +233,10 @@ extern "C" sgf_status sgf_build_pattern(int64_t n_atoms, const double *d_xyz, do
     SGF_LAUNCHED();
     rc = inclusive_scan_i64(L.row_cnt + 1, n_atoms, L.scan, st);
     if (rc) return rc;
-    k_row_ptr<<<grid_for(n_atoms + 1), BUILD_T, 0, st>>>(L.row_cnt, n_atoms, d_row_ptr);
-    SGF_LAUNCHED();
+    if (d_row_ptr) {
+        k_row_ptr<<<grid_for(n_atoms + 1), BUILD_T, 0, st>>>(L.row_cnt, n_atoms, d_row_ptr);
+        SGF_LAUNCHED();
+    }
     int64_t total = 0;
     BuildHeader hdr;
     SGF_HIP(hipMemcpyAsync(&total, L.row_cnt + n_atoms, sizeof(int64_t), hipMemcpyDeviceToHost, st));
@@ -247,6 +253,39 @@ extern "C" sgf_status sgf_build_pattern(int64_t n_atoms, const double *d_xyz, do
     *nnzb = total;
     return SGF_OK;
 }
+
+extern "C" sgf_status sgf_build_pattern(int64_t n_atoms, const double *d_xyz, double r_cut, void *d_ws, size_t ws_bytes,
+                                        int32_t *d_row_ptr, int64_t *nnzb, void *stream) {
+    SGF_REQUIRE(d_row_ptr, "sgf_build_pattern: NULL pointer");
+    return bond_pattern(n_atoms, d_xyz, r_cut, d_ws, ws_bytes, d_row_ptr, nnzb, stream);
+}
+
+extern "C" sgf_status sgf_hamiltonian_size(int64_t n_atoms, const double *d_xyz, const sgf_tb_params *p, void *d_ws,
+                                           size_t ws_bytes, int64_t *nnzb, void *stream) {
+    SGF_REQUIRE(p, "sgf_hamiltonian_size: NULL parameters");
+    return bond_pattern(n_atoms, d_xyz, p->r_cut, d_ws, ws_bytes, nullptr, nnzb, stream);
+}
+
+extern "C" sgf_status sgf_system_from_bsr(const sgf_bsr *m, const double *d_xyz, sgf_system **out) {
+    SGF_REQUIRE(m && out, "sgf_system_from_bsr: NULL argument");
+    SGF_REQUIRE(m->n_atoms >= 1 && m->n_atoms < (int64_t)1 << 30, "sgf_system_from_bsr: n_atoms %lld out of range",
+                (long long)m->n_atoms);
+    SGF_REQUIRE(m->nnzb >= m->n_atoms && m->nnzb < (int64_t)1 << 31,
+                "sgf_system_from_bsr: nnzb %lld (need at least one diagonal block per row, below 2^31)",
+                (long long)m->nnzb);
+    SGF_REQUIRE(m->row_ptr && m->col && m->h, "sgf_system_from_bsr: row_ptr, col and h are required");
+    SGF_REQUIRE(!m->s32 || m->s, "sgf_system_from_bsr: an FP32 overlap shadow without the overlap");
+    sgf_system *sys = static_cast<sgf_system *>(std::malloc(sizeof(sgf_system)));
+    if (!sys) {
+        set_error("sgf_system_from_bsr: out of host memory");
+        return SGF_ENOMEM;
+    }
+    *sys = sgf_system{m->n_atoms, m->nnzb, m->row_ptr, m->col, m->h, m->s, m->h32, m->s32, d_xyz};
+    *out = sys;
+    return SGF_OK;
+}
+
+extern "C" void sgf_system_destroy(sgf_system *sys) { std::free(sys); }
 
 extern "C" sgf_status sgf_build_hamiltonian(int64_t n_atoms, const double *d_xyz, const double *d_onsite,
                                             const sgf_tb_params *p, const void *d_ws, size_t ws_bytes,

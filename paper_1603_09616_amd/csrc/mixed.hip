@@ -430,7 +430,8 @@ __global__ __launch_bounds__(256) void k_shift_mx(SolveArgs a) {
             mb = fmax(mb, rpart[v]);
             mg = fmax(mg, rpart[4 + v]);
         }
-        if (meta.status == SGF_CONVERGED && !(mb <= a.g_tol * mg)) a.status[c] = SGF_DRIFT;
+        // certified diagonal: SGF_DIAG_ONLY (the other rows are FP32-Krylov values)
+        if (meta.status == SGF_CONVERGED) a.status[c] = mb <= a.g_tol * mg ? SGF_DIAG_ONLY : SGF_DRIFT;
     }
     __syncthreads();  // rpart is reused below
 
@@ -444,6 +445,10 @@ __global__ __launch_bounds__(256) void k_shift_mx(SolveArgs a) {
         if (kof >= 0 && a.G) {
             a.G[2 * ((out0 + r) * a.ns + kof)] = Gr.x;
             a.G[2 * ((out0 + r) * a.ns + kof) + 1] = Gr.y;
+        }
+        if (kof >= 0 && a.gdiag && lrow_ == jl) {
+            a.gdiag[2 * (c * a.ns + kof)] = Gr.x;
+            a.gdiag[2 * (c * a.ns + kof) + 1] = Gr.y;
         }
         double t = kof >= 0 ? fma(wk.x, Gr.y, wk.y * Gr.x) : 0.0;
         t = wave_reduce(t);

@@ -1734,6 +1734,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MS == 1 && 
         if (kof[u] >= 0 && a.w) wk[u] = a.w[kof[u]];
     }
     const int64_t out0 = a.proj_off[c];
+    // the projection row of the column's own orbital (for the diagonal output)
+    int rdiag = -1;
+    if (a.gdiag) {  // uniform
+        const int32_t pl = a.col_plan[c];
+        const int64_t p0 = a.pa_off[pl];
+        const int32_t cl = a.center_loc[pl];
+        for (int q = 0; q < npa; ++q)
+            if (a.pa_loc[p0 + q] == cl) rdiag = 4 * q + (int)(a.cols[c] & 3);
+    }
 #pragma unroll
     for (int r = 0; r < 4 * NPA; ++r) {
         if (r >= nrow) continue;  // uniform
@@ -1745,6 +1754,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MS == 1 && 
             if (a.G) {
                 a.G[2 * ((out0 + r) * a.ns + kof[u])] = Gr.x;
                 a.G[2 * ((out0 + r) * a.ns + kof[u]) + 1] = Gr.y;
+            }
+            if (r == rdiag) {  // uniform
+                a.gdiag[2 * (c * a.ns + kof[u])] = Gr.x;
+                a.gdiag[2 * (c * a.ns + kof[u]) + 1] = Gr.y;
             }
             t = fma(wk[u].x, Gr.y, fma(wk[u].y, Gr.x, t));
         }
@@ -2084,6 +2097,7 @@ static sgf_status shifted_solve_in(const sgf_system *sys, const sgf_plan *plan, 
     a.G = d_G;
     a.rho = d_rho;
     a.eps = opts->eps_out;
+    a.gdiag = opts->g_diag_out;
     a.resid = d_resid;
     a.iters = d_iters;
     a.status = d_status;

@@ -50,6 +50,7 @@ struct SolveArgs {
     const int64_t *proj_off;
     double *G, *rho, *resid;
     double *eps;        // energy-density matrix on the projection rows (nullable)
+    double *gdiag;      // G_jj(z_k) per column, complex [n_cols][ns] (nullable)
     int32_t *iters, *status, *shift_iters;
     // history (per batch slot)
     int cap;            // recorded iterations per slot (max_iter of the batch)

@@ -56,7 +56,8 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(sgf.SystemC) == 9 * 8
     assert ctypes.sizeof(sgf.PlanC) == 12 * 8
     assert ctypes.sizeof(sgf.PlanTotalsC) == 3 * 8 + 4 * 4
-    assert ctypes.sizeof(sgf.SolveOptsC) == 88
+    assert ctypes.sizeof(sgf.SolveOptsC) == 96
+    assert ctypes.sizeof(sgf.BsrC) == 8 * 8
 
 
 def test_product_path_has_no_oracle_dependency():
@@ -67,3 +68,23 @@ def test_product_path_has_no_oracle_dependency():
             if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
                 src = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in src.replace("the oracle", ""), f
+
+
+def test_system_from_bsr_host_checks(libsgf):
+    """sgf_system_from_bsr fills a host descriptor from the caller's
+    (device) arrays without touching them, and refuses inconsistent sizes."""
+    import paper_1603_09616_amd as sgf
+    fake = [0x1000 * (i + 1) for i in range(6)]   # never dereferenced by this call
+    m = sgf.BsrC(10, 28, fake[0], fake[1], fake[2], None, fake[3], None)
+    out = ctypes.c_void_p()
+    assert libsgf.sgf_system_from_bsr(ctypes.byref(m), ctypes.c_void_p(fake[4]), ctypes.byref(out)) == 0
+    c = sgf.SystemC.from_address(out.value)
+    assert (c.n_atoms, c.nnzb, c.row_ptr, c.col, c.h, c.s, c.h32, c.s32, c.xyz) == \
+        (10, 28, fake[0], fake[1], fake[2], None, fake[3], None, fake[4])
+    libsgf.sgf_system_destroy(out)
+    libsgf.sgf_system_destroy(None)
+    for bad in (sgf.BsrC(0, 1, fake[0], fake[1], fake[2], None, None, None),    # no rows
+                sgf.BsrC(10, 9, fake[0], fake[1], fake[2], None, None, None),   # fewer blocks than diagonal blocks
+                sgf.BsrC(10, 28, fake[0], None, fake[2], None, None, None),     # no column indices
+                sgf.BsrC(10, 28, fake[0], fake[1], fake[2], None, None, fake[5])):  # FP32 S without S
+        assert libsgf.sgf_system_from_bsr(ctypes.byref(bad), None, ctypes.byref(out)) == -1
