@@ -638,6 +638,29 @@ sgf_status sgf_band_forces(const sgf_system *sys, const double *d_xyz, const sgf
                            const int32_t *d_status, const double *d_rho, const double *d_eps, double *d_force,
                            void *stream);
 
+/* ------------------------------------------------------------------------ */
+/* Quantum molecular dynamics: the time step                                  */
+/* ------------------------------------------------------------------------ */
+
+/* Acceleration in nm/fs^2 of a force of 1 eV/nm on a mass of 1 amu:
+ * (e / u) x 1e-12 with the exact elementary charge e = 1.602176634e-19 C
+ * and the CODATA 2018 atomic mass constant u = 1.66053906660e-27 kg. */
+#define SGF_ACCEL_EV_NM_AMU 9.648533215665326e-5
+
+/* One step of the quantum molecular dynamics of Sec. 2 (time step h_MD,
+ * 1 fs in the paper) by velocity Verlet (Swope, Andersen, Berens and Wilson,
+ * J. Chem. Phys. 76, 637 (1982)): with forces F(x_n),
+ *   sgf_md_kick  (v += (h/2) F / m),  sgf_md_drift (x += h v),
+ *   new H, plans, shifted solve and sgf_band_forces at x_{n+1},
+ *   sgf_md_kick  (v += (h/2) F_{n+1} / m).
+ * Units: positions nm, velocities nm/fs, forces eV/nm, masses amu, h in fs
+ * (negative h runs backwards).  Device arrays [n_atoms][3] (d_mass
+ * [n_atoms]), updated in place; asynchronous on the stream.  EINVAL on NULL
+ * arrays, n_atoms < 0 or a non-finite or absurd step (|h| >= 1e6 fs). */
+sgf_status sgf_md_kick(int64_t n_atoms, const double *d_force, const double *d_mass, double h_fs, double *d_vel,
+                       void *stream);
+sgf_status sgf_md_drift(int64_t n_atoms, const double *d_vel, double h_fs, double *d_xyz, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

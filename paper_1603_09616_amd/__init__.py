@@ -29,10 +29,11 @@ EXPORTED = (
     "sgf_bsr_apply", "sgf_solve_stage_shifts", "sgf_trace_workspace", "sgf_traces", "sgf_occupation",
     "sgf_fermi_level", "sgf_wp_workspace", "sgf_wp_bounds", "sgf_wp_terms", "sgf_wp_propagate",
     "sgf_band_forces", "sgf_energy_density", "sgf_shifted_solve_static", "sgf_hamiltonian_size",
-    "sgf_system_from_bsr", "sgf_system_destroy",
+    "sgf_system_from_bsr", "sgf_system_destroy", "sgf_md_kick", "sgf_md_drift",
 )
 MLP_NFEAT, MLP_NPARAM, MLP_BATCH = 5, 4619, 128
 STATIC_SCRATCH_BYTES = 256 << 20   # SGF_STATIC_SCRATCH_BYTES
+ACCEL_EV_NM_AMU = 9.648533215665326e-5   # SGF_ACCEL_EV_NM_AMU: nm/fs^2 per eV/nm per amu
 
 
 class SgfError(RuntimeError):
@@ -127,6 +128,8 @@ def lib():
             "sgf_energy_density": [i64, i32, P, P, P, P, P],
             "sgf_hamiltonian_size": [i64, P, P, P, szt, P, P],
             "sgf_system_from_bsr": [P, P, P],
+            "sgf_md_kick": [i64, P, P, dbl, P, P],
+            "sgf_md_drift": [i64, P, dbl, P, P],
         }
         for name, args in sigs.items():
             f = getattr(L, name)
@@ -914,3 +917,55 @@ def energy_density(res: Result, z, w, stream=None):
     eps = torch.empty(max(rows, 1), dtype=torch.float64, device=dev)
     _call("sgf_energy_density", rows, ns, _ptr(d_z), _ptr(d_w), _ptr(res.G), _ptr(eps), _stream(stream))
     return eps[:rows]
+
+
+# --- quantum molecular dynamics ------------------------------------------------------
+
+def md_kick(force, mass, h_fs, vel, stream=None):
+    """vel += (h/2) force / mass in place (nm/fs; force eV/nm, mass amu)."""
+    n = int(vel.shape[0])
+    _call("sgf_md_kick", n, _ptr(force), _ptr(mass), float(h_fs), _ptr(vel), _stream(stream))
+    return vel
+
+
+def md_drift(vel, h_fs, xyz, stream=None):
+    """xyz += h vel in place (nm)."""
+    n = int(xyz.shape[0])
+    _call("sgf_md_drift", n, _ptr(vel), float(h_fs), _ptr(xyz), _stream(stream))
+    return xyz
+
+
+class QMD:
+    """Quantum molecular dynamics with the band forces of the shifted solves:
+    every step is velocity Verlet around the whole path at the new positions
+    (neighbour list and H / S, local subspaces, shifted solve of every
+    column, band forces with the energy-density term when S != I).
+
+    xyz, vel: [n_atoms, 3] (nm, nm/fs), mass: [n_atoms] amu; z, w: shifts and
+    quadrature weights; radius: local-subspace radius (nm)."""
+
+    def __init__(self, xyz, vel, mass, params, z, w, tol=1e-12, radius=1.0, prune=True, device="cuda",
+                 **solve_kw):
+        torch = _torch()
+        self.xyz = _dev(xyz, torch.float64, device).clone()
+        self.vel = _dev(vel, torch.float64, device).clone()
+        self.mass = _dev(mass, torch.float64, device).contiguous()
+        self.params, self.z, self.w, self.tol, self.radius, self.prune = params, z, w, tol, radius, prune
+        self.solve_kw = solve_kw
+        self.columns = np.arange(4 * self.xyz.shape[0], dtype=np.int64)
+        self.force, self.last = self.forces()
+
+    def forces(self):
+        """Band forces at the current positions (and the solve behind them)."""
+        system = build_hamiltonian(self.xyz, self.params, device=self.xyz.device)
+        prep = prepare(system, self.columns, radius=self.radius, prune=self.prune)
+        ovl = bool(self.params.overlap)
+        res = solve_prepared(prep, self.z, self.w, tol=self.tol, g_out=False, eps_out=ovl, **self.solve_kw)
+        return band_forces(prep, res, self.params, xyz=self.xyz, eps=res.eps if ovl else None), (prep, res)
+
+    def step(self, h_fs=1.0):
+        md_kick(self.force, self.mass, h_fs, self.vel)
+        md_drift(self.vel, h_fs, self.xyz)
+        self.force, self.last = self.forces()
+        md_kick(self.force, self.mass, h_fs, self.vel)
+        return self

@@ -1,5 +1,6 @@
 // forces.hip -- band-structure forces from the density matrix (the force
-// step of the quantum molecular dynamics, Sec. 2 of the paper).
+// step of the quantum molecular dynamics, Sec. 2 of the paper), and the
+// velocity-Verlet update that advances the atoms with them.
 //
 // The band energy of the solved columns is E_band = sum_j sum_{i in P(j)}
 // rho_ij H_ij (per spin).  With an orthogonal basis (S = I) the force is
@@ -119,11 +120,47 @@ __global__ __launch_bounds__(FORCE_T) void k_band_force(int64_t n_cols, int64_t 
     add3(F, C, own, -1.0);
 }
 
+// Velocity Verlet (Swope et al. 1982), one thread per coordinate: the half
+// kick v += (h / 2) F / m and the drift x += h v, in nm, fs, eV/nm and amu.
+__global__ void k_md_kick(int64_t n3, const double *__restrict__ F, const double *__restrict__ mass, double c,
+                          double *__restrict__ v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n3; i += (int64_t)gridDim.x * blockDim.x)
+        v[i] = fma(c / mass[i / 3], F[i], v[i]);
+}
+
+__global__ void k_md_drift(int64_t n3, const double *__restrict__ v, double h, double *__restrict__ x) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n3; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = fma(h, v[i], x[i]);
+}
+
 }  // namespace
 
 }  // namespace sgf
 
 using namespace sgf;
+
+extern "C" sgf_status sgf_md_kick(int64_t n_atoms, const double *d_force, const double *d_mass, double h_fs,
+                                  double *d_vel, void *stream) {
+    SGF_REQUIRE(n_atoms >= 0 && d_force && d_mass && d_vel, "sgf_md_kick: NULL argument or n_atoms < 0");
+    SGF_REQUIRE(h_fs == h_fs && h_fs > -1e6 && h_fs < 1e6, "sgf_md_kick: bad time step");
+    if (n_atoms == 0) return SGF_OK;
+    const int64_t n3 = 3 * n_atoms;
+    const unsigned g = (unsigned)((n3 + FORCE_T - 1) / FORCE_T < 65536 ? (n3 + FORCE_T - 1) / FORCE_T : 65536);
+    k_md_kick<<<g, FORCE_T, 0, as_stream(stream)>>>(n3, d_force, d_mass, 0.5 * h_fs * SGF_ACCEL_EV_NM_AMU, d_vel);
+    SGF_LAUNCHED();
+    return SGF_OK;
+}
+
+extern "C" sgf_status sgf_md_drift(int64_t n_atoms, const double *d_vel, double h_fs, double *d_xyz, void *stream) {
+    SGF_REQUIRE(n_atoms >= 0 && d_vel && d_xyz, "sgf_md_drift: NULL argument or n_atoms < 0");
+    SGF_REQUIRE(h_fs == h_fs && h_fs > -1e6 && h_fs < 1e6, "sgf_md_drift: bad time step");
+    if (n_atoms == 0) return SGF_OK;
+    const int64_t n3 = 3 * n_atoms;
+    const unsigned g = (unsigned)((n3 + FORCE_T - 1) / FORCE_T < 65536 ? (n3 + FORCE_T - 1) / FORCE_T : 65536);
+    k_md_drift<<<g, FORCE_T, 0, as_stream(stream)>>>(n3, d_vel, h_fs, d_xyz);
+    SGF_LAUNCHED();
+    return SGF_OK;
+}
 
 extern "C" sgf_status sgf_band_forces(const sgf_system *sys, const double *d_xyz, const sgf_tb_params *p,
                                       int64_t n_cols, const int64_t *d_cols, const int64_t *d_proj_off,
