@@ -558,6 +558,65 @@ def qmd_steps(sgf, wl, steps=5, batch_cols=131072):
             "max_displacement_nm": moved, "columns_not_converged": int(np.sum(st != 0))}
 
 
+def fermi_poles_leg(sgf, W, dev, ws_gib, kT=0.1, mu=0.0, n_poles=48, reps=5, check_n=300):
+    """Fewer shifts: the bundle's 473,200 columns with the 49 shifts of the
+    Fermi-Dirac pole expansion at kT = 0.1 eV (seed at the pole nearest the
+    real axis), timed like the other workloads, and its rho against the plain
+    definition f(H_L) from the dense eigen-decomposition of the local
+    subspaces of `check_n` seeded columns; the real-axis grid's rho (the
+    headline step's 128 shifts) is measured against the same definition."""
+    import torch
+    from oracle import contour
+    import oracle
+    wl = W.config_bundle()
+    s = sgf.system_for(wl)
+    prep = sgf.prepare(s, wl.columns, radius=wl.radius, prune=True)
+    z, w = sgf.fermi_shifts(n_poles, kT, mu)
+    batch = sgf.batch_limit(prep, z.size, int(ws_gib * (1 << 30)))
+    buf, times, seeds, shifts = None, [], [], []
+    for rep in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = sgf.solve_prepared(prep, z, w, tol=wl.tol, seed_index=-2, batch_cols=batch, out=buf, profile=True)
+        prof = sgf.solve_profile()
+        torch.cuda.synchronize()
+        if rep:
+            times.append((time.perf_counter() - t0) * 1e3)
+            seeds.append(prof[0])
+            shifts.append(prof[1])
+        buf = res._out
+    ms = float(np.median(times))
+    st = res.status.cpu().numpy()
+    conv = int(np.sum(res.resid.cpu().numpy() <= wl.tol))
+    pick = np.sort(np.random.default_rng(1603).choice(wl.columns.size, check_n, replace=False))
+    off = prep.proj_off.cpu().numpy()
+    rows = np.concatenate([np.arange(off[c], off[c + 1]) for c in pick])
+    rho = res.rho[torch.as_tensor(rows, device=dev)].cpu().numpy()
+    grid = sgf.solve_prepared(prep, wl.z, wl.w, tol=wl.tol, g_out=False, batch_cols=batch)
+    rho_grid = grid.rho[torch.as_tensor(rows, device=dev)].cpu().numpy()
+    iters_grid = float(grid.iters.float().mean())
+    del grid
+    b = oracle.system_for(wl)
+    poff, _, exact = contour.fermi_rho_columns(b, wl.xyz, wl.columns[pick], kT, mu, radius=wl.radius, prune=True)
+    e_pole = e_grid = 0.0
+    for i in range(pick.size):
+        a, c = poff[i], poff[i + 1]
+        sc = np.abs(exact[a:c]).max()
+        e_pole = max(e_pole, np.abs(rho[a:c] - exact[a:c]).max() / sc)
+        e_grid = max(e_grid, np.abs(rho_grid[a:c] - exact[a:c]).max() / sc)
+    out = {"workload": "bundle, all 473,200 columns, R = 1.0 nm pruned, Fermi-Dirac rho at kT = 0.1 eV, mu = 0",
+           "shifts": int(z.size), "poles": n_poles, "tol": wl.tol, "ms": ms, "reps": reps, "seed_ms": float(np.median(seeds)),
+           "shift_ms": float(np.median(shifts)), "solves_per_s": conv / (ms * 1e-3),
+           "iters_mean": float(res.iters.float().mean()), "columns_not_converged": int(np.sum(st != 0)),
+           "rho_vs_f_H_L": {"columns": int(check_n), "poles": e_pole, "real_axis_grid_128": e_grid,
+                            "real_axis_iters_mean": iters_grid}}
+    log(f"[bench] Fermi poles: {z.size} shifts in {ms:.1f} ms, {out['iters_mean']:.1f} iterations; rho vs f(H_L) "
+        f"{e_pole:.2e} (real-axis grid {e_grid:.2e}, {iters_grid:.1f} iterations)")
+    del res, buf, prep, s
+    torch.cuda.empty_cache()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -760,6 +819,10 @@ def main(argv=None):
         hbm["wavepacket"] = wp_stream(sgf, W, dev)
 
     extra, extra_keep = None, None
+    fewer = None
+    if not args.no_extra and not args.no_cpu_baseline:
+        torch.cuda.empty_cache()
+        fewer = fermi_poles_leg(sgf, W, dev, min(args.ws_gib, 64.0))
     if not args.no_extra:
         torch.cuda.empty_cache()
         extra, extra_keep = extra_workloads(sgf, W, dev, min(args.ws_gib, 64.0), 1000, only=only)
@@ -806,6 +869,7 @@ def main(argv=None):
         "hbm_stream": hbm,
         "after_rho": post,
         "other_workloads": extra,
+        "fewer_shifts": fewer,
         "autotune": {"choice": launch, "timings_ms": tuned["timings_ms"], "sample_columns": 32768},
         "variants": variants,
         "scheduler": train_info,

@@ -255,7 +255,10 @@ typedef struct {
                               FP64 recurrence scalars, FP64 true-residual monitor and FP64 epilogue) */
     double tol;            /* shift k stops when ||s_{n+1}||_2 / |pi^k_{n+1}| <= tol ||b||_2 */
     int32_t max_iter;      /* <= 0: 10 * (local orbitals) per column (mixed precision: 40 *) */
-    int32_t seed_index;    /* < 0: n_shifts / 2 */
+    int32_t seed_index;    /* >= 0: that shift; -1 (or below -2): n_shifts / 2; -2: the shift nearest
+                              the real axis (smallest Im z; among equals the one nearest n_shifts / 2),
+                              the slowest to converge, so that the seed iterates at least as long as any
+                              other shift and its residual cannot underflow first */
     int32_t monitor_every; /* mixed: FP64 true residual every K iterations (0: only at the end) */
     int32_t stage_lds;     /* seed pass, S = I: -1 auto (register rows for subspaces of <= 64 orbitals and
                               <= 8 blocks per row, else an LDS-staged operator when it fits);
@@ -428,6 +431,25 @@ sgf_status sgf_solve_stage_shifts(int32_t n_shifts, const double *z, const doubl
  * those events).  *batches = number of launches of each pass.  EINVAL if no
  * profiled solve is pending; the events are released by this call. */
 sgf_status sgf_solve_profile(double *seed_ms, double *shift_ms, int32_t *batches);
+
+/* Shifts and weights for the Fermi-Dirac density matrix (HOST call).  The
+ * order-N energy of the Introduction needs rho = f(H), f(e) = 1/(1 +
+ * exp((e - mu)/kT)); a real-axis grid needs energies close to the axis and
+ * many of them.  The pole expansion of f from the continued fraction of
+ * tanh (Ozaki, Phys. Rev. B 75, 035123 (2007)),
+ *   f(y) = 1/2 - sum_p R_p (1/(y - i z_p) + 1/(y + i z_p)), y = (e - mu)/kT,
+ * gives rho = S^{-1}/2 + 2 kT sum_p R_p Re G(mu + i z_p kT), with S^{-1} =
+ * Re(i M G(i M)) up to |H|^2/M^2.  Writes n_poles + 1 complex shifts z and
+ * weights w (host, interleaved re, im) for sgf_shifted_solve: z_p = mu + i
+ * z_p kT with w_p = -2 pi i kT R_p for p = 0 .. n_poles-1, nearest the real
+ * axis first (z_0 = mu + i pi kT to rounding), then z = i*moment with
+ * w = pi moment / 2.  The expansion holds for |e - mu| up to about
+ * 20 n_poles kT (measured: 40 poles reach 5e-10 at |y| = 600, 60 poles 3e-13
+ * at |y| = 1000); choose n_poles from the spectral bounds (sgf_wp_bounds).
+ * A seed at the pole nearest the axis (opts.seed_index = -2) keeps the seed
+ * system the slowest one.  EINVAL on n_poles outside [1, 511], kT <= 0,
+ * moment <= 0 or NULL outputs. */
+sgf_status sgf_fermi_shifts(int32_t n_poles, double kT, double mu, double moment, double *z, double *w);
 
 /* ------------------------------------------------------------------------ */
 /* Global operator application                                                */

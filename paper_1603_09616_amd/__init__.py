@@ -29,7 +29,7 @@ EXPORTED = (
     "sgf_bsr_apply", "sgf_solve_stage_shifts", "sgf_trace_workspace", "sgf_traces", "sgf_occupation",
     "sgf_fermi_level", "sgf_wp_workspace", "sgf_wp_bounds", "sgf_wp_terms", "sgf_wp_propagate",
     "sgf_band_forces", "sgf_energy_density", "sgf_shifted_solve_static", "sgf_hamiltonian_size",
-    "sgf_system_from_bsr", "sgf_system_destroy", "sgf_md_kick", "sgf_md_drift",
+    "sgf_system_from_bsr", "sgf_system_destroy", "sgf_md_kick", "sgf_md_drift", "sgf_fermi_shifts",
 )
 MLP_NFEAT, MLP_NPARAM, MLP_BATCH = 5, 4619, 128
 STATIC_SCRATCH_BYTES = 256 << 20   # SGF_STATIC_SCRATCH_BYTES
@@ -130,6 +130,7 @@ def lib():
             "sgf_system_from_bsr": [P, P, P],
             "sgf_md_kick": [i64, P, P, dbl, P, P],
             "sgf_md_drift": [i64, P, dbl, P, P],
+            "sgf_fermi_shifts": [i32, dbl, dbl, dbl, P, P],
         }
         for name, args in sigs.items():
             f = getattr(L, name)
@@ -674,6 +675,20 @@ def solve_workload(wl, system: Optional[System] = None, cols=None, prune=True, *
             rpc = rpc[[pos[int(j)] for j in cols]]
     kw.setdefault("tol", wl.tol)
     return shifted_solve(system, cols, wl.z, wl.w, radius=wl.radius, radius_per_col=rpc, prune=prune, **kw)
+
+
+# --- Fermi-Dirac shifts -------------------------------------------------------------
+
+def fermi_shifts(n_poles: int, kT: float, mu: float, moment: float = 1e8):
+    """(z, w) complex128 [n_poles + 1]: the pole expansion of the Fermi
+    function as shifts and weights of the shifted solve, so that its rho is
+    f(H) at temperature kT (eV) and chemical potential mu (eV).  The pole
+    nearest the real axis comes first; solve with seed_index=-2."""
+    z = np.zeros(2 * (n_poles + 1))
+    w = np.zeros(2 * (n_poles + 1))
+    _call("sgf_fermi_shifts", int(n_poles), float(kT), float(mu), float(moment), z.ctypes.data_as(P),
+          w.ctypes.data_as(P))
+    return z.view(np.complex128), w.view(np.complex128)
 
 
 # --- global operator ------------------------------------------------------------

@@ -1996,7 +1996,13 @@ static sgf_status shifted_solve_in(const sgf_system *sys, const sgf_plan *plan, 
     }
     SGF_REQUIRE(!opts->eps_out || w, "sgf_shifted_solve: the energy-density output needs the weights w");
     SGF_REQUIRE(opts->max_iter >= 0, "sgf_shifted_solve: max_iter must be >= 0");
-    const int seed = opts->seed_index < 0 ? n_shifts / 2 : opts->seed_index;
+    int seed = opts->seed_index < 0 ? n_shifts / 2 : opts->seed_index;
+    if (opts->seed_index == -2) {  // the shift nearest the real axis
+        for (int kk = 0; kk < n_shifts; ++kk) {
+            const double a = z[2 * kk + 1], b = z[2 * seed + 1];
+            if (a < b || (a == b && std::abs(kk - n_shifts / 2) < std::abs(seed - n_shifts / 2))) seed = kk;
+        }
+    }
     SGF_REQUIRE(seed < n_shifts, "sgf_shifted_solve: seed_index %d >= n_shifts %d", seed, n_shifts);
     for (int kk = 0; kk < n_shifts; ++kk)
         SGF_REQUIRE(z[2 * kk + 1] > 0, "sgf_shifted_solve: Im z[%d] = %g is not positive", kk, z[2 * kk + 1]);
