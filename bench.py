@@ -561,13 +561,11 @@ def qmd_steps(sgf, wl, steps=5, batch_cols=131072):
 def fermi_poles_leg(sgf, W, dev, ws_gib, kT=0.1, mu=0.0, n_poles=48, reps=5, check_n=300):
     """Fewer shifts: the bundle's 473,200 columns with the 49 shifts of the
     Fermi-Dirac pole expansion at kT = 0.1 eV (seed at the pole nearest the
-    real axis), timed like the other workloads, and its rho against the plain
-    definition f(H_L) from the dense eigen-decomposition of the local
-    subspaces of `check_n` seeded columns; the real-axis grid's rho (the
-    headline step's 128 shifts) is measured against the same definition."""
+    real axis), timed like the other workloads.  Returns the timings and the
+    rho of `check_n` seeded columns from these shifts and from the real-axis
+    grid (the headline step's 128 shifts), which the CPU-baseline leg checks
+    against the plain definition f(H_L) (check_fermi)."""
     import torch
-    from oracle import contour
-    import oracle
     wl = W.config_bundle()
     s = sgf.system_for(wl)
     prep = sgf.prepare(s, wl.columns, radius=wl.radius, prune=True)
@@ -596,6 +594,25 @@ def fermi_poles_leg(sgf, W, dev, ws_gib, kT=0.1, mu=0.0, n_poles=48, reps=5, che
     rho_grid = grid.rho[torch.as_tensor(rows, device=dev)].cpu().numpy()
     iters_grid = float(grid.iters.float().mean())
     del grid
+    out = {"workload": "bundle, all 473,200 columns, R = 1.0 nm pruned, Fermi-Dirac rho at kT = 0.1 eV, mu = 0",
+           "shifts": int(z.size), "poles": n_poles, "tol": wl.tol, "ms": ms, "reps": reps, "seed_ms": float(np.median(seeds)),
+           "shift_ms": float(np.median(shifts)), "solves_per_s": conv / (ms * 1e-3),
+           "iters_mean": float(res.iters.float().mean()), "columns_not_converged": int(np.sum(st != 0)),
+           "real_axis_grid": {"shifts": int(wl.z.size), "iters_mean": iters_grid}}
+    log(f"[bench] Fermi poles: {z.size} shifts in {ms:.1f} ms, {out['iters_mean']:.1f} iterations "
+        f"(real-axis grid: {iters_grid:.1f})")
+    del res, buf, prep, s
+    torch.cuda.empty_cache()
+    return out, (wl, pick, rho, rho_grid, kT, mu)
+
+
+def check_fermi(keep):
+    """CPU-baseline leg: the plain definition rho = f(H_L) (dense
+    eigen-decomposition of each sampled column's local subspace, oracle)
+    against the pole-expansion rho and the real-axis grid's rho."""
+    import oracle
+    from oracle import contour
+    wl, pick, rho, rho_grid, kT, mu = keep
     b = oracle.system_for(wl)
     poff, _, exact = contour.fermi_rho_columns(b, wl.xyz, wl.columns[pick], kT, mu, radius=wl.radius, prune=True)
     e_pole = e_grid = 0.0
@@ -604,17 +621,8 @@ def fermi_poles_leg(sgf, W, dev, ws_gib, kT=0.1, mu=0.0, n_poles=48, reps=5, che
         sc = np.abs(exact[a:c]).max()
         e_pole = max(e_pole, np.abs(rho[a:c] - exact[a:c]).max() / sc)
         e_grid = max(e_grid, np.abs(rho_grid[a:c] - exact[a:c]).max() / sc)
-    out = {"workload": "bundle, all 473,200 columns, R = 1.0 nm pruned, Fermi-Dirac rho at kT = 0.1 eV, mu = 0",
-           "shifts": int(z.size), "poles": n_poles, "tol": wl.tol, "ms": ms, "reps": reps, "seed_ms": float(np.median(seeds)),
-           "shift_ms": float(np.median(shifts)), "solves_per_s": conv / (ms * 1e-3),
-           "iters_mean": float(res.iters.float().mean()), "columns_not_converged": int(np.sum(st != 0)),
-           "rho_vs_f_H_L": {"columns": int(check_n), "poles": e_pole, "real_axis_grid_128": e_grid,
-                            "real_axis_iters_mean": iters_grid}}
-    log(f"[bench] Fermi poles: {z.size} shifts in {ms:.1f} ms, {out['iters_mean']:.1f} iterations; rho vs f(H_L) "
-        f"{e_pole:.2e} (real-axis grid {e_grid:.2e}, {iters_grid:.1f} iterations)")
-    del res, buf, prep, s
-    torch.cuda.empty_cache()
-    return out
+    log(f"[bench] Fermi poles: rho vs f(H_L) {e_pole:.2e} (real-axis grid {e_grid:.2e})")
+    return {"columns": int(pick.size), "poles": e_pole, "real_axis_grid": e_grid}
 
 
 def main(argv=None):
@@ -819,10 +827,10 @@ def main(argv=None):
         hbm["wavepacket"] = wp_stream(sgf, W, dev)
 
     extra, extra_keep = None, None
-    fewer = None
-    if not args.no_extra and not args.no_cpu_baseline:
+    fewer, fewer_keep = None, None
+    if not args.no_extra:
         torch.cuda.empty_cache()
-        fewer = fermi_poles_leg(sgf, W, dev, min(args.ws_gib, 64.0))
+        fewer, fewer_keep = fermi_poles_leg(sgf, W, dev, min(args.ws_gib, 64.0))
     if not args.no_extra:
         torch.cuda.empty_cache()
         extra, extra_keep = extra_workloads(sgf, W, dev, min(args.ws_gib, 64.0), 1000, only=only)
@@ -833,6 +841,8 @@ def main(argv=None):
         if extra:
             for name, a in check_extra(extra_keep).items():
                 extra[name]["accuracy_vs_oracle"] = a
+        if fewer:
+            fewer["rho_vs_f_H_L"] = check_fermi(fewer_keep)
         ref13 = None
         for name, (G, rho, st) in samples.items():
             r = ref
