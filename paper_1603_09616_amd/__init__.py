@@ -957,25 +957,35 @@ class QMD:
     column, band forces with the energy-density term when S != I).
 
     xyz, vel: [n_atoms, 3] (nm, nm/fs), mass: [n_atoms] amu; z, w: shifts and
-    quadrature weights; radius: local-subspace radius (nm)."""
+    quadrature weights; radius: local-subspace radius (nm); ws_budget: bytes
+    of solve workspace per step (the columns run in launches of what it
+    holds, which follows the subspaces as the atoms move)."""
 
     def __init__(self, xyz, vel, mass, params, z, w, tol=1e-12, radius=1.0, prune=True, device="cuda",
-                 **solve_kw):
+                 ws_budget=None, **solve_kw):
         torch = _torch()
         self.xyz = _dev(xyz, torch.float64, device).clone()
         self.vel = _dev(vel, torch.float64, device).clone()
         self.mass = _dev(mass, torch.float64, device).contiguous()
         self.params, self.z, self.w, self.tol, self.radius, self.prune = params, z, w, tol, radius, prune
         self.solve_kw = solve_kw
+        self.ws_budget = ws_budget   # bytes of solve workspace per step (None: all columns in one launch)
         self.columns = np.arange(4 * self.xyz.shape[0], dtype=np.int64)
+        # the column -> subspace-centre map does not change with the positions
+        centers, radii, col_plan = plan_columns(self.columns, radius)
+        self._plan_in = tuple(_dev(a, t, device) for a, t in ((self.columns, torch.int64), (col_plan, torch.int32),
+                                                              (centers, torch.int32), (radii, torch.float64)))
         self.force, self.last = self.forces()
 
     def forces(self):
         """Band forces at the current positions (and the solve behind them)."""
         system = build_hamiltonian(self.xyz, self.params, device=self.xyz.device)
-        prep = prepare(system, self.columns, radius=self.radius, prune=self.prune)
+        prep = prepare_planned(system, *self._plan_in, prune=self.prune)
         ovl = bool(self.params.overlap)
-        res = solve_prepared(prep, self.z, self.w, tol=self.tol, g_out=False, eps_out=ovl, **self.solve_kw)
+        kw = dict(self.solve_kw)
+        if self.ws_budget is not None:
+            kw["batch_cols"] = batch_limit(prep, len(self.z), self.ws_budget)
+        res = solve_prepared(prep, self.z, self.w, tol=self.tol, g_out=False, eps_out=ovl, **kw)
         return band_forces(prep, res, self.params, xyz=self.xyz, eps=res.eps if ovl else None), (prep, res)
 
     def step(self, h_fs=1.0):
