@@ -251,7 +251,9 @@ def hbm_stream(sgf, W, dev, reps=50):
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / reps
             nbytes = s.nnzb * (16 * bc // 2 + 4) + (s.n_atoms + 1) * 4 + 2 * n * k * bc
-            name = {1: f"k_bsr_apply<{dtn}, 1, false>"}.get(k, f"k_bsr_apply_br<{dtn}, {k}, false>")
+            rpt = 2 if k == 8 or (k == 4 and prec == "fp32") else 1
+            name = (f"k_bsr_apply<{dtn}, 1, false>" if k == 1 else
+                    f"k_bsr_apply_lx<{dtn}, {k}, {rpt}, false>")
             traffic = recorded_traffic(name, "apply")
             cases[f"{prec}_rhs{k}"] = {"ms": ms, "bytes": nbytes, "GBps": nbytes / ms / 1e6,
                                        "frac": nbytes / ms / 1e6 / PEAK_HBM_GBS, "traffic": traffic,

@@ -460,7 +460,8 @@ sgf_status sgf_fermi_shifts(int32_t n_poles, double kT, double mu, double moment
  * against its right-hand side in FP64).  z: HOST complex (re, im).
  * precision 0: FP64 operator (h, s), d_x / d_y complex128; 1: FP32 shadows
  * (h32, s32), complex64.  Layout [4 n_atoms][n_rhs] (right-hand sides
- * contiguous per orbital); d_x and d_y must not alias.  S = I when the
+ * contiguous per orbital); d_x and d_y must not alias and must be 16-byte
+ * aligned (EINVAL otherwise).  S = I when the
  * system has no overlap.  Asynchronous on the stream.  One pass over the
  * matrix in HBM: 16 n_rhs complex multiply-adds per 4x4 block, so the call
  * is bound by HBM bandwidth. */
