@@ -32,6 +32,10 @@ if ROOT not in sys.path:
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector peak
 PEAK_HBM_GBS = 8000.0
+# columns (whole plans) the autotuner times each launch candidate on: enough
+# persistent waves per compute unit that the tail of a launch weighs as it
+# does on the whole bundle
+TUNE_SAMPLE = 131072
 
 
 def log(*a):
@@ -705,7 +709,7 @@ def main(argv=None):
     if args.no_autotune:
         tuned = {"choice": {}, "timings_ms": None}
     else:
-        tuned = autotune.tune(p_probe, wl.z, wl.w, wl.tol, use_cache=False, log=log)
+        tuned = autotune.tune(p_probe, wl.z, wl.w, wl.tol, use_cache=False, log=log, sample=TUNE_SAMPLE)
     launch = tuned["choice"]
     torch.cuda.empty_cache()
     log(f"[bench] autotuned launch: {launch}")
@@ -722,8 +726,7 @@ def main(argv=None):
             prep = sgf.prepare_planned(s, d_cols, d_cp, d_centers, d_radii, prune=True)
             order = None
             if order_mode == "learned":
-                pred = model.predict(sgf.features(prep))
-                order = sgf.order_by_prediction(pred, 0.0, float(np.log(4096.0)))
+                order = sgf.learned_order(prep, model)
             res = sgf.solve_prepared(prep, wl.z, wl.w, tol=tol, precision=precision, g_out=not args.no_g,
                                      batch_cols=batch_cols, order=order, out=out_buf.get("out"), profile=profile,
                                      shift_iters=True, **lo)
@@ -889,7 +892,7 @@ def main(argv=None):
         "after_rho": post,
         "other_workloads": extra,
         "fewer_shifts": fewer,
-        "autotune": {"choice": launch, "timings_ms": tuned["timings_ms"], "sample_columns": 32768},
+        "autotune": {"choice": launch, "timings_ms": tuned["timings_ms"], "sample_columns": TUNE_SAMPLE},
         "variants": variants,
         "scheduler": train_info,
         "converged_solves": converged,

@@ -260,9 +260,11 @@ typedef struct {
                               the slowest to converge, so that the seed iterates at least as long as any
                               other shift and its residual cannot underflow first */
     int32_t monitor_every; /* mixed: FP64 true residual every K iterations (0: only at the end) */
-    int32_t stage_lds;     /* seed pass, S = I: -1 auto (register rows for subspaces of <= 64 orbitals and
-                              <= 8 blocks per row, else an LDS-staged operator when it fits);
-                              1 LDS-staged operator; 0 operator read from global.
+    int32_t stage_lds;     /* seed pass, S = I: -1 auto (for subspaces of <= 64 orbitals and <= 8 blocks per
+                              row: four columns per wavefront with the blocks in LDS at <= 128 shifts,
+                              one column per wavefront with its rows in registers above; else an
+                              LDS-staged operator when it fits); 3 one column per wavefront with rows in
+                              registers; 1 LDS-staged operator; 0 operator read from global.
                               S != I: -1 auto (subspaces of <= 16 atoms in a launch with the dense
                               overlap inverse, larger ones in a second launch with its packed
                               triangle; both with two wavefronts per column when every subspace
@@ -522,6 +524,18 @@ sgf_status sgf_mlp_gradient(const float *d_params, const float *d_feat, const fl
 sgf_status sgf_order_workspace(size_t *ws_bytes);
 sgf_status sgf_order_by_prediction(const float *d_pred, int64_t n, float y_lo, float y_hi, int32_t *d_order,
                                    void *d_ws, size_t ws_bytes, void *stream);
+
+/* The same order by plans: the columns that share a plan (d_col_plan, as in
+ * the solve) stay next to each other, and the plans are queued by the
+ * largest prediction among their columns (counting sort over [y_lo, y_hi]).
+ * The seed pass that runs four columns of one plan per wavefront then finds
+ * a plan's columns together.  Columns with a plan index outside
+ * [0, n_plans) go last.  Writes a permutation of 0..n-1 into d_order; the
+ * order inside a plan's run is unspecified (results do not depend on it). */
+sgf_status sgf_order_groups_workspace(int64_t n_plans, size_t *ws_bytes);
+sgf_status sgf_order_groups_by_prediction(const float *d_pred, int64_t n, const int32_t *d_col_plan, int64_t n_plans,
+                                          float y_lo, float y_hi, int32_t *d_order, void *d_ws, size_t ws_bytes,
+                                          void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* After rho: traces, electron count, band energy, Fermi level               */

@@ -30,6 +30,7 @@ EXPORTED = (
     "sgf_fermi_level", "sgf_wp_workspace", "sgf_wp_bounds", "sgf_wp_terms", "sgf_wp_propagate",
     "sgf_band_forces", "sgf_energy_density", "sgf_shifted_solve_static", "sgf_hamiltonian_size",
     "sgf_system_from_bsr", "sgf_system_destroy", "sgf_md_kick", "sgf_md_drift", "sgf_fermi_shifts",
+    "sgf_order_groups_workspace", "sgf_order_groups_by_prediction",
 )
 MLP_NFEAT, MLP_NPARAM, MLP_BATCH = 5, 4619, 128
 STATIC_SCRATCH_BYTES = 256 << 20   # SGF_STATIC_SCRATCH_BYTES
@@ -131,6 +132,8 @@ def lib():
             "sgf_md_kick": [i64, P, P, dbl, P, P],
             "sgf_md_drift": [i64, P, dbl, P, P],
             "sgf_fermi_shifts": [i32, dbl, dbl, dbl, P, P],
+            "sgf_order_groups_workspace": [i64, P],
+            "sgf_order_groups_by_prediction": [P, i64, P, i64, ctypes.c_float, ctypes.c_float, P, P, szt, P],
         }
         for name, args in sigs.items():
             f = getattr(L, name)
@@ -834,9 +837,25 @@ class IterationModel:
 
 
 def learned_order(prep: Prepared, model: "IterationModel", stream=None, y_lo=0.0, y_hi=float(np.log(4096.0))):
-    """Work-queue order of the prepared columns, largest predicted iteration
-    count first (features -> network -> counting sort on the device)."""
-    return order_by_prediction(model.predict(features(prep, stream), stream), y_lo, y_hi, stream)
+    """Work-queue order of the prepared columns: plans by the largest
+    predicted iteration count among their columns, the columns of a plan
+    together (features -> network -> grouped counting sort on the device)."""
+    return order_groups_by_prediction(model.predict(features(prep, stream), stream), prep.col_plan,
+                                      prep.plan.n_plans, y_lo, y_hi, stream)
+
+
+def order_groups_by_prediction(pred, col_plan, n_plans, y_lo, y_hi, stream=None):
+    """Permutation of the columns with the columns of each plan together,
+    plans by their largest prediction first."""
+    torch = _torch()
+    n = pred.numel()
+    ws = ctypes.c_size_t()
+    _call("sgf_order_groups_workspace", int(n_plans), ctypes.byref(ws))
+    d_ws = _bytes(ws.value, pred.device)
+    order = torch.empty(max(n, 1), dtype=torch.int32, device=pred.device)
+    _call("sgf_order_groups_by_prediction", _ptr(pred.contiguous()), n, _ptr(col_plan), int(n_plans), float(y_lo),
+          float(y_hi), _ptr(order), _ptr(d_ws), ws.value, _stream(stream))
+    return order[:n]
 
 
 def order_by_prediction(pred, y_lo, y_hi, stream=None):

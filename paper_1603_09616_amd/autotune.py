@@ -2,15 +2,18 @@
 
 The choices that do not change the method, only how it maps onto the chip:
 
-* ``stage_lds``: the seed-pass variant (-1: register rows when every local
-  subspace fits a wavefront, 1: local operator staged in LDS, 0: operator
-  read from global memory);
+* ``stage_lds``: the seed-pass variant (-1: when every local subspace fits
+  a wavefront, four columns of a plan per wavefront with its blocks in LDS
+  up to 128 shifts and register rows above; 3: register rows, one column
+  per wavefront; 1: local operator staged in LDS; 0: operator read from
+  global memory);
 * ``shifts_per_lane``: shifts handled by one lane of the shift pass (1, 2);
 * ``grid``: persistent seed-pass workgroups (0: as many as fit the device).
 
 Each candidate is timed with HIP events on the launch stream, on a seeded
-sample of the prepared columns (solved through the work-queue order, so no
-re-planning), median of ``reps`` runs after a warm-up.  The winner is cached
+sample of the prepared columns (whole plans, their columns next to each
+other, solved through the work-queue order, so no re-planning), median of
+``reps`` runs after a warm-up.  The winner is cached
 in a JSON file keyed by the device and the shape of the workload (precision,
 shift count, largest subspace, largest row, projection size, overlap), and
 reused by later calls with the same key.  Results do not depend on the
@@ -38,7 +41,7 @@ def signature(totals, n_shifts: int, precision: str, has_overlap: bool, device_n
 def candidates(totals, precision: str, has_overlap: bool) -> list:
     """The launch choices that apply to this workload shape."""
     register_ok = totals.max_loc_atoms <= 16 and totals.max_row_blocks <= 8 and not has_overlap
-    seeds = [-1] if precision == "mixed" or has_overlap else ([-1, 1, 0] if register_ok else [-1, 0])
+    seeds = [-1] if precision == "mixed" or has_overlap else ([-1, 3, 1, 0] if register_ok else [-1, 0])
     lanes = [1, 2] if (precision == "fp64" and totals.max_proj_atoms <= 5) else [1]
     grids = [0, 2048, 1024]
     out = []
@@ -81,8 +84,16 @@ def tune(prep, z, w=None, tol=1e-10, precision="fp64", sample=32768, reps=3, see
     if key in table:
         return {"choice": table[key]["choice"], "key": key, "timings_ms": None, "cached": True}
 
-    n = prep.cols.numel()
-    pick = np.sort(np.random.default_rng(seed).choice(n, min(sample, n), replace=False)).astype(np.int32)
+    # whole plans, drawn at random, with each plan's columns together (the
+    # four-column seed pass takes a plan's columns in one wavefront)
+    cp = prep.col_plan.cpu().numpy()
+    by_plan = np.argsort(cp, kind="stable")
+    plans = np.unique(cp)
+    chosen = np.random.default_rng(seed).permutation(plans)
+    per_plan = max(1, int(round(cp.size / max(plans.size, 1))))
+    chosen = np.sort(chosen[:max(1, sample // per_plan)])
+    keep = np.isin(cp[by_plan], chosen)
+    pick = by_plan[keep].astype(np.int32)
     order = torch.as_tensor(pick, device=prep.cols.device)
     out = None
     timings = {}

@@ -326,6 +326,61 @@ __global__ __launch_bounds__(ORDER_T) void k_order_scatter(const float *y, int64
     }
 }
 
+// ---------------------------------------------------------------------------
+// The same order at the granularity of plans: the columns that share a plan
+// (the orbitals of one atom) are kept next to each other, so that the seed
+// pass that runs a plan's columns in one wavefront finds them together; plans
+// are queued by the largest prediction among their columns.
+// ---------------------------------------------------------------------------
+__global__ void k_zero_i64_one(int64_t *p) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *p = 0;
+}
+
+__global__ void k_group_init(int32_t n_plans, float y_lo, float *key, int32_t *cnt, int32_t *fill) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_plans; i += gridDim.x * blockDim.x) {
+        key[i] = y_lo;
+        cnt[i] = 0;
+        fill[i] = 0;
+    }
+}
+
+// per plan: the largest (clamped) prediction of its columns, and its column count
+__global__ void k_group_key(const float *pred, int64_t n, const int32_t *col_plan, int32_t n_plans, float y_lo,
+                            float y_hi, float *key, int32_t *cnt) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t p = col_plan[i];
+        if (p < 0 || p >= n_plans) continue;
+        const float y = fminf(fmaxf(pred[i], y_lo), y_hi) - y_lo;   // >= 0: its bits order like the values
+        atomicMax(reinterpret_cast<int32_t *>(&key[p]), __float_as_int(y));
+        atomicAdd(&cnt[p], 1);
+    }
+}
+
+// after the plans are ordered: rank of each plan, and its column count by rank
+__global__ void k_group_rank(const int32_t *plan_order, int32_t n_plans, const int32_t *cnt, int32_t *rank,
+                             int64_t *size_by_rank) {
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n_plans; r += gridDim.x * blockDim.x) {
+        const int32_t p = plan_order[r];
+        rank[p] = r;
+        size_by_rank[r + 1] = cnt[p];
+        if (r == 0) size_by_rank[0] = 0;
+    }
+}
+
+// every column into its plan's run (offsets are inclusive sums shifted by one)
+__global__ void k_group_scatter(int64_t n, const int32_t *col_plan, int32_t n_plans, const int32_t *rank,
+                                const int64_t *start, int32_t *fill, int32_t *order, int64_t *n_out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t p = col_plan[i];
+        if (p < 0 || p >= n_plans) {
+            // a column without a valid plan goes last; the solve reports it
+            order[n - 1 - atomicAdd(reinterpret_cast<unsigned long long *>(n_out), 1ull)] = (int32_t)i;
+            continue;
+        }
+        order[start[rank[p]] + atomicAdd(&fill[p], 1)] = (int32_t)i;
+    }
+}
+
 }  // namespace sgf
 
 using namespace sgf;
@@ -416,6 +471,57 @@ extern "C" sgf_status sgf_order_by_prediction(const float *d_pred, int64_t n, fl
     sgf_status rc = inclusive_scan_i64(cnt + 1, ORDER_BUCKETS, scan, st);
     if (rc) return rc;
     k_order_scatter<<<dim3((unsigned)blocks), ORDER_T, 0, st>>>(d_pred, n, y_lo, y_hi, cnt, fill, d_order);
+    SGF_LAUNCHED();
+    return SGF_OK;
+}
+
+extern "C" sgf_status sgf_order_groups_workspace(int64_t n_plans, size_t *ws_bytes) {
+    SGF_REQUIRE(ws_bytes && n_plans >= 0 && n_plans < ((int64_t)1 << 31), "sgf_order_groups_workspace: bad arguments");
+    size_t order_ws = 0;
+    sgf_order_workspace(&order_ws);
+    const int64_t np = n_plans > 0 ? n_plans : 1;
+    *ws_bytes = align_up(4 * np) * 5 + align_up(8 * (np + 1)) + align_up(8) + prefix_scratch_bytes(np) + align_up(order_ws);
+    return SGF_OK;
+}
+
+extern "C" sgf_status sgf_order_groups_by_prediction(const float *d_pred, int64_t n, const int32_t *d_col_plan,
+                                                     int64_t n_plans, float y_lo, float y_hi, int32_t *d_order,
+                                                     void *d_ws, size_t ws_bytes, void *stream) {
+    SGF_REQUIRE(n >= 0 && (n == 0 || (d_pred && d_col_plan && d_order)), "sgf_order_groups_by_prediction: NULL array");
+    SGF_REQUIRE(y_hi > y_lo, "sgf_order_groups_by_prediction: y_hi must exceed y_lo");
+    SGF_REQUIRE(n < ((int64_t)1 << 31) && n_plans >= 1 && n_plans < ((int64_t)1 << 31),
+                "sgf_order_groups_by_prediction: bad sizes");
+    size_t need = 0;
+    sgf_order_groups_workspace(n_plans, &need);
+    SGF_REQUIRE(d_ws && ws_bytes >= need, "sgf_order_groups_by_prediction: workspace %zu < %zu", ws_bytes, need);
+    if (n == 0) return SGF_OK;
+    size_t order_ws = 0;
+    sgf_order_workspace(&order_ws);
+    Carve cv(d_ws, ws_bytes);
+    float *key = cv.take<float>(n_plans);
+    int32_t *cnt = cv.take<int32_t>(n_plans);
+    int32_t *fill = cv.take<int32_t>(n_plans);
+    int32_t *rank = cv.take<int32_t>(n_plans);
+    int32_t *plan_order = cv.take<int32_t>(n_plans);
+    int64_t *start = cv.take<int64_t>(n_plans + 1);
+    int64_t *n_out = cv.take<int64_t>(1);
+    char *scan = cv.take<char>(prefix_scratch_bytes(n_plans));
+    void *ows = cv.take<char>(order_ws);
+    hipStream_t st = as_stream(stream);
+    const unsigned gp = (unsigned)((n_plans + 255) / 256 < 4096 ? (n_plans + 255) / 256 : 4096);
+    const unsigned gc = (unsigned)((n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192);
+    k_group_init<<<gp, 256, 0, st>>>((int32_t)n_plans, 0.0f, key, cnt, fill);
+    k_zero_i64_one<<<1, 64, 0, st>>>(n_out);
+    k_group_key<<<gc, 256, 0, st>>>(d_pred, n, d_col_plan, (int32_t)n_plans, y_lo, y_hi, key, cnt);
+    SGF_LAUNCHED();
+    // plans, largest key first (keys are predictions shifted by y_lo)
+    sgf_status rc = sgf_order_by_prediction(key, n_plans, 0.0f, y_hi - y_lo, plan_order, ows, order_ws, stream);
+    if (rc) return rc;
+    k_group_rank<<<gp, 256, 0, st>>>(plan_order, (int32_t)n_plans, cnt, rank, start);
+    SGF_LAUNCHED();
+    rc = inclusive_scan_i64(start + 1, n_plans, scan, st);
+    if (rc) return rc;
+    k_group_scatter<<<gc, 256, 0, st>>>(n, d_col_plan, (int32_t)n_plans, rank, start, fill, d_order, n_out);
     SGF_LAUNCHED();
     return SGF_OK;
 }

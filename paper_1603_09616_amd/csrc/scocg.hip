@@ -467,6 +467,307 @@ __global__ __launch_bounds__(SEED_T) void k_seed_r1(SolveArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Seed pass, S = I, four columns per wavefront.  Lane l serves column slot
+// cs = l / 16 of a group of four consecutive work-queue entries and local atom
+// a = l % 16 of that column's subspace (at most 16 atoms, 64 orbitals): its
+// four orbital rows of s, p and w stay in registers, and the subspace's
+// blocks of H sit in LDS, shared by the columns of the group that have the
+// same plan (the four orbitals of one atom).  The recurrence scalars of a
+// column are formed by its 16 lanes only: per iteration a wavefront pays
+// the complex divisions and the branch logic of the COCG recurrence once for
+// four columns, and its sums are 16-lane row reductions (DPP row shifts, the
+// row total handed to the row's lanes through LDS, so all of them hold the
+// same bits).  Each lane steps the collinearity factors of ns/16 shifts of
+// its own column.  The columns of a group whose plans differ run one after
+// another, each with its own plan's blocks in LDS.
+// ---------------------------------------------------------------------------
+constexpr int Q4_HS = 18;   // doubles per staged block: 16 values and 2 of padding (bank spread)
+constexpr int Q4_VP = 17;   // double2 per (column slot, orbital) row of p: 16 atoms and 1 of padding
+
+// Sum over the 16 lanes of each row, delivered to every lane of the row
+// (fixed order, so the lanes of a row agree bit for bit).  rb: 4 rows x NV
+// doubles of LDS scratch.
+template <int NV>
+__device__ __forceinline__ void row_sums16(double (&v)[NV], double *rb) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double t = v[i];
+        t += dpp_shr<0x111>(t);  // row_shr:1
+        t += dpp_shr<0x112>(t);  // row_shr:2
+        t += dpp_shr<0x114>(t);  // row_shr:4
+        t += dpp_shr<0x118>(t);  // row_shr:8
+        v[i] = t;
+    }
+    if ((lane & 15) == 15) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) rb[(lane >> 4) * 8 + i] = v[i];
+    }
+    wave_lds_fence();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = rb[(lane >> 4) * 8 + i];
+    wave_lds_fence();  // rb may be written again by the next call
+}
+
+template <int M4, int BMAX>
+__global__ __launch_bounds__(SEED_T) void k_seed_q4(SolveArgs a) {
+    __shared__ __align__(16) double hs[(16 * BMAX + 1) * Q4_HS];   // the plan's blocks, then one zero block
+    __shared__ int hcol[16 * BMAX + 1];                            // local column atom of each staged block
+    __shared__ __align__(16) double2 vp[16 * Q4_VP];               // p: [slot][orbital] rows of 16 atoms
+    __shared__ __align__(16) double rb[4 * 8];                     // row sums
+    __shared__ __align__(16) double2 sg[16 * M4];                  // sigma_k = z_k - z_s
+    const int lane = threadIdx.x;
+    const int cs = lane >> 4, al = lane & 15;
+    const double2 zs = a.z[a.seed];
+    for (int k = lane; k < 16 * M4; k += 64) sg[k] = k < a.ns ? csub(a.z[k], zs) : make_double2(0.0, 0.0);
+    const double tol2 = a.tol * a.tol;
+    const double2 zero = make_double2(0.0, 0.0), one = make_double2(1.0, 0.0);
+    const int64_t nbatch = a.batch_end - a.batch_begin;
+
+    for (;;) {
+        int64_t ticket = 0;
+        if (lane == 0) ticket = (int64_t)atomicAdd(reinterpret_cast<unsigned long long *>(a.ticket), 1ull);
+        ticket = __shfl(ticket, 0, 64);
+        if (4 * ticket >= nbatch) break;
+        // this lane's column: queue entry 4 ticket + cs of the batch
+        const int64_t slot = 4 * ticket + cs;
+        const bool have = slot < nbatch;
+        int64_t c = -1, j = -1;
+        int32_t pl = -1;
+        int64_t a0 = 0, b0 = 0, p0 = 0;
+        int n_loc = 0, nblk = 0, npa = 0, cl = 0;
+        bool bad = !have;
+        if (have) {
+            c = a.order ? (int64_t)a.order[a.batch_begin + slot] : a.batch_begin + slot;
+            bad = c < 0 || c >= a.n_cols;
+        }
+        if (!bad) {
+            j = a.cols[c];
+            pl = a.col_plan[c];
+            bad = pl < 0 || pl >= a.n_plans || j < 0;
+        }
+        if (!bad) {
+            a0 = a.atom_off[pl];
+            n_loc = (int)(a.atom_off[pl + 1] - a0);
+            b0 = a.blk_off[pl];
+            nblk = (int)(a.blk_off[pl + 1] - b0);
+            p0 = a.pa_off[pl];
+            npa = (int)(a.pa_off[pl + 1] - p0);
+            cl = a.center_loc[pl];
+            bad = n_loc < 1 || n_loc > 16 || nblk > 16 * BMAX || npa < 1 || 4 * npa > a.rmax || cl < 0 ||
+                  cl >= n_loc || a.loc_atom[a0 + cl] != (int32_t)(j >> 2);
+        }
+        if (!bad) {  // rows of more than BMAX blocks: this kernel cannot take the column
+            int nb = 0;
+            if (al < n_loc) nb = (al + 1 < n_loc ? a.lrow[a0 + al + 1] : nblk) - a.lrow[a0 + al];
+            const uint64_t over = __ballot(nb > BMAX);
+            bad = ((over >> (16 * cs)) & 0xffffull) != 0;
+        }
+        if (have && bad && al == 0) {
+            a.meta[slot] = ColMeta{-1, 0, 0, SGF_BADCOLUMN};
+            if (c >= 0 && c < a.n_cols) {
+                a.iters[c] = 0;
+                a.status[c] = SGF_BADCOLUMN;
+            }
+        }
+        // column slots still to run (bit cs), one plan at a time
+        uint32_t todo = 0;
+        {
+            const uint64_t ok = __ballot(!bad && al == 0);
+#pragma unroll
+            for (int g = 0; g < 4; ++g) todo |= ((ok >> (16 * g)) & 1ull) ? (1u << g) : 0u;
+        }
+        while (todo) {
+            const int lead = __builtin_ctz(todo);
+            const int32_t plead = __shfl(pl, 16 * lead, 64);
+            const uint64_t same = __ballot(al == 0 && ((todo >> cs) & 1u) && pl == plead);
+            uint32_t pass = 0;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) pass |= ((same >> (16 * g)) & 1ull) ? (1u << g) : 0u;
+            todo &= ~pass;
+            const bool mine = (pass >> cs) & 1u;   // this lane's column runs in this pass
+            // the plan's sizes, from the lead column's lanes (all equal within the pass)
+            const int64_t pa0 = __shfl(a0, 16 * lead, 64), pb0 = __shfl(b0, 16 * lead, 64);
+            const int64_t pp0 = __shfl(p0, 16 * lead, 64);
+            const int pn_loc = __shfl(n_loc, 16 * lead, 64), pnblk = __shfl(nblk, 16 * lead, 64);
+            const int pnpa = __shfl(npa, 16 * lead, 64), pcl = __shfl(cl, 16 * lead, 64);
+            // stage the plan's blocks of H (and a zero block at index pnblk)
+            wave_lds_fence();
+            for (int i = lane; i < (pnblk + 1) * 8; i += 64) {
+                const int t = i >> 3, h2 = i & 7;
+                double2 v = zero;
+                int cb = 0;  // the zero block multiplies atom 0's p
+                if (t < pnblk) {
+                    const int32_t g = a.lblk[2 * (pb0 + t) + 1];
+                    v = reinterpret_cast<const double2 *>(a.h + 16 * (int64_t)g)[h2];
+                    cb = a.lblk[2 * (pb0 + t)];
+                }
+                reinterpret_cast<double2 *>(hs + t * Q4_HS)[h2] = v;
+                if (h2 == 0) hcol[t] = cb;
+            }
+            // this lane's row: its first staged block and block count (absent
+            // blocks, and the rows of lanes without an atom, take the zero block)
+            const bool row = mine && al < pn_loc;
+            int t0 = 0, nb = 0;
+            if (row) {
+                t0 = a.lrow[pa0 + al];
+                nb = (al + 1 < pn_loc ? a.lrow[pa0 + al + 1] : pnblk) - t0;
+            }
+            int pq = -1;  // projection index of this lane's atom
+            for (int q = 0; q < pnpa; ++q)
+                if (row && a.pa_loc[pp0 + q] == al) pq = q;
+            const int jo = (int)(j & 3);
+            double2 *hab = a.hab + (size_t)slot * a.cap * 2;
+            double2 *hr = a.hr + (size_t)slot * (a.cap + 1) * a.rmax;
+            // start: x = 0, s_0 = p_0 = e_j
+            double2 sv[4], pv[4];
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+                sv[o] = (row && al == pcl && o == jo) ? one : zero;
+                pv[o] = sv[o];
+                vp[(4 * cs + o) * Q4_VP + al] = pv[o];
+                if (mine && pq >= 0) hr[4 * pq + o] = sv[o];
+            }
+            wave_lds_fence();
+
+            double2 pc[M4], po[M4];
+            uint32_t act = 0;
+#pragma unroll
+            for (int m = 0; m < M4; ++m) {
+                pc[m] = po[m] = one;
+                if (mine && al + 16 * m < a.ns) act |= 1u << m;
+            }
+            double2 rho = one, inv_rho = one, ba_old = zero;
+            int status = SGF_MAXITER, iters = 0, applied = 0;
+            bool running = mine;
+            double snorm2 = 1.0;
+            const int max_iter = a.max_iter > 0 ? a.max_iter : 40 * pn_loc;  // 10 per local orbital
+
+            for (int it = 0; it < max_iter; ++it) {
+                // w = z_s p - H p on this lane's four rows
+                double ax[4] = {0.0, 0.0, 0.0, 0.0}, ay[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+                for (int b = 0; b < BMAX; ++b) {
+                    const int t = b < nb ? t0 + b : pnblk;
+                    const double2 *hb = reinterpret_cast<const double2 *>(hs + t * Q4_HS);
+                    const int bcol = hcol[t];
+                    double2 pb[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) pb[q] = vp[(4 * cs + q) * Q4_VP + bcol];
+#pragma unroll
+                    for (int o = 0; o < 4; ++o) {
+                        const double2 h01 = hb[2 * o], h23 = hb[2 * o + 1];
+                        ax[o] = fma(h01.x, pb[0].x, ax[o]);
+                        ay[o] = fma(h01.x, pb[0].y, ay[o]);
+                        ax[o] = fma(h01.y, pb[1].x, ax[o]);
+                        ay[o] = fma(h01.y, pb[1].y, ay[o]);
+                        ax[o] = fma(h23.x, pb[2].x, ax[o]);
+                        ay[o] = fma(h23.x, pb[2].y, ay[o]);
+                        ax[o] = fma(h23.y, pb[3].x, ax[o]);
+                        ay[o] = fma(h23.y, pb[3].y, ay[o]);
+                    }
+                }
+                double2 wv[4];
+                double sm[2] = {0.0, 0.0};
+#pragma unroll
+                for (int o = 0; o < 4; ++o) {
+                    wv[o] = make_double2(zs.x * pv[o].x - zs.y * pv[o].y - ax[o],
+                                         zs.x * pv[o].y + zs.y * pv[o].x - ay[o]);
+                    sm[0] = fma(pv[o].x, wv[o].x, fma(-pv[o].y, wv[o].y, sm[0]));
+                    sm[1] = fma(pv[o].x, wv[o].y, fma(pv[o].y, wv[o].x, sm[1]));
+                }
+                row_sums16<2>(sm, rb);
+                const double2 mu = make_double2(sm[0], sm[1]);
+                if (running) {
+                    iters = it + 1;
+                    if (!cfinite(mu)) { status = SGF_NONFINITE; running = false; }
+                    else if (mu.x == 0.0 && mu.y == 0.0) { status = SGF_BREAKDOWN; running = false; }
+                }
+                const double2 alpha = cmul(rho, crcp(mu));
+                const double2 ia = cmul(mu, inv_rho);  // 1/alpha
+                double sr[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                for (int o = 0; o < 4; ++o) {
+                    sv[o] = csub(sv[o], cmul(alpha, wv[o]));
+                    sr[0] = fma(sv[o].x, sv[o].x, fma(-sv[o].y, sv[o].y, sr[0]));
+                    sr[1] = fma(2.0 * sv[o].x, sv[o].y, sr[1]);
+                    sr[2] = fma(sv[o].x, sv[o].x, fma(sv[o].y, sv[o].y, sr[2]));
+                }
+                row_sums16<3>(sr, rb);
+                const double2 rho_new = make_double2(sr[0], sr[1]);
+                const double2 beta = cmul(rho_new, inv_rho);
+                const double2 ba = cmul(beta, ia);  // beta_n / alpha_n
+#pragma unroll
+                for (int o = 0; o < 4; ++o) {
+                    pv[o] = cfma(beta, pv[o], sv[o]);
+                    vp[(4 * cs + o) * Q4_VP + al] = pv[o];
+                }
+                if (running) {
+                    snorm2 = sr[2];
+                    // history: 1/alpha_n, beta_n/alpha_n, r_{n+1} on P
+                    if (al == 0) {
+                        hab[2 * it] = ia;
+                        hab[2 * it + 1] = ba;
+                    }
+                    if (pq >= 0) {
+#pragma unroll
+                        for (int o = 0; o < 4; ++o) hr[(size_t)(it + 1) * a.rmax + 4 * pq + o] = sv[o];
+                    }
+                    // collinearity factors and the freeze test ||s|| <= tol |pi^k|
+                    const double2 coup = cmul(alpha, ba_old);
+                    const double2 c1 = cadd(one, coup), ncoup = make_double2(-coup.x, -coup.y);
+#pragma unroll
+                    for (int m = 0; m < M4; ++m) {
+                        const double2 pn = cfma(cfma(alpha, sg[al + 16 * m], c1), pc[m], cmul(ncoup, po[m]));
+                        const double pn2 = fma(pn.x, pn.x, pn.y * pn.y);
+                        po[m] = pc[m];
+                        pc[m] = pn;
+                        if (((act >> m) & 1u) && snorm2 <= tol2 * pn2) {
+                            act &= ~(1u << m);
+                            const int k = al + 16 * m;
+                            const double res = sqrt(snorm2 / pn2);
+                            a.nk[(size_t)slot * a.ns_pad + k] = it + 1;
+                            if (a.resid) a.resid[c * a.ns + k] = res;
+                            if (a.shift_iters) a.shift_iters[c * a.ns + k] = it + 1;
+                        }
+                    }
+                    applied = it + 1;
+                    ba_old = ba;
+                    rho = rho_new;
+                    // the column stops when none of its 16 lanes holds an active shift
+                    const uint64_t alive = __ballot(act != 0);
+                    const bool any_alive = ((alive >> (16 * cs)) & 0xffffull) != 0;
+                    if (!any_alive || snorm2 == 0.0) { status = SGF_CONVERGED; running = false; }
+                    else if (rho_new.x == 0.0 && rho_new.y == 0.0) { status = SGF_BREAKDOWN; running = false; }
+                    else if (!isfinite(rho_new.x + rho_new.y + snorm2)) { status = SGF_NONFINITE; running = false; }
+                    else inv_rho = crcp(rho_new);
+                }
+                wave_lds_fence();  // p is in LDS for the next block product
+                if (!__any(running)) break;
+            }
+            if (mine) {
+#pragma unroll
+                for (int m = 0; m < M4; ++m) {
+                    const int k = al + 16 * m;
+                    if (k >= a.ns || !((act >> m) & 1u)) continue;
+                    const double pn2 = fma(pc[m].x, pc[m].x, pc[m].y * pc[m].y);
+                    const double res = applied > 0 ? sqrt(snorm2 / pn2) : 1.0;
+                    a.nk[(size_t)slot * a.ns_pad + k] = applied;
+                    if (a.resid) a.resid[c * a.ns + k] = res;
+                    if (a.shift_iters) a.shift_iters[c * a.ns + k] = applied;
+                }
+                if (al == 0) {
+                    a.meta[slot] = ColMeta{(int32_t)c, iters, pnpa, status};
+                    a.iters[c] = iters;
+                    a.status[c] = status;
+                }
+            }
+        }
+        wave_lds_fence();  // hs and vp are reused by the next group
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Seed pass for S != I.  COCG on A = S^{-1}(z_s S - H) with the S-bilinear
 // form [u, v] = u^T S v (A is symmetric in it since H and S are real
 // symmetric): s is the true-space residual, r = S^{-1} s, q = S p and
@@ -1877,6 +2178,13 @@ static KernelFn pick_seed_r1(int M, int bmax) {
     return bmax <= 5 ? pick_seed_r1_m<5>(M) : bmax <= 6 ? pick_seed_r1_m<6>(M) : pick_seed_r1_m<8>(M);
 }
 
+// four columns per wavefront; M4 = shifts per lane (ns_pad / 16: 4 or 8)
+template <int BMAX>
+static KernelFn pick_seed_q4_m(int M4) { return M4 <= 4 ? k_seed_q4<4, BMAX> : k_seed_q4<8, BMAX>; }
+static KernelFn pick_seed_q4(int M4, int bmax) {
+    return bmax <= 5 ? pick_seed_q4_m<5>(M4) : bmax <= 6 ? pick_seed_q4_m<6>(M4) : pick_seed_q4_m<8>(M4);
+}
+
 template <int BMAX, bool PACKED>
 static KernelFn pick_seed_gen_m(int M) {
     switch (M) {
@@ -2139,7 +2447,10 @@ static sgf_status shifted_solve_in(const sgf_system *sys, const sgf_plan *plan, 
     const int M = hs.ns_pad / 64;
     // register variant when every subspace has <= 64 orbitals and <= 8 blocks per row
     const bool gen = sys->s != nullptr;
-    const bool r1 = !gen && opts->stage_lds < 0 && totals->max_loc_atoms <= 16 && totals->max_row_blocks <= 8;
+    const bool r1 = !gen && (opts->stage_lds < 0 || opts->stage_lds == 3) && totals->max_loc_atoms <= 16 &&
+                    totals->max_row_blocks <= 8;
+    // four columns per wavefront when there are at most 128 shifts (8 per lane)
+    const bool q4 = r1 && !mixed && opts->stage_lds < 0 && hs.ns_pad <= 128;
     // S != I with the overlap inverse in register tiles when every subspace has
     // <= 22 atoms and <= 8 blocks per row and there are <= 256 shifts (the
     // dense-LDS variant otherwise, or when stage_lds asks for it); subspaces
@@ -2173,6 +2484,7 @@ static sgf_status shifted_solve_in(const sgf_system *sys, const sgf_plan *plan, 
                        : gen2 ? pick_seed_gen2((hs.ns_pad + GEN2_T - 1) / GEN2_T, totals->max_row_blocks)
                        : gen2_one ? pick_seed_gen2s((hs.ns_pad + GEN2_T - 1) / GEN2_T, totals->max_row_blocks)
                        : gen ? pick_seed_gen(M, totals->max_row_blocks, gen_packed)
+                             : q4 ? pick_seed_q4(hs.ns_pad / 16, totals->max_row_blocks)
                              : (r1 ? pick_seed_r1(M, totals->max_row_blocks) : pick_seed(stage, M));
     const int seed_threads = (gen2 || gen2_one) ? GEN2_T : SEED_T;
     KernelFn seed_fn2 = ovl2 ? pick_seed_ovl(2, (hs.ns_pad + 127) / 128, totals->max_row_blocks) : nullptr;
@@ -2274,7 +2586,8 @@ static sgf_status shifted_solve_in(const sgf_system *sys, const sgf_plan *plan, 
         const int64_t b1 = b0 + slots < n_tickets ? b0 + slots : n_tickets;
         a.batch_begin = b0;
         a.batch_end = b1;
-        const int64_t grid = seed_grid_max < b1 - b0 ? seed_grid_max : b1 - b0;
+        const int64_t n_tk = q4 ? (b1 - b0 + 3) / 4 : b1 - b0;  // work-queue tickets of this batch
+        const int64_t grid = seed_grid_max < n_tk ? seed_grid_max : n_tk;
         k_zero_ticket<<<1, 64, 0, st>>>(L.ticket);
         SGF_LAUNCHED();
         hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;

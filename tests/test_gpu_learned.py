@@ -148,3 +148,35 @@ def test_order_many_chunks_crowded_buckets(sgf):
     assert np.array_equal(np.sort(o), np.arange(n))
     po = np.clip(pred[o], 0.0, 3.0)
     assert np.all(np.diff(po) <= 3.0 / 4096 + 1e-6)
+
+
+def test_grouped_order_keeps_plans_together(sgf):
+    """sgf_order_groups_by_prediction: a permutation in which the columns of
+    each plan are contiguous and the plans come by their largest prediction
+    (bucket resolution), with columns of an out-of-range plan last; a solve
+    in that order gives the natural order's bits."""
+    import torch
+    wl = W.bundle_workload(3, 3, 40, n_shifts=64, config_no=170)
+    s = sgf.system_for(wl)
+    prep = sgf.prepare(s, wl.columns, radius=wl.radius)
+    pred = torch.as_tensor(np.random.default_rng(5).uniform(3.0, 6.0, wl.columns.size).astype(np.float32),
+                           device="cuda")
+    n_plans = prep.plan.n_plans
+    order = sgf.order_groups_by_prediction(pred, prep.col_plan, n_plans, 0.0, float(np.log(4096.0))).cpu().numpy()
+    assert sorted(order.tolist()) == list(range(wl.columns.size))
+    cp = prep.col_plan.cpu().numpy()[order]
+    runs = np.concatenate([[0], np.nonzero(np.diff(cp))[0] + 1])
+    assert len(runs) == n_plans                       # one run per plan
+    pk = np.full(n_plans, -1.0)
+    np.maximum.at(pk, prep.col_plan.cpu().numpy(), pred.cpu().numpy())
+    b = np.floor((np.log(4096.0) - pk[cp[runs]]) / np.log(4096.0) * 4096)
+    assert np.all(np.diff(b) >= -1)                   # largest first (to a bucket: FP32 keys)
+    # an out-of-range plan index goes last
+    bad = prep.col_plan.clone()
+    bad[7] = n_plans + 3
+    o2 = sgf.order_groups_by_prediction(pred, bad, n_plans, 0.0, float(np.log(4096.0))).cpu().numpy()
+    assert o2[-1] == 7 and sorted(o2.tolist()) == list(range(wl.columns.size))
+    a = sgf.solve_prepared(prep, wl.z, wl.w, tol=wl.tol).numpy()
+    g = sgf.solve_prepared(prep, wl.z, wl.w, tol=wl.tol, order=torch.as_tensor(order, device="cuda")).numpy()
+    np.testing.assert_array_equal(a.G, g.G)
+    np.testing.assert_array_equal(a.rho, g.rho)
