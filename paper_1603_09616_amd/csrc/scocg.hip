@@ -2451,18 +2451,6 @@ static sgf_status shifted_solve_in(const sgf_system *sys, const sgf_plan *plan, 
                     totals->max_row_blocks <= 8;
     // four columns per wavefront when there are at most 128 shifts (8 per lane)
     const bool q4 = r1 && !mixed && opts->stage_lds < 0 && hs.ns_pad <= 128;
-    // S != I with the overlap inverse in register tiles when every subspace has
-    // <= 22 atoms and <= 8 blocks per row and there are <= 256 shifts (the
-    // dense-LDS variant otherwise, or when stage_lds asks for it); subspaces
-    // of 17 to 22 atoms go to a second, two-wavefront launch
-    // Switched off: on a small S != I bundle (subspaces of 8 to 15 atoms, one
-    // wavefront per column) the register-tile seed pass never finished on the
-    // GPU, and no cause has been found in its source or its generated code.
-    // Until one is, every S != I solve takes the LDS seed passes below.
-    constexpr bool kRegisterTileOverlapSeed = false;
-    const bool ovl = kRegisterTileOverlapSeed && gen && !mixed && opts->stage_lds < 0 &&
-                     totals->max_loc_atoms <= 22 && totals->max_row_blocks <= 8 && hs.ns_pad <= 256;
-    const bool ovl2 = ovl && totals->max_loc_atoms > 16;
     // S != I, dense-LDS variant.  stage_lds < 0: subspaces of up to 16 atoms
     // in a launch of their own with the dense inverse, the larger ones in a
     // second launch with the packed triangle (half the LDS, so twice the
@@ -2471,24 +2459,22 @@ static sgf_status shifted_solve_in(const sgf_system *sys, const sgf_plan *plan, 
     // stage_lds = 2: the same split, with one wavefront per column in the
     // second launch too.  Otherwise the second launch (17 to 32 atoms, rows of
     // at most 8 blocks) runs two wavefronts per column (k_seed_gen2).
-    const bool gen_split = gen && !ovl && !mixed && (opts->stage_lds < 0 || opts->stage_lds == 2) &&
+    const bool gen_split = gen && !mixed && (opts->stage_lds < 0 || opts->stage_lds == 2) &&
                            totals->max_loc_atoms > 16;
     const bool gen2 = gen_split && opts->stage_lds < 0 && totals->max_loc_atoms <= 32 && totals->max_row_blocks <= 8;
     // every subspace of at most 16 atoms: one launch of the two-wavefront
     // dense kernel of the small class
-    const bool gen2_one = gen && !ovl && !mixed && opts->stage_lds < 0 && !gen_split &&
+    const bool gen2_one = gen && !mixed && opts->stage_lds < 0 && !gen_split &&
                           totals->max_loc_atoms <= 16 && totals->max_row_blocks <= 8;
     const bool gen_packed = gen_split || (gen && opts->stage_lds == 1);
     KernelFn seed_fn = mixed ? pick_seed_mx(M, totals->max_row_blocks)
-                       : ovl ? pick_seed_ovl(1, M, totals->max_row_blocks)
                        : gen2 ? pick_seed_gen2((hs.ns_pad + GEN2_T - 1) / GEN2_T, totals->max_row_blocks)
                        : gen2_one ? pick_seed_gen2s((hs.ns_pad + GEN2_T - 1) / GEN2_T, totals->max_row_blocks)
                        : gen ? pick_seed_gen(M, totals->max_row_blocks, gen_packed)
                              : q4 ? pick_seed_q4(hs.ns_pad / 16, totals->max_row_blocks)
                              : (r1 ? pick_seed_r1(M, totals->max_row_blocks) : pick_seed(stage, M));
     const int seed_threads = (gen2 || gen2_one) ? GEN2_T : SEED_T;
-    KernelFn seed_fn2 = ovl2 ? pick_seed_ovl(2, (hs.ns_pad + 127) / 128, totals->max_row_blocks) : nullptr;
-    size_t seed_lds = (r1 || mixed || ovl) ? 0 : lds;
+    size_t seed_lds = (r1 || mixed) ? 0 : lds;
     // S != I: p, s, w, q, r and the dense inverse of the local overlap, laid
     // out for subspaces of up to nlx orbitals
     auto gen_layout = [](SolveArgs &g, int nlx, bool packed) {
@@ -2511,7 +2497,7 @@ static sgf_status shifted_solve_in(const sgf_system *sys, const sgf_plan *plan, 
                                        : pick_seed_gen(M, totals->max_row_blocks, false);
     const int small_threads = gen2 ? GEN2_T : SEED_T;
     size_t lds_small = 0;
-    if (gen && !ovl) {
+    if (gen) {
         seed_lds = gen_layout(a, nl, gen_packed);
         if (seed_lds > 160 * 1024) {
             set_error("sgf_shifted_solve: S != I with a local subspace of %d orbitals needs %zu bytes of LDS "
@@ -2550,17 +2536,6 @@ static sgf_status shifted_solve_in(const sgf_system *sys, const sgf_plan *plan, 
     SGF_HIP(hipGetDevice(&dev));
     SGF_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
     const int64_t seed_grid_max = opts->grid > 0 ? opts->grid : (int64_t)per_cu * n_cu;
-    int64_t seed_grid_max2 = 0;
-    if (ovl2) {
-        int per_cu2 = 0;
-        SGF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, reinterpret_cast<const void *>(seed_fn2),
-                                                             2 * SEED_T, 0));
-        if (per_cu2 < 1) {
-            set_error("sgf_shifted_solve: two-wavefront seed kernel does not fit a compute unit");
-            return SGF_EUNSUPPORTED;
-        }
-        seed_grid_max2 = opts->grid > 0 ? opts->grid : (int64_t)per_cu2 * n_cu;
-    }
     int64_t seed_grid_small = 0;
     if (gen_split) {
         a_small = a;
@@ -2610,14 +2585,6 @@ static sgf_status shifted_solve_in(const sgf_system *sys, const sgf_plan *plan, 
         }
         hipLaunchKernelGGL(seed_fn, dim3((unsigned)grid), dim3(seed_threads), seed_lds, st, a);
         SGF_LAUNCHED();
-        if (ovl2) {
-            // the same tickets again for the columns of 17 to 22 atoms
-            const int64_t grid2 = seed_grid_max2 < b1 - b0 ? seed_grid_max2 : b1 - b0;
-            k_zero_ticket<<<1, 64, 0, st>>>(L.ticket);
-            SGF_LAUNCHED();
-            hipLaunchKernelGGL(seed_fn2, dim3((unsigned)grid2), dim3(2 * SEED_T), 0, st, a);
-            SGF_LAUNCHED();
-        }
         if (timed) SGF_HIP(hipEventRecord(e1, st));
         hipLaunchKernelGGL(shift_fn, dim3((unsigned)(b1 - b0)), dim3(shift_threads), shift_lds, st, a);
         SGF_LAUNCHED();

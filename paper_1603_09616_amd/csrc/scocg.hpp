@@ -88,9 +88,6 @@ using KernelFn = void (*)(SolveArgs);
 
 // Mixed-precision passes (mixed.hip).
 KernelFn pick_seed_mx(int M, int bmax);
-// S != I seed pass with the local overlap inverse in register tiles: W = 1
-// (one wavefront, <= 16 local atoms) or 2 (two wavefronts, 17 to 22 atoms).
-KernelFn pick_seed_ovl(int W, int M, int bmax);
 KernelFn shift_mx_kernel();
 
 }  // namespace sgf

@@ -398,7 +398,8 @@ def test_overlap_two_wavefront_shift_counts(sgf, O, n_shifts):
 
 
 @pytest.mark.skip(reason="the register-tile S != I seed pass did not finish on the GPU (small overlap bundle, "
-                         "one wavefront per column); cause not found, so the path is switched off in the library")
+                         "one wavefront per column); its cause was not found, and the kernel was removed from the "
+                         "library: every S != I solve takes the LDS seed passes")
 def test_overlap_register_tiles_match_dense_inverse(sgf):
     """S != I seed pass with the overlap inverse in register tiles (one
     wavefront up to 16 local atoms, two for 17 to 22) against the variant
