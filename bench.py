@@ -83,10 +83,16 @@ def path_bytes(nrow, iters, ns, g_out):
     return 2.0 * hist + out
 
 
-def seed_kernel_name(ns, max_row_blocks):
+def seed_kernel_name(ns, max_row_blocks, stage_lds=-1):
+    """The S = I seed kernel the library launches for subspaces of <= 16
+    atoms: four columns per wavefront (k_seed_q4) up to 128 shifts with the
+    default choice, one column per wavefront (k_seed_r1) otherwise."""
+    b = 5 if max_row_blocks <= 5 else 6 if max_row_blocks <= 6 else 8
+    ns_pad = (ns + 63) // 64 * 64
+    if stage_lds == -1 and ns_pad <= 128:
+        return f"k_seed_q4<{ns_pad // 16}, {b}>"
     m = (ns + 63) // 64
     m = {1: 1, 2: 2, 3: 4, 4: 4}.get(m, 8)
-    b = 5 if max_row_blocks <= 5 else 6 if max_row_blocks <= 6 else 8
     return f"k_seed_r1<{m}, {b}>"
 
 
@@ -94,7 +100,7 @@ def shift_kernel_name(max_proj_atoms):
     return f"k_shift<{min(max(max_proj_atoms, 1), 8)}, 1>"
 
 
-def solve_figures(prep, res, ns, seed_ms, shift_ms, g_out):
+def solve_figures(prep, res, ns, seed_ms, shift_ms, g_out, stage_lds=-1):
     """Roofline figures of one S = I solve from its plan and per-column
     counts: the seed pass against the FP64 vector peak (seed-operator flops
     only), the whole path (both passes, both flop terms), the kernels'
@@ -114,7 +120,8 @@ def solve_figures(prep, res, ns, seed_ms, shift_ms, g_out):
     whole_tf = (a4 + a8) / ((seed_ms + shift_ms) * 1e-3) / 1e12
     r1 = t.max_loc_atoms <= 16 and t.max_row_blocks <= 8
     return {
-        "seed_kernel": seed_kernel_name(ns, t.max_row_blocks) if r1 else "k_seed (LDS-staged or global operator)",
+        "seed_kernel": (seed_kernel_name(ns, t.max_row_blocks, stage_lds) if r1 and stage_lds in (-1, 3)
+                        else "k_seed (LDS-staged or global operator)"),
         "shift_kernel": shift_kernel_name(t.max_proj_atoms),
         "column_iterations": float(iters.sum()), "active_shift_steps": float(nk.sum()),
         "mean_local_blocks": float(nblk.mean()), "mean_local_orbitals": float(nl.mean()),
@@ -203,12 +210,17 @@ def kernel_fingerprint(kind):
     else:
         src = open(os.path.join(CSRC, "scocg.hip")).read()
         head = {"seed": r"template <int M, int BMAX>\n__global__ __launch_bounds__\(SEED_T\) void k_seed_r1",
+                "seed_q4": r"template <int M4, int BMAX>\n__global__ __launch_bounds__\(SEED_T\) void k_seed_q4",
                 "shift": r"template <int NPA, int MS>\n__global__ __launch_bounds__\(512\)[^\n]* void k_shift"}[kind]
         m = re.search(head, src)
         if m is None:
             return None
+        start = m.start()
+        if kind == "seed_q4":   # with the row-sum helper and constants in front of it
+            h = src.find("constexpr int Q4_HS")
+            start = h if 0 <= h < start else start
         end = src.find("\n}\n", m.start())
-        text = src[m.start():end + 3]
+        text = src[start:end + 3]
     return hashlib.sha256((text + common).encode()).hexdigest()
 
 
@@ -773,8 +785,9 @@ def main(argv=None):
     resid = res.resid.cpu().numpy()
     converged = int(np.sum(resid <= wl.tol))
     value = converged / (ms_step * 1e-3)
-    fig = solve_figures(prep, res, ns, seed_ms, shift_ms, not args.no_g)
-    traffic_seed = recorded_traffic(fig["seed_kernel"], "seed")
+    fig = solve_figures(prep, res, ns, seed_ms, shift_ms, not args.no_g, launch.get("stage_lds", -1))
+    traffic_seed = recorded_traffic(fig["seed_kernel"], "seed_q4" if fig["seed_kernel"].startswith("k_seed_q4")
+                                    else "seed")
     traffic_shift = recorded_traffic(fig["shift_kernel"], "shift")
     hbm_counted = None
     if traffic_seed is not None and traffic_shift is not None:
