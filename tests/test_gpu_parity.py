@@ -245,6 +245,34 @@ def test_nonfinite_column_only(sgf, O):
     assert list(got.status) == [sgf.NONFINITE, sgf.NONFINITE, sgf.CONVERGED, sgf.CONVERGED]
 
 
+@pytest.mark.parametrize("explicit_s", [False, True])
+@pytest.mark.parametrize("stage", [-1, 0, 1, 3])
+def test_breakdown_status(sgf, O, stage, explicit_s):
+    """The crafted input of workloads.breakdown_block makes mu vanish exactly
+    in the second iteration (worked by hand beside the oracle's pin of the
+    same case).  Every seed kernel ends the column with SGF_BREAKDOWN after
+    two iterations, and the one completed step gives x^k = e_0 / z_k on every
+    shift, as on the oracle."""
+    import torch
+    if explicit_s and stage == 3:
+        pytest.skip("stage_lds 3 is an S = I launch shape")
+    row_ptr, col, h, z = W.breakdown_block()
+    s = np.eye(4)[None].copy() if explicit_s else None
+    xyz = np.zeros((1, 3))
+    d = lambda a: None if a is None else torch.as_tensor(a, device="cuda")
+    system = sgf.system_from_bsr(d(row_ptr), d(col), d(h), s=d(s), xyz=d(xyz))
+    got = sgf.shifted_solve(system, np.array([0]), z, tol=1e-12, radius=1.0, seed_index=1, stage_lds=stage).numpy()
+    ref = O.shifted_solve(O.BSR(row_ptr, col, h, s), xyz, np.array([0]), z, None, tol=1e-12, radius=1.0,
+                          prune=True, seed_index=1)
+    assert got.status[0] == sgf.BREAKDOWN == ref.status[0]
+    assert got.iters[0] == 2 == ref.iters[0]
+    np.testing.assert_array_equal(got.proj_row, ref.proj_row)
+    G = got.G.reshape(4, z.size)
+    np.testing.assert_allclose(G[0], 1.0 / z, rtol=1e-15, atol=0)
+    assert np.all(G[1:] == 0)
+    np.testing.assert_allclose(got.G, ref.G, rtol=1e-15, atol=0)
+
+
 def test_invalid_arguments(sgf):
     wl = W.bundle_workload(1, 1, 10, n_shifts=8, config_no=78)
     s = sgf.system_for(wl)

@@ -375,6 +375,36 @@ def test_status_codes(oracle_lib):
     assert list(r.status) == [O.NONFINITE, O.NONFINITE, O.CONVERGED, O.CONVERGED]
 
 
+# The breakdown case (workloads.breakdown_block), worked by hand in exact
+# arithmetic; every value is a small Gaussian integer, so FP64 reproduces it
+# bit for bit.  Column j = 0, seed z_s = i: p_0 = e_0, w_0 = (i, -1, 0, 0),
+# mu_0 = i, alpha_0 = -i, s_1 = (0, -i, 0, 0), rho_1 = -1, beta_0 = -1,
+# p_1 = (-1, -i, 0, 0), w_1 = z_s p_1 - H p_1 = (-2i, 2, 0, 0) and
+# mu_1 = p_1^T w_1 = 2i - 2i = 0 with s_1 != 0: a breakdown in the second
+# iteration.  (For a symmetric H and Im z > 0 the pivots of z - T of the
+# underlying Lanczos tridiagonal T keep Im >= Im z, so mu never vanishes; the
+# crafted block breaks that symmetry on purpose.)  After the one completed
+# step every shift holds the one-dimensional Galerkin solution
+# x^k = e_0 / (z_k - H_00) = e_0 / z_k.
+
+
+@pytest.mark.parametrize("explicit_s", [False, True])
+def test_breakdown_status(oracle_lib, explicit_s):
+    """SGF_BREAKDOWN on the hand-worked case above, through the S = I path
+    and through the generalized path with S given as the identity block."""
+    O = oracle_lib
+    row_ptr, col, h, z = W.breakdown_block()
+    s = np.eye(4)[None].copy() if explicit_s else None
+    b = O.BSR(row_ptr, col, h, s)
+    xyz = np.zeros((1, 3))
+    r = O.shifted_solve(b, xyz, np.array([0]), z, None, tol=1e-12, radius=1.0, prune=True, seed_index=1)
+    assert r.status[0] == O.BREAKDOWN and r.iters[0] == 2
+    np.testing.assert_array_equal(r.proj_row, np.arange(4))
+    G = r.G.reshape(4, z.size)
+    np.testing.assert_allclose(G[0], 1.0 / z, rtol=1e-15, atol=0)
+    assert np.all(G[1:] == 0)
+
+
 @pytest.mark.parametrize("overlap", [False, True])
 def test_apply_inverts_the_dense_solve(oracle_lib, overlap):
     """The global operator apply, pinned by an independent LAPACK solve: for

@@ -278,6 +278,16 @@ MLP_NF, MLP_NH = 5, 64
 MLP_NPARAM = 2 * MLP_NF + MLP_NH * MLP_NF + MLP_NH + MLP_NH * MLP_NH + MLP_NH + MLP_NH + 1
 
 
+def breakdown_block():
+    """A crafted one-atom input for the BREAKDOWN status: one 4x4 block with
+    H_01 = -1 and H_10 = 1 (deliberately not symmetric), all other entries
+    0, S = I, and the shifts -1 + i, i, 1 + i with the seed at index 1.
+    Returns (row_ptr, col, h [1, 4, 4], z)."""
+    h = np.zeros((1, 4, 4))
+    h[0, 0, 1], h[0, 1, 0] = -1.0, 1.0
+    return np.array([0, 1], np.int32), np.array([0], np.int32), h, np.array([-1 + 1j, 1j, 1 + 1j])
+
+
 def mlp_init(seed: int = 0) -> np.ndarray:
     """He-normal weights and zero biases in the flat layout
     [mean(5), inv_std(5), W1(64x5), b1, W2(64x64), b2, W3(64), b3];
