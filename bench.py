@@ -392,13 +392,20 @@ def extra_workloads(sgf, W, dev, ws_gib, check_n, reps=5, only=None):
             nl = 4 * np.diff(prep.plan.atom_off.cpu().numpy())[cp].astype(np.float64)
             nblk = np.diff(prep.plan.blk_off.cpu().numpy())[cp].astype(np.float64)
             it = res.iters.cpu().numpy().astype(np.float64)
-            # H p and S p (64 each per block) and the dense S_L^{-1} s (4 per entry) per column-iteration
-            f = float(np.sum(it * (128.0 * nblk + 4.0 * nl * nl)))
+            # w = z_s q - H p: 64 per local block (q = S p comes from its own
+            # recurrence); r = S_L^{-1} s: a real n_L x n_L matrix times a
+            # complex vector, 4 n_L^2, or with blocks s_ab I4 the per-atom
+            # inverse (S_a^{-1} (x) I4), 4 n_L (n_L / 4) = n_L^2
+            per_atom = bool(prep.system.s_orbital_diagonal)
+            f = float(np.sum(it * (64.0 * nblk + (1.0 if per_atom else 4.0) * nl * nl)))
             out[name]["roofline"] = {"seed_pass": {"ms": seed_ms, "tflop": f / 1e12,
                                                    "tflops": f / (seed_ms * 1e-3) / 1e12,
                                                    "frac": f / (seed_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
-                                                   "flop_model": "128 per local block (H p, S p) + 4 n_L^2 "
-                                                                 "(dense S_L^-1 s) per column-iteration"}}
+                                                   "flop_model": "64 per local block (H p) + "
+                                                                 + ("n_L^2 (per-atom S^-1 s)" if per_atom else
+                                                                    "4 n_L^2 (orbital S_L^-1 s)")
+                                                                 + " per column-iteration",
+                                                   "kernel": "k_seed_kr" if per_atom else "k_seed_gen2s / k_seed_gen2"}}
         log(f"[bench] {name}: {wl.columns.size} columns x {ns} shifts in {ms:.1f} ms (median of {n_reps}; "
             f"{conv / (ms * 1e-3):.3g} solves/s, {prof[2]} launches)")
         if wl.tb and wl.tb.overlap:

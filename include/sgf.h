@@ -88,7 +88,15 @@ typedef struct {
 /* Device view of a built system (all pointers device, caller-owned).
  * s / s32 are NULL when S = I.  h32 / s32 are FP32 shadows used by the
  * mixed-precision path (NULL when it is not used).  xyz (nm, [n_atoms][3])
- * may be NULL when every plan uses the whole system (radius <= 0). */
+ * may be NULL when every plan uses the whole system (radius <= 0).
+ * s_orbital_diagonal = 1 states that every block of s is a multiple of the
+ * 4 x 4 identity, S_ab = s_ab I4 (the overlap model of sgf_tb_params
+ * overlap = 1, which sgf_build_hamiltonian writes exactly so): the local
+ * overlap is then S_a (x) I4 with S_a one number per atom pair, and the FP64
+ * S != I seed pass inverts the n x n S_a of a subspace of n atoms instead
+ * of the 4n x 4n S_L.  The seed pass checks every block it reads; a column
+ * whose blocks are not of that form ends SGF_BADCOLUMN.  0: any symmetric
+ * positive definite S. */
 typedef struct {
     int64_t n_atoms;
     int64_t nnzb;
@@ -99,12 +107,14 @@ typedef struct {
     const float *h32;
     const float *s32;
     const double *xyz;
+    int32_t s_orbital_diagonal;
 } sgf_system;
 
 /* A caller-built block-sparse matrix (for example from another tight-binding
  * code), all pointers device and caller-owned: the BSR layout above with
  * n_atoms block rows, nnzb blocks, FP64 values h (and s, NULL for S = I)
- * and optional FP32 shadows h32 / s32. */
+ * and optional FP32 shadows h32 / s32.  s_orbital_diagonal as in
+ * sgf_system (copied into the descriptor). */
 typedef struct {
     int64_t n_atoms;
     int64_t nnzb;
@@ -114,6 +124,7 @@ typedef struct {
     const double *s;
     const float *h32;
     const float *s32;
+    int32_t s_orbital_diagonal;
 } sgf_bsr;
 
 /* The system of the shifted equations (z S - H) x = b of the Introduction,
@@ -265,13 +276,16 @@ typedef struct {
                               one column per wavefront with its rows in registers above; else an
                               LDS-staged operator when it fits); 3 one column per wavefront with rows in
                               registers; 1 LDS-staged operator; 0 operator read from global.
-                              S != I: -1 auto (subspaces of <= 16 atoms in a launch with the dense
-                              overlap inverse, larger ones in a second launch with its packed
-                              triangle; both with two wavefronts per column when every subspace
-                              has <= 32 atoms and rows of <= 8 blocks); 0 one launch, dense; 1 one
-                              launch, packed;
-                              2 the split of -1 with one wavefront per column throughout (S = I
-                              treats 2 as 0) */
+                              S != I: -1 auto: with s_orbital_diagonal, subspaces of <= 32 atoms,
+                              rows of <= 8 blocks and <= 256 shifts, the per-atom overlap inverse
+                              (one wavefront per column, one launch for <= 16 atoms and one for
+                              17-32); otherwise subspaces of <= 16 atoms in a launch with the dense
+                              orbital overlap inverse, larger ones in a second launch with its
+                              packed triangle, both with two wavefronts per column when every
+                              subspace has <= 32 atoms and rows of <= 8 blocks; 0 one launch,
+                              dense; 1 one launch, packed; 2 the split of -1 with one wavefront
+                              per column throughout (S = I treats 2 as 0).  0, 1 and 2 never take
+                              the per-atom inverse */
     int32_t grid;          /* seed-pass persistent workgroups; 0: fill the device */
     int32_t profile;       /* 1: record HIP events around each pass (read with sgf_solve_profile) */
     int64_t batch_cols;    /* columns per launch (0: all); the solve also stops at what the workspace holds */

@@ -55,7 +55,7 @@ class TBParamsC(ctypes.Structure):
 
 class SystemC(ctypes.Structure):
     _fields_ = [("n_atoms", i64), ("nnzb", i64), ("row_ptr", P), ("col", P), ("h", P), ("s", P), ("h32", P),
-                ("s32", P), ("xyz", P)]
+                ("s32", P), ("xyz", P), ("s_orbital_diagonal", i32)]
 
 
 class PlanC(ctypes.Structure):
@@ -77,7 +77,7 @@ class SolveOptsC(ctypes.Structure):
 
 class BsrC(ctypes.Structure):
     _fields_ = [("n_atoms", i64), ("nnzb", i64), ("row_ptr", P), ("col", P), ("h", P), ("s", P), ("h32", P),
-                ("s32", P)]
+                ("s32", P), ("s_orbital_diagonal", i32)]
 
 
 _lib = None
@@ -196,10 +196,12 @@ class System:
     s32: "object" = None
     xyz: "object" = None
     build_ws: "object" = None
+    s_orbital_diagonal: bool = False  # every block of s is a multiple of I4
 
     def c(self) -> SystemC:
         return SystemC(self.n_atoms, self.nnzb, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.h), _ptr(self.s),
-                       _ptr(self.h32), _ptr(self.s32), _ptr(self.xyz))
+                       _ptr(self.h32), _ptr(self.s32), _ptr(self.xyz),
+                       int(bool(self.s_orbital_diagonal) and self.s is not None))
 
     def add_f32(self, stream=None) -> "System":
         """FP32 shadows of H (and S) for the mixed-precision path."""
@@ -238,7 +240,8 @@ def build_hamiltonian(xyz, params, onsite=None, device="cuda", stream=None) -> S
     tb = _tb_c(params)
     _call("sgf_build_hamiltonian", n, _ptr(d_xyz), _ptr(d_on), ctypes.byref(tb), _ptr(d_ws), ws.value,
           _ptr(row_ptr), nb, _ptr(col), _ptr(h), _ptr(s), st)
-    return System(n, nb, row_ptr, col, h, s, xyz=d_xyz, build_ws=d_ws)
+    # the builder's overlap blocks are s(r) I4 exactly
+    return System(n, nb, row_ptr, col, h, s, xyz=d_xyz, build_ws=d_ws, s_orbital_diagonal=bool(params.overlap))
 
 
 def build_chain(eps, t: float, device="cuda", stream=None) -> System:
@@ -272,21 +275,26 @@ def hamiltonian_size(xyz, params, device="cuda", stream=None) -> int:
     return nnzb.value
 
 
-def system_from_bsr(row_ptr, col, h, s=None, xyz=None, h32=None, s32=None, hash_cell=0.3, stream=None) -> System:
+def system_from_bsr(row_ptr, col, h, s=None, xyz=None, h32=None, s32=None, hash_cell=0.3, s_orbital_diagonal=False,
+                    stream=None) -> System:
     """A System around a caller's block-sparse matrix (device tensors:
     row_ptr int32 [n+1], col int32 [nnzb], h (and s) float64 [nnzb, 4, 4];
     xyz float64 [n, 3] in nm for radius-limited subspaces).  The C call
     checks the sizes; the tensors are borrowed, not copied.  With xyz, the
     spatial hash that finds the atoms of a local subspace is built by the
     library's neighbour search (sgf_hamiltonian_size with cells of
-    hash_cell nm)."""
+    hash_cell nm).  s_orbital_diagonal: the caller states that every block
+    of s is a multiple of I4 (the solve then inverts the overlap per atom
+    pair; a column whose blocks are not of that form ends BADCOLUMN)."""
     n, nb = int(row_ptr.numel()) - 1, int(col.numel())
-    m = BsrC(n, nb, _ptr(row_ptr), _ptr(col), _ptr(h), _ptr(s), _ptr(h32), _ptr(s32))
+    m = BsrC(n, nb, _ptr(row_ptr), _ptr(col), _ptr(h), _ptr(s), _ptr(h32), _ptr(s32),
+             int(bool(s_orbital_diagonal) and s is not None))
     out = ctypes.c_void_p()
     _call("sgf_system_from_bsr", ctypes.byref(m), _ptr(xyz), ctypes.byref(out))
     try:
         c = SystemC.from_address(out.value)
         assert c.n_atoms == n and c.nnzb == nb and c.row_ptr == _ptr(row_ptr) and c.h == _ptr(h)
+        assert c.s_orbital_diagonal == m.s_orbital_diagonal
     finally:
         lib().sgf_system_destroy(out)
     build_ws = None
@@ -298,7 +306,7 @@ def system_from_bsr(row_ptr, col, h, s=None, xyz=None, h32=None, s32=None, hash_
         tb = TBParamsC(0, 0, 0, 0, 0, 0, 1.0, 0.0, float(hash_cell), 0, 0.0, 1.0)
         _call("sgf_hamiltonian_size", n, _ptr(xyz), ctypes.byref(tb), _ptr(build_ws), ws.value, ctypes.byref(cnt),
               _stream(stream))
-    return System(n, nb, row_ptr, col, h, s, h32, s32, xyz, build_ws)
+    return System(n, nb, row_ptr, col, h, s, h32, s32, xyz, build_ws, bool(s_orbital_diagonal) and s is not None)
 
 
 def system_for(wl, device="cuda") -> System:

@@ -275,12 +275,15 @@ extern "C" sgf_status sgf_system_from_bsr(const sgf_bsr *m, const double *d_xyz,
                 (long long)m->nnzb);
     SGF_REQUIRE(m->row_ptr && m->col && m->h, "sgf_system_from_bsr: row_ptr, col and h are required");
     SGF_REQUIRE(!m->s32 || m->s, "sgf_system_from_bsr: an FP32 overlap shadow without the overlap");
+    SGF_REQUIRE(m->s_orbital_diagonal == 0 || m->s_orbital_diagonal == 1,
+                "sgf_system_from_bsr: s_orbital_diagonal must be 0 or 1");
     sgf_system *sys = static_cast<sgf_system *>(std::malloc(sizeof(sgf_system)));
     if (!sys) {
         set_error("sgf_system_from_bsr: out of host memory");
         return SGF_ENOMEM;
     }
-    *sys = sgf_system{m->n_atoms, m->nnzb, m->row_ptr, m->col, m->h, m->s, m->h32, m->s32, d_xyz};
+    *sys = sgf_system{m->n_atoms, m->nnzb, m->row_ptr, m->col, m->h, m->s, m->h32, m->s32, d_xyz,
+                      m->s ? m->s_orbital_diagonal : 0};
     *out = sys;
     return SGF_OK;
 }

@@ -2459,22 +2459,28 @@ static sgf_status shifted_solve_in(const sgf_system *sys, const sgf_plan *plan, 
     // stage_lds = 2: the same split, with one wavefront per column in the
     // second launch too.  Otherwise the second launch (17 to 32 atoms, rows of
     // at most 8 blocks) runs two wavefronts per column (k_seed_gen2).
-    const bool gen_split = gen && !mixed && (opts->stage_lds < 0 || opts->stage_lds == 2) &&
+    // S != I with every block of S a multiple of I4: the per-atom overlap
+    // inverse, one wavefront per column (a second launch for 17 to 32 atoms)
+    const bool kron = gen && sys->s_orbital_diagonal == 1 && !mixed && opts->stage_lds < 0 && hs.ns_pad <= 256 &&
+                      totals->max_loc_atoms <= 32 && totals->max_row_blocks <= 8;
+    const bool kron_split = kron && totals->max_loc_atoms > 16;
+    const bool gen_split = gen && !kron && !mixed && (opts->stage_lds < 0 || opts->stage_lds == 2) &&
                            totals->max_loc_atoms > 16;
     const bool gen2 = gen_split && opts->stage_lds < 0 && totals->max_loc_atoms <= 32 && totals->max_row_blocks <= 8;
     // every subspace of at most 16 atoms: one launch of the two-wavefront
     // dense kernel of the small class
-    const bool gen2_one = gen && !mixed && opts->stage_lds < 0 && !gen_split &&
+    const bool gen2_one = gen && !kron && !mixed && opts->stage_lds < 0 && !gen_split &&
                           totals->max_loc_atoms <= 16 && totals->max_row_blocks <= 8;
     const bool gen_packed = gen_split || (gen && opts->stage_lds == 1);
     KernelFn seed_fn = mixed ? pick_seed_mx(M, totals->max_row_blocks)
+                       : kron ? pick_seed_kron(kron_split ? 2 : 1, M, totals->max_row_blocks)
                        : gen2 ? pick_seed_gen2((hs.ns_pad + GEN2_T - 1) / GEN2_T, totals->max_row_blocks)
                        : gen2_one ? pick_seed_gen2s((hs.ns_pad + GEN2_T - 1) / GEN2_T, totals->max_row_blocks)
                        : gen ? pick_seed_gen(M, totals->max_row_blocks, gen_packed)
                              : q4 ? pick_seed_q4(hs.ns_pad / 16, totals->max_row_blocks)
                              : (r1 ? pick_seed_r1(M, totals->max_row_blocks) : pick_seed(stage, M));
     const int seed_threads = (gen2 || gen2_one) ? GEN2_T : SEED_T;
-    size_t seed_lds = (r1 || mixed) ? 0 : lds;
+    size_t seed_lds = (r1 || mixed || kron) ? 0 : lds;
     // S != I: p, s, w, q, r and the dense inverse of the local overlap, laid
     // out for subspaces of up to nlx orbitals
     auto gen_layout = [](SolveArgs &g, int nlx, bool packed) {
@@ -2492,12 +2498,13 @@ static sgf_status shifted_solve_in(const sgf_system *sys, const sgf_plan *plan, 
     SolveArgs a_small{};
     // with gen2, the small class also runs two wavefronts per column (each
     // row's product split between them by column halves)
-    KernelFn seed_fn_small = !gen_split ? nullptr
+    KernelFn seed_fn_small = kron_split ? pick_seed_kron(1, M, totals->max_row_blocks)
+                             : !gen_split ? nullptr
                              : gen2    ? pick_seed_gen2s((hs.ns_pad + GEN2_T - 1) / GEN2_T, totals->max_row_blocks)
                                        : pick_seed_gen(M, totals->max_row_blocks, false);
     const int small_threads = gen2 ? GEN2_T : SEED_T;
     size_t lds_small = 0;
-    if (gen) {
+    if (gen && !kron) {
         seed_lds = gen_layout(a, nl, gen_packed);
         if (seed_lds > 160 * 1024) {
             set_error("sgf_shifted_solve: S != I with a local subspace of %d orbitals needs %zu bytes of LDS "
@@ -2513,6 +2520,10 @@ static sgf_status shifted_solve_in(const sgf_system *sys, const sgf_plan *plan, 
     if (gen2_one) {
         a.loc_lo = 0;
         a.loc_hi = 16;
+    }
+    if (kron) {  // loc_hi: the largest subspace that this solve's launches take
+        a.loc_lo = 0;
+        a.loc_hi = kron_split ? 32 : 16;
     }
     const int ms = mixed ? 1 : shift_ms(totals->max_proj_atoms, opts->shifts_per_lane);
     KernelFn shift_fn = mixed ? shift_mx_kernel() : pick_shift(totals->max_proj_atoms, ms);
@@ -2537,11 +2548,11 @@ static sgf_status shifted_solve_in(const sgf_system *sys, const sgf_plan *plan, 
     SGF_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
     const int64_t seed_grid_max = opts->grid > 0 ? opts->grid : (int64_t)per_cu * n_cu;
     int64_t seed_grid_small = 0;
-    if (gen_split) {
+    if (gen_split || kron_split) {
         a_small = a;
-        lds_small = gen_layout(a_small, 64, false);
+        lds_small = kron_split ? 0 : gen_layout(a_small, 64, false);
         a_small.loc_lo = 0;
-        a_small.loc_hi = 16;
+        a_small.loc_hi = kron_split ? 32 : 16;
         int per_cu_s = 0;
         SGF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(seed_fn_small),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_small));
@@ -2572,7 +2583,7 @@ static sgf_status shifted_solve_in(const sgf_system *sys, const sgf_plan *plan, 
             SGF_HIP(prof.add(e2));
             SGF_HIP(hipEventRecord(e0, st));
         }
-        if (gen_split) {
+        if (gen_split || kron_split) {
             // subspaces of up to 16 atoms first, then the same tickets again
             // for the larger ones
             a_small.batch_begin = b0;

@@ -90,4 +90,8 @@ using KernelFn = void (*)(SolveArgs);
 KernelFn pick_seed_mx(int M, int bmax);
 KernelFn shift_mx_kernel();
 
+// S != I seed pass with the per-atom overlap inverse (seed_kron.hip):
+// rows_per_lane 1 for subspaces of <= 16 atoms, 2 for 17 to 32.
+KernelFn pick_seed_kron(int rows_per_lane, int M, int bmax);
+
 }  // namespace sgf

@@ -53,11 +53,11 @@ def test_struct_layouts_match_header():
     """ctypes mirrors of the C structs have the sizes the header implies."""
     import paper_1603_09616_amd as sgf
     assert ctypes.sizeof(sgf.TBParamsC) == 12 * 8
-    assert ctypes.sizeof(sgf.SystemC) == 9 * 8
+    assert ctypes.sizeof(sgf.SystemC) == 10 * 8
     assert ctypes.sizeof(sgf.PlanC) == 12 * 8
     assert ctypes.sizeof(sgf.PlanTotalsC) == 3 * 8 + 4 * 4
     assert ctypes.sizeof(sgf.SolveOptsC) == 96
-    assert ctypes.sizeof(sgf.BsrC) == 8 * 8
+    assert ctypes.sizeof(sgf.BsrC) == 9 * 8
 
 
 def test_product_path_has_no_oracle_dependency():
@@ -81,9 +81,17 @@ def test_system_from_bsr_host_checks(libsgf):
     c = sgf.SystemC.from_address(out.value)
     assert (c.n_atoms, c.nnzb, c.row_ptr, c.col, c.h, c.s, c.h32, c.s32, c.xyz) == \
         (10, 28, fake[0], fake[1], fake[2], None, fake[3], None, fake[4])
+    assert c.s_orbital_diagonal == 0
     libsgf.sgf_system_destroy(out)
+    # the per-atom overlap flag is kept with an overlap and dropped without one
+    for s_ptr, flag in ((fake[5], 1), (None, 0)):
+        m = sgf.BsrC(10, 28, fake[0], fake[1], fake[2], s_ptr, None, None, 1)
+        assert libsgf.sgf_system_from_bsr(ctypes.byref(m), None, ctypes.byref(out)) == 0
+        assert sgf.SystemC.from_address(out.value).s_orbital_diagonal == flag
+        libsgf.sgf_system_destroy(out)
     libsgf.sgf_system_destroy(None)
     for bad in (sgf.BsrC(0, 1, fake[0], fake[1], fake[2], None, None, None),    # no rows
+                sgf.BsrC(10, 28, fake[0], fake[1], fake[2], fake[5], None, None, 2),  # flag neither 0 nor 1
                 sgf.BsrC(10, 9, fake[0], fake[1], fake[2], None, None, None),   # fewer blocks than diagonal blocks
                 sgf.BsrC(10, 28, fake[0], None, fake[2], None, None, None),     # no column indices
                 sgf.BsrC(10, 28, fake[0], fake[1], fake[2], None, None, fake[5])):  # FP32 S without S

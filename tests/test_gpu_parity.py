@@ -352,7 +352,7 @@ def test_overlap_workload_sampled(sgf, O):
 
 
 def test_overlap_size_classes_bitwise(sgf):
-    """S != I: the default seed pass runs subspaces of <= 16 atoms in a launch
+    """S != I, general S: the default seed pass runs subspaces of <= 16 atoms in a launch
     with the dense overlap inverse, and the larger ones in a second launch with
     its packed triangle, both with two wavefronts per column.  stage_lds 2
     makes the same split with one wavefront per column; each of its classes
@@ -363,6 +363,7 @@ def test_overlap_size_classes_bitwise(sgf):
     solves are bitwise equal."""
     wl = W.config_bundle_overlap(n_columns=4096)
     s = sgf.system_for(wl)
+    s.s_orbital_diagonal = False  # treated as a general S: the orbital-level inverse
     prep = sgf.prepare(s, wl.columns, radius_per_col=wl.radius_per_col)
     n_loc = np.diff(prep.plan.atom_off.cpu().numpy())[prep.col_plan.cpu().numpy()]
     assert n_loc.min() <= 16 < n_loc.max()
@@ -401,6 +402,7 @@ def test_overlap_two_wavefront_shift_counts(sgf, O, n_shifts):
     (stage_lds 2) within the parity bar."""
     wl = W.config_bundle_overlap(n_columns=1536, n_shifts=n_shifts, config_no=31)
     s = sgf.system_for(wl)
+    s.s_orbital_diagonal = False  # treated as a general S: the orbital-level inverse
     prep = sgf.prepare(s, wl.columns, radius_per_col=wl.radius_per_col)
     n_loc = np.diff(prep.plan.atom_off.cpu().numpy())[prep.col_plan.cpu().numpy()]
     assert n_loc.min() <= 16 < n_loc.max()
@@ -423,6 +425,95 @@ def test_overlap_two_wavefront_shift_counts(sgf, O, n_shifts):
     sub.proj_row, sub.G, sub.rho = got.proj_row[rows], got.G[rows], got.rho[rows]
     sub.status, sub.iters = got.status[pick], got.iters[pick]
     compare(sub, ref)
+
+
+def _sub(res, pick):
+    """The outputs of columns `pick` of a solve, in the oracle's layout."""
+    class Sub:
+        pass
+    sub = Sub()
+    rows = np.concatenate([np.arange(res.proj_off[c], res.proj_off[c + 1]) for c in pick])
+    sub.proj_off = np.concatenate([[0], np.cumsum(res.proj_off[pick + 1] - res.proj_off[pick])])
+    sub.proj_row, sub.G, sub.rho = res.proj_row[rows], res.G[rows], res.rho[rows]
+    sub.status, sub.iters = res.status[pick], res.iters[pick]
+    return sub
+
+
+@pytest.mark.parametrize("n_shifts", [64, 256])
+def test_overlap_per_atom_inverse(sgf, O, n_shifts):
+    """The builder's overlap has blocks s(r) I4, so the default S != I seed
+    pass inverts S_a (one number per atom pair) instead of the orbital-level
+    S_L: one wavefront per column, a launch for <= 16 atoms (one row per lane)
+    and one for 17-32 (two rows per lane).  Against the orbital-level dense
+    inverse (stage_lds 0) within the parity bar on every column, against the
+    oracle on sampled columns of both classes, and bitwise on a repeat."""
+    wl = W.config_bundle_overlap(n_columns=2048, n_shifts=n_shifts, config_no=32)
+    s = sgf.system_for(wl)
+    assert s.s_orbital_diagonal
+    prep = sgf.prepare(s, wl.columns, radius_per_col=wl.radius_per_col)
+    n_loc = np.diff(prep.plan.atom_off.cpu().numpy())[prep.col_plan.cpu().numpy()]
+    assert n_loc.min() <= 16 < n_loc.max()
+    got = sgf.solve_prepared(prep, wl.z, wl.w, tol=wl.tol).numpy()
+    again = sgf.solve_prepared(prep, wl.z, wl.w, tol=wl.tol).numpy()
+    dense = sgf.solve_prepared(prep, wl.z, wl.w, tol=wl.tol, stage_lds=0).numpy()
+    assert np.all(got.status == sgf.CONVERGED) and np.all(dense.status == sgf.CONVERGED)
+    np.testing.assert_array_equal(got.G, again.G)
+    np.testing.assert_array_equal(got.rho, again.rho)
+    dense.proj_ptr = dense.proj_off
+    e_g, e_r = col_rel_err(got, dense), rho_rel_err(got, dense)
+    print(f"  {n_shifts} shifts: per-atom vs orbital inverse: G {e_g:.2e}, rho {e_r:.2e}; iterations "
+          f"{got.iters.mean():.1f} vs {dense.iters.mean():.1f}", flush=True)
+    assert e_g < FP64_RTOL and e_r < FP64_RTOL
+    assert abs(got.iters.mean() - dense.iters.mean()) <= 0.1 * dense.iters.mean() + 2
+    small, big = np.nonzero(n_loc <= 16)[0][:12], np.nonzero(n_loc > 16)[0][:12]
+    pick = np.sort(np.concatenate([small, big]))
+    ref = O.solve_workload(wl, cols=wl.columns[pick], threads=8)
+    compare(_sub(got, pick), ref)
+
+
+def test_overlap_per_atom_inverse_one_class(sgf, O):
+    """Every subspace at most 16 atoms (R = 0.8 nm): the per-atom seed pass
+    runs one launch, against the oracle."""
+    wl = W.bundle_workload(3, 2, 60, overlap=True, n_shifts=128, config_no=33)
+    s = sgf.system_for(wl)
+    cols = wl.columns[::3]
+    got = sgf.shifted_solve(s, cols, wl.z, wl.w, tol=wl.tol, radius=0.8).numpy()
+    ref = O.shifted_solve(O.system_for(wl), wl.xyz, cols, wl.z, wl.w, tol=wl.tol, radius=0.8, prune=True,
+                          threads=8)
+    assert np.diff(ref.proj_ptr).size == cols.size
+    compare(got, ref)
+
+
+def test_overlap_block_not_orbital_diagonal_is_refused(sgf):
+    """A system that states s_orbital_diagonal while one off-diagonal block of
+    S carries an orbital coupling: every column whose subspace holds that
+    block ends BADCOLUMN, the others are bitwise those of the unmodified
+    system; stated as a general S, every column converges."""
+    import torch
+    wl = W.bundle_workload(2, 1, 30, overlap=True, n_shifts=64, config_no=34)
+    base = sgf.system_for(wl)
+    s2 = base.s.clone()
+    rp = base.row_ptr.cpu().numpy()
+    cl = base.col.cpu().numpy()
+    t = next(t for t in range(rp[10], rp[11]) if cl[t] == 11)   # block (10, 11)
+    u = next(u for u in range(rp[11], rp[12]) if cl[u] == 10)   # and its transpose
+    s2[t, 0, 1] = s2[t, 1, 0] = 1e-3
+    s2[u, 0, 1] = s2[u, 1, 0] = 1e-3
+    cols = np.arange(4 * 30)
+    kw = dict(tol=1e-12, radius=0.6)
+    ref = sgf.shifted_solve(base, cols, wl.z, wl.w, **kw).numpy()
+    stated = sgf.system_from_bsr(base.row_ptr, base.col, base.h, s=s2, xyz=base.xyz, s_orbital_diagonal=True)
+    got = sgf.shifted_solve(stated, cols, wl.z, wl.w, **kw).numpy()
+    hit = got.status == sgf.BADCOLUMN
+    assert hit.any() and np.all(got.status[~hit] == sgf.CONVERGED)
+    for c in np.nonzero(~hit)[0]:
+        rows = slice(got.proj_off[c], got.proj_off[c + 1])
+        np.testing.assert_array_equal(got.G[rows], ref.G[rows])
+    general = sgf.system_from_bsr(base.row_ptr, base.col, base.h, s=s2, xyz=base.xyz)
+    res = sgf.shifted_solve(general, cols, wl.z, wl.w, **kw).numpy()
+    assert np.all(res.status == sgf.CONVERGED)
+    print(f"  {int(hit.sum())} of {cols.size} columns refused", flush=True)
+    del torch
 
 
 @pytest.mark.skip(reason="the register-tile S != I seed pass did not finish on the GPU (small overlap bundle, "
