@@ -278,14 +278,16 @@ typedef struct {
                               registers; 1 LDS-staged operator; 0 operator read from global.
                               S != I: -1 auto: with s_orbital_diagonal, subspaces of <= 32 atoms,
                               rows of <= 8 blocks and <= 256 shifts, the per-atom overlap inverse
-                              (one wavefront per column, one launch for <= 16 atoms and one for
-                              17-32); otherwise subspaces of <= 16 atoms in a launch with the dense
-                              orbital overlap inverse, larger ones in a second launch with its
-                              packed triangle, both with two wavefronts per column when every
-                              subspace has <= 32 atoms and rows of <= 8 blocks; 0 one launch,
+                              (a launch for <= 16 atoms with one wavefront per column, a row per
+                              lane, and one for 17-32 with two, a row per thread); otherwise subspaces of <= 16 atoms in a launch with
+                              the dense orbital overlap inverse, larger ones in a second launch
+                              with its packed triangle, both with two wavefronts per column when
+                              every subspace has <= 32 atoms and rows of <= 8 blocks; 0 one launch,
                               dense; 1 one launch, packed; 2 the split of -1 with one wavefront
-                              per column throughout (S = I treats 2 as 0).  0, 1 and 2 never take
-                              the per-atom inverse */
+                              per column throughout; 4 the per-atom inverse of -1 with one
+                              wavefront per column (two rows per lane) in the launch for 17-32
+                              atoms, else as 0 (S = I treats 2 and 4 as 0).  0, 1 and 2 never
+                              take the per-atom inverse */
     int32_t grid;          /* seed-pass persistent workgroups; 0: fill the device */
     int32_t profile;       /* 1: record HIP events around each pass (read with sgf_solve_profile) */
     int64_t batch_cols;    /* columns per launch (0: all); the solve also stops at what the workspace holds */

@@ -2,11 +2,14 @@
 
 The choices that do not change the method, only how it maps onto the chip:
 
-* ``stage_lds``: the seed-pass variant (-1: when every local subspace fits
-  a wavefront, four columns of a plan per wavefront with its blocks in LDS
-  up to 128 shifts and register rows above; 3: register rows, one column
-  per wavefront; 1: local operator staged in LDS; 0: operator read from
-  global memory);
+* ``stage_lds``: the seed-pass variant.  S = I: -1, when every local
+  subspace fits a wavefront, four columns of a plan per wavefront with its
+  blocks in LDS up to 128 shifts and register rows above; 3: register rows,
+  one column per wavefront; 1: local operator staged in LDS; 0: operator
+  read from global memory.  S != I, for the subspaces of more than 16
+  atoms: -1 the library's default (two wavefronts per column); 4 (overlap
+  blocks s_ab I4) one wavefront per column with two rows per lane; 2 (a
+  general overlap) one wavefront per column with the orbital-level inverse;
 * ``shifts_per_lane``: shifts handled by one lane of the shift pass (1, 2);
 * ``grid``: persistent seed-pass workgroups (0: as many as fit the device).
 
@@ -38,10 +41,16 @@ def signature(totals, n_shifts: int, precision: str, has_overlap: bool, device_n
             f"row_blocks={totals.max_row_blocks}|proj_atoms={totals.max_proj_atoms}|S={int(has_overlap)}")
 
 
-def candidates(totals, precision: str, has_overlap: bool) -> list:
+def candidates(totals, precision: str, has_overlap: bool, per_atom_overlap: bool = False) -> list:
     """The launch choices that apply to this workload shape."""
     register_ok = totals.max_loc_atoms <= 16 and totals.max_row_blocks <= 8 and not has_overlap
-    seeds = [-1] if precision == "mixed" or has_overlap else ([-1, 3, 1, 0] if register_ok else [-1, 0])
+    if precision == "mixed":
+        seeds = [-1]
+    elif has_overlap:
+        # the variants differ only where some subspace has more than 16 atoms
+        seeds = [-1] if totals.max_loc_atoms <= 16 else [-1, 4 if per_atom_overlap else 2]
+    else:
+        seeds = [-1, 3, 1, 0] if register_ok else [-1, 0]
     lanes = [1, 2] if (precision == "fp64" and totals.max_proj_atoms <= 5) else [1]
     grids = [0, 2048, 1024]
     out = []
@@ -97,7 +106,7 @@ def tune(prep, z, w=None, tol=1e-10, precision="fp64", sample=32768, reps=3, see
     order = torch.as_tensor(pick, device=prep.cols.device)
     out = None
     timings = {}
-    for cand in candidates(totals, precision, has_s):
+    for cand in candidates(totals, precision, has_s, bool(getattr(prep.system, "s_orbital_diagonal", False))):
         name = json.dumps(cand, sort_keys=True)
         ms = []
         for r in range(reps + 1):

@@ -343,13 +343,14 @@ __global__ __launch_bounds__(SEED_T) void k_seed_r1(SolveArgs a) {
         double2 pc[M], po[M];
         bool act[M];
         int nkm[M];
-        double res[M];
+        double res[M], fzs[M];  // a frozen shift's |pi^k|^2 and ||s||^2 at its freeze
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             pc[m] = po[m] = one;
             act[m] = lane + 64 * m < a.ns;
             nkm[m] = 0;
             res[m] = 1.0;
+            fzs[m] = 1.0;
         }
         double2 rho = one, inv_rho = one;
         double2 ba_old = zero;  // beta_{n-1} / alpha_{n-1}
@@ -416,9 +417,11 @@ __global__ __launch_bounds__(SEED_T) void k_seed_r1(SolveArgs a) {
             int alive = 0;
 #pragma unroll
             for (int m = 0; m < M; ++m) {
-                // Stepped for every shift, frozen or not: a frozen shift's
-                // pi^k is never read again (its step count and residual were
-                // recorded when it froze), so no selects are spent keeping it.
+                // Stepped for every shift of a slot that still has a running
+                // one, frozen or not: a frozen shift's pi^k is never read again
+                // (its step count and the squares of its residual estimate
+                // were kept when it froze), so no selects are spent keeping it.
+                if (!__any(act[m])) continue;
                 const double2 pn = cfma(cfma(alpha, sigma[m], c1), pc[m], cmul(ncoup, po[m]));
                 const double pn2 = fma(pn.x, pn.x, pn.y * pn.y);
                 const bool on = act[m];
@@ -427,7 +430,8 @@ __global__ __launch_bounds__(SEED_T) void k_seed_r1(SolveArgs a) {
                 pc[m] = pn;
                 if (done) {
                     nkm[m] = it + 1;
-                    res[m] = sqrt(snorm2 / pn2);
+                    res[m] = pn2;
+                    fzs[m] = snorm2;
                 }
                 act[m] = on && !done;
                 alive |= act[m] ? 1 : 0;
@@ -452,6 +456,8 @@ __global__ __launch_bounds__(SEED_T) void k_seed_r1(SolveArgs a) {
                 nkm[m] = applied;
                 const double pn2 = fma(pc[m].x, pc[m].x, pc[m].y * pc[m].y);
                 res[m] = applied > 0 ? sqrt(snorm2 / pn2) : 1.0;
+            } else {
+                res[m] = sqrt(fzs[m] / res[m]);  // ||s|| / |pi^k| at the freeze
             }
             a.nk[(size_t)slot * a.ns_pad + k] = nkm[m];
             if (a.resid) a.resid[c * a.ns + k] = res[m];
@@ -511,8 +517,8 @@ __device__ __forceinline__ void row_sums16(double (&v)[NV], double *rb) {
 
 template <int M4, int BMAX>
 __global__ __launch_bounds__(SEED_T) void k_seed_q4(SolveArgs a) {
-    __shared__ __align__(16) double hs[(16 * BMAX + 1) * Q4_HS];   // the plan's blocks, then one zero block
-    __shared__ int hcol[16 * BMAX + 1];                            // local column atom of each staged block
+    __shared__ __align__(16) double hs[16 * BMAX * Q4_HS];  // block b of local atom A's row in slot 16 b + A
+    __shared__ int hcol[16 * BMAX];                         // local column atom of each slot's block
     __shared__ __align__(16) double2 vp[16 * Q4_VP];               // p: [slot][orbital] rows of 16 atoms
     __shared__ __align__(16) double rb[4 * 8];                     // row sums
     __shared__ __align__(16) double2 sg[16 * M4];                  // sigma_k = z_k - z_s
@@ -591,28 +597,31 @@ __global__ __launch_bounds__(SEED_T) void k_seed_q4(SolveArgs a) {
             const int64_t pp0 = __shfl(p0, 16 * lead, 64);
             const int pn_loc = __shfl(n_loc, 16 * lead, 64), pnblk = __shfl(nblk, 16 * lead, 64);
             const int pnpa = __shfl(npa, 16 * lead, 64), pcl = __shfl(cl, 16 * lead, 64);
-            // stage the plan's blocks of H (and a zero block at index pnblk)
+            // stage the plan's blocks of H: block b of local atom A's row in
+            // slot 16 b + A, a zero block (times atom 0's p) where the row has
+            // b or fewer blocks or there is no atom A.  At step b the 16 lanes
+            // of a column read 16 consecutive slots, whose stride of 9 x 16 B
+            // starts them on 8 different 16-byte bank groups (the row-major
+            // order put the rows' first blocks about 4 slots apart, on 2)
             wave_lds_fence();
-            for (int i = lane; i < (pnblk + 1) * 8; i += 64) {
-                const int t = i >> 3, h2 = i & 7;
+            for (int i = lane; i < 16 * BMAX * 8; i += 64) {
+                const int sl = i >> 3, h2 = i & 7, A = sl & 15, b = sl >> 4;
                 double2 v = zero;
-                int cb = 0;  // the zero block multiplies atom 0's p
-                if (t < pnblk) {
-                    const int32_t g = a.lblk[2 * (pb0 + t) + 1];
-                    v = reinterpret_cast<const double2 *>(a.h + 16 * (int64_t)g)[h2];
-                    cb = a.lblk[2 * (pb0 + t)];
+                int cb = 0;
+                if (A < pn_loc) {
+                    const int u0 = a.lrow[pa0 + A];
+                    const int u1 = A + 1 < pn_loc ? a.lrow[pa0 + A + 1] : pnblk;
+                    if (b < u1 - u0) {
+                        const int32_t *lb = &a.lblk[2 * (pb0 + u0 + b)];
+                        v = reinterpret_cast<const double2 *>(a.h + 16 * (int64_t)lb[1])[h2];
+                        cb = lb[0];
+                    }
                 }
-                reinterpret_cast<double2 *>(hs + t * Q4_HS)[h2] = v;
-                if (h2 == 0) hcol[t] = cb;
+                reinterpret_cast<double2 *>(hs + sl * Q4_HS)[h2] = v;
+                if (h2 == 0) hcol[sl] = cb;
             }
-            // this lane's row: its first staged block and block count (absent
-            // blocks, and the rows of lanes without an atom, take the zero block)
+            // this lane's row
             const bool row = mine && al < pn_loc;
-            int t0 = 0, nb = 0;
-            if (row) {
-                t0 = a.lrow[pa0 + al];
-                nb = (al + 1 < pn_loc ? a.lrow[pa0 + al + 1] : pnblk) - t0;
-            }
             int pq = -1;  // projection index of this lane's atom
             for (int q = 0; q < pnpa; ++q)
                 if (row && a.pa_loc[pp0 + q] == al) pq = q;
@@ -643,17 +652,19 @@ __global__ __launch_bounds__(SEED_T) void k_seed_q4(SolveArgs a) {
             double snorm2 = 1.0;
             const int max_iter = a.max_iter > 0 ? a.max_iter : 40 * pn_loc;  // 10 per local orbital
 
+            const double *hsl = hs + al * Q4_HS;       // this lane's slots: hsl + 16 b Q4_HS
+            const double2 *vpc = vp + 4 * cs * Q4_VP;  // this lane's column of p
+
             for (int it = 0; it < max_iter; ++it) {
                 // w = z_s p - H p on this lane's four rows
                 double ax[4] = {0.0, 0.0, 0.0, 0.0}, ay[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 1
+#pragma unroll
                 for (int b = 0; b < BMAX; ++b) {
-                    const int t = b < nb ? t0 + b : pnblk;
-                    const double2 *hb = reinterpret_cast<const double2 *>(hs + t * Q4_HS);
-                    const int bcol = hcol[t];
+                    const double2 *hb = reinterpret_cast<const double2 *>(hsl + 16 * Q4_HS * b);
+                    const int bcol = hcol[16 * b + al];
                     double2 pb[4];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) pb[q] = vp[(4 * cs + q) * Q4_VP + bcol];
+                    for (int q = 0; q < 4; ++q) pb[q] = vpc[q * Q4_VP + bcol];
 #pragma unroll
                     for (int o = 0; o < 4; ++o) {
                         const double2 h01 = hb[2 * o], h23 = hb[2 * o + 1];
@@ -713,21 +724,29 @@ __global__ __launch_bounds__(SEED_T) void k_seed_q4(SolveArgs a) {
 #pragma unroll
                         for (int o = 0; o < 4; ++o) hr[(size_t)(it + 1) * a.rmax + 4 * pq + o] = sv[o];
                     }
-                    // collinearity factors and the freeze test ||s|| <= tol |pi^k|
+                    // collinearity factors and the freeze test ||s|| <= tol |pi^k|;
+                    // a slot whose shifts have all frozen, in every running
+                    // column of the wavefront, is not stepped (its factors
+                    // are never read again)
                     const double2 coup = cmul(alpha, ba_old);
                     const double2 c1 = cadd(one, coup), ncoup = make_double2(-coup.x, -coup.y);
 #pragma unroll
                     for (int m = 0; m < M4; ++m) {
+                        if (!__any((act >> m) & 1u)) continue;
                         const double2 pn = cfma(cfma(alpha, sg[al + 16 * m], c1), pc[m], cmul(ncoup, po[m]));
                         const double pn2 = fma(pn.x, pn.x, pn.y * pn.y);
                         po[m] = pc[m];
                         pc[m] = pn;
                         if (((act >> m) & 1u) && snorm2 <= tol2 * pn2) {
+                            // the estimate ||s|| / |pi^k| is formed after the
+                            // column from the two squares kept here
                             act &= ~(1u << m);
                             const int k = al + 16 * m;
-                            const double res = sqrt(snorm2 / pn2);
                             a.nk[(size_t)slot * a.ns_pad + k] = it + 1;
-                            if (a.resid) a.resid[c * a.ns + k] = res;
+                            if (a.resid) {
+                                a.resid[c * a.ns + k] = pn2;
+                                a.fz[(size_t)slot * a.ns_pad + k] = snorm2;
+                            }
                             if (a.shift_iters) a.shift_iters[c * a.ns + k] = it + 1;
                         }
                     }
@@ -749,7 +768,12 @@ __global__ __launch_bounds__(SEED_T) void k_seed_q4(SolveArgs a) {
 #pragma unroll
                 for (int m = 0; m < M4; ++m) {
                     const int k = al + 16 * m;
-                    if (k >= a.ns || !((act >> m) & 1u)) continue;
+                    if (k >= a.ns) continue;
+                    if (!((act >> m) & 1u)) {  // frozen: ||s|| / |pi^k| at its freeze
+                        if (a.resid)
+                            a.resid[c * a.ns + k] = sqrt(a.fz[(size_t)slot * a.ns_pad + k] / a.resid[c * a.ns + k]);
+                        continue;
+                    }
                     const double pn2 = fma(pc[m].x, pc[m].x, pc[m].y * pc[m].y);
                     const double res = applied > 0 ? sqrt(snorm2 / pn2) : 1.0;
                     a.nk[(size_t)slot * a.ns_pad + k] = applied;
@@ -2111,8 +2135,8 @@ HistoryShape history_shape(const sgf_plan_totals &tot, int ns, const sgf_solve_o
     const int nl_max = 4 * (tot.max_loc_atoms > 0 ? tot.max_loc_atoms : 1);
     h.cap = o.max_iter > 0 ? o.max_iter : (o.precision == 1 ? 40 : 10) * nl_max;
     h.rmax = o.precision == 1 ? 32 : 4 * (tot.max_proj_atoms > 0 ? tot.max_proj_atoms : 1);
-    h.per_col = align_up(sizeof(ColMeta), 16) + align_up((size_t)h.ns_pad * 4, 16) + (size_t)h.cap * 32 +
-                (size_t)(h.cap + 1) * h.rmax * 16;
+    h.per_col = align_up(sizeof(ColMeta), 16) + align_up((size_t)h.ns_pad * 4, 16) + (size_t)h.ns_pad * 8 +
+                (size_t)h.cap * 32 + (size_t)(h.cap + 1) * h.rmax * 16;
     h.fixed = 4096 + 2 * align_up((size_t)ns * 16);
     return h;
 }
@@ -2125,6 +2149,7 @@ SolveLayout solve_layout(const HistoryShape &hs, int ns, int64_t slots, void *ba
     L.w = c.take<double2>(ns);
     L.meta = c.take<ColMeta>(slots);
     L.nk = c.take<int32_t>((size_t)slots * hs.ns_pad);
+    L.fz = c.take<double>((size_t)slots * hs.ns_pad);
     L.hab = c.take<double2>((size_t)slots * hs.cap * 2);
     L.hr = c.take<double2>((size_t)slots * (hs.cap + 1) * hs.rmax);
     L.slots = slots;
@@ -2420,6 +2445,7 @@ static sgf_status shifted_solve_in(const sgf_system *sys, const sgf_plan *plan, 
     a.rmax = hs.rmax;
     a.meta = L.meta;
     a.nk = L.nk;
+    a.fz = L.fz;
     a.hab = L.hab;
     a.hr = L.hr;
     a.ticket = L.ticket;
@@ -2460,10 +2486,13 @@ static sgf_status shifted_solve_in(const sgf_system *sys, const sgf_plan *plan, 
     // second launch too.  Otherwise the second launch (17 to 32 atoms, rows of
     // at most 8 blocks) runs two wavefronts per column (k_seed_gen2).
     // S != I with every block of S a multiple of I4: the per-atom overlap
-    // inverse, one wavefront per column (a second launch for 17 to 32 atoms)
-    const bool kron = gen && sys->s_orbital_diagonal == 1 && !mixed && opts->stage_lds < 0 && hs.ns_pad <= 256 &&
+    // inverse, one wavefront per column (a second launch for 17 to 32 atoms,
+    // two rows per lane; stage_lds 4: two wavefronts per column there)
+    const bool kron = gen && sys->s_orbital_diagonal == 1 && !mixed &&
+                      (opts->stage_lds < 0 || opts->stage_lds == 4) && hs.ns_pad <= 256 &&
                       totals->max_loc_atoms <= 32 && totals->max_row_blocks <= 8;
     const bool kron_split = kron && totals->max_loc_atoms > 16;
+    const bool kron_two_waves = kron_split && opts->stage_lds < 0;
     const bool gen_split = gen && !kron && !mixed && (opts->stage_lds < 0 || opts->stage_lds == 2) &&
                            totals->max_loc_atoms > 16;
     const bool gen2 = gen_split && opts->stage_lds < 0 && totals->max_loc_atoms <= 32 && totals->max_row_blocks <= 8;
@@ -2473,13 +2502,14 @@ static sgf_status shifted_solve_in(const sgf_system *sys, const sgf_plan *plan, 
                           totals->max_loc_atoms <= 16 && totals->max_row_blocks <= 8;
     const bool gen_packed = gen_split || (gen && opts->stage_lds == 1);
     KernelFn seed_fn = mixed ? pick_seed_mx(M, totals->max_row_blocks)
-                       : kron ? pick_seed_kron(kron_split ? 2 : 1, M, totals->max_row_blocks)
+                       : kron ? (kron_two_waves ? pick_seed_kron2((hs.ns_pad + 127) / 128, totals->max_row_blocks)
+                                                : pick_seed_kron(kron_split ? 2 : 1, M, totals->max_row_blocks))
                        : gen2 ? pick_seed_gen2((hs.ns_pad + GEN2_T - 1) / GEN2_T, totals->max_row_blocks)
                        : gen2_one ? pick_seed_gen2s((hs.ns_pad + GEN2_T - 1) / GEN2_T, totals->max_row_blocks)
                        : gen ? pick_seed_gen(M, totals->max_row_blocks, gen_packed)
                              : q4 ? pick_seed_q4(hs.ns_pad / 16, totals->max_row_blocks)
                              : (r1 ? pick_seed_r1(M, totals->max_row_blocks) : pick_seed(stage, M));
-    const int seed_threads = (gen2 || gen2_one) ? GEN2_T : SEED_T;
+    const int seed_threads = (gen2 || gen2_one || kron_two_waves) ? GEN2_T : SEED_T;
     size_t seed_lds = (r1 || mixed || kron) ? 0 : lds;
     // S != I: p, s, w, q, r and the dense inverse of the local overlap, laid
     // out for subspaces of up to nlx orbitals

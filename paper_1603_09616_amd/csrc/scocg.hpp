@@ -57,6 +57,8 @@ struct SolveArgs {
     int rmax;           // projection rows per slot (4 * npa_max)
     ColMeta *meta;      // [slots]
     int32_t *nk;        // [slots][ns_pad] freeze iteration of every shift
+    double *fz;         // [slots][ns_pad] ||s||^2 when each shift froze (four-column seed pass:
+                        // the residual estimates are formed after the column)
     double2 *hab;       // [slots][cap][2]: 1/alpha_n, beta_n/alpha_n
     double2 *hr;        // [slots][cap+1][rmax]: projected residuals r_n on P
                         // (mixed: the same bytes hold r_n on all 64 rows as float2)
@@ -70,6 +72,7 @@ struct SolveLayout {
     double2 *z, *w;
     ColMeta *meta;
     int32_t *nk;
+    double *fz;
     double2 *hab, *hr;
     int64_t slots;
     size_t bytes;
@@ -93,5 +96,8 @@ KernelFn shift_mx_kernel();
 // S != I seed pass with the per-atom overlap inverse (seed_kron.hip):
 // rows_per_lane 1 for subspaces of <= 16 atoms, 2 for 17 to 32.
 KernelFn pick_seed_kron(int rows_per_lane, int M, int bmax);
+// the same for 17 to 32 atoms with two wavefronts per column (a row per
+// thread), M2 = ns_pad / 128 rounded up
+KernelFn pick_seed_kron2(int M2, int bmax);
 
 }  // namespace sgf

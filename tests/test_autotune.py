@@ -15,9 +15,13 @@ def test_candidates_follow_the_workload_shape():
     # large subspaces: no register variant; wide projections: one shift per lane
     c = AT.candidates(totals(atoms=60, proj=7), "fp64", False)
     assert {x["stage_lds"] for x in c} == {-1, 0} and {x["shifts_per_lane"] for x in c} == {1}
-    # mixed precision and S != I have a single seed variant
+    # mixed precision has a single seed variant, and so has S != I when no
+    # subspace is larger than 16 atoms; above, one and two wavefronts per
+    # column (per-atom inverse: 4, orbital-level inverse: 2)
     assert {x["stage_lds"] for x in AT.candidates(totals(), "mixed", False)} == {-1}
     assert {x["stage_lds"] for x in AT.candidates(totals(), "fp64", True)} == {-1}
+    assert {x["stage_lds"] for x in AT.candidates(totals(atoms=21), "fp64", True, True)} == {-1, 4}
+    assert {x["stage_lds"] for x in AT.candidates(totals(atoms=21), "fp64", True)} == {-1, 2}
 
 
 def test_signature_separates_shapes():

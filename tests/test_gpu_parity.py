@@ -443,10 +443,12 @@ def _sub(res, pick):
 def test_overlap_per_atom_inverse(sgf, O, n_shifts):
     """The builder's overlap has blocks s(r) I4, so the default S != I seed
     pass inverts S_a (one number per atom pair) instead of the orbital-level
-    S_L: one wavefront per column, a launch for <= 16 atoms (one row per lane)
-    and one for 17-32 (two rows per lane).  Against the orbital-level dense
-    inverse (stage_lds 0) within the parity bar on every column, against the
-    oracle on sampled columns of both classes, and bitwise on a repeat."""
+    S_L: a launch for <= 16 atoms (one wavefront per column, one row per
+    lane) and one for 17-32 (two wavefronts per column, a row per thread; or
+    one wavefront with two rows per lane, stage_lds 4).  Against the
+    orbital-level dense inverse (stage_lds 0) within the parity bar on every
+    column, the two forms of the larger class against each other, against
+    the oracle on sampled columns of both classes, and bitwise on a repeat."""
     wl = W.config_bundle_overlap(n_columns=2048, n_shifts=n_shifts, config_no=32)
     s = sgf.system_for(wl)
     assert s.s_orbital_diagonal
@@ -455,15 +457,26 @@ def test_overlap_per_atom_inverse(sgf, O, n_shifts):
     assert n_loc.min() <= 16 < n_loc.max()
     got = sgf.solve_prepared(prep, wl.z, wl.w, tol=wl.tol).numpy()
     again = sgf.solve_prepared(prep, wl.z, wl.w, tol=wl.tol).numpy()
+    one_wave = sgf.solve_prepared(prep, wl.z, wl.w, tol=wl.tol, stage_lds=4).numpy()
     dense = sgf.solve_prepared(prep, wl.z, wl.w, tol=wl.tol, stage_lds=0).numpy()
     assert np.all(got.status == sgf.CONVERGED) and np.all(dense.status == sgf.CONVERGED)
+    assert np.all(one_wave.status == sgf.CONVERGED)
     np.testing.assert_array_equal(got.G, again.G)
     np.testing.assert_array_equal(got.rho, again.rho)
+    # the classes of <= 16 atoms run the same kernel in both
+    small = n_loc <= 16
+    for c in np.nonzero(small)[0][:64]:
+        rows = slice(got.proj_off[c], got.proj_off[c + 1])
+        np.testing.assert_array_equal(got.G[rows], one_wave.G[rows])
     dense.proj_ptr = dense.proj_off
+    one_wave.proj_ptr = one_wave.proj_off
     e_g, e_r = col_rel_err(got, dense), rho_rel_err(got, dense)
-    print(f"  {n_shifts} shifts: per-atom vs orbital inverse: G {e_g:.2e}, rho {e_r:.2e}; iterations "
-          f"{got.iters.mean():.1f} vs {dense.iters.mean():.1f}", flush=True)
+    e_g1, e_r1 = col_rel_err(got, one_wave), rho_rel_err(got, one_wave)
+    print(f"  {n_shifts} shifts: per-atom vs orbital inverse: G {e_g:.2e}, rho {e_r:.2e}; two vs one wavefront "
+          f"per column: G {e_g1:.2e}, rho {e_r1:.2e}; iterations {got.iters.mean():.1f} vs "
+          f"{dense.iters.mean():.1f}", flush=True)
     assert e_g < FP64_RTOL and e_r < FP64_RTOL
+    assert e_g1 < FP64_RTOL and e_r1 < FP64_RTOL
     assert abs(got.iters.mean() - dense.iters.mean()) <= 0.1 * dense.iters.mean() + 2
     small, big = np.nonzero(n_loc <= 16)[0][:12], np.nonzero(n_loc > 16)[0][:12]
     pick = np.sort(np.concatenate([small, big]))
