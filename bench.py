@@ -170,16 +170,22 @@ def roofline_line(fig, seed_ms, shift_ms, launches, traffic_seed, traffic_shift,
     }
 
 
-def train_scheduler(sgf, W, dev, n_logged=50000):
+def train_scheduler(sgf, W, dev, n_logged=50000, kind="bundle"):
     """The learned scheduler's setup (outside the timed region): log the
-    iteration counts of n_logged solves of a differently seeded bundle of the
-    same shape, then train the iteration-count network on them with the
-    library's own kernels."""
+    iteration counts of n_logged solves of a differently seeded workload of
+    the same shape (kind "bundle": the S = I bundle; "overlap": the overlap
+    bundle with its radius per column), then train the iteration-count
+    network on them with the library's own kernels."""
     import torch
-    tw = W.config_bundle(config_no=20)
-    cols = np.sort(np.random.default_rng(5).choice(tw.columns, n_logged, replace=False))
+    if kind == "overlap":
+        tw = W.config_bundle_overlap(config_no=30)
+    else:
+        tw = W.config_bundle(config_no=20)
+    pick = np.sort(np.random.default_rng(5).choice(tw.columns.size, n_logged, replace=False))
+    cols = tw.columns[pick]
+    rpc = None if tw.radius_per_col is None else tw.radius_per_col[pick]
     ts = sgf.system_for(tw)
-    tp = sgf.prepare(ts, cols, radius=tw.radius, prune=True)
+    tp = sgf.prepare(ts, cols, radius=tw.radius, radius_per_col=rpc, prune=True)
     tr = sgf.solve_prepared(tp, tw.z, tw.w, tol=tw.tol, g_out=False,
                             batch_cols=sgf.batch_limit(tp, tw.z.size, 16 << 30))
     feat = sgf.features(tp)
@@ -324,7 +330,7 @@ def wp_stream(sgf, W, dev, steps=10):
             "peak_GBps": PEAK_HBM_GBS, "steps": steps, "cases": cases}
 
 
-def extra_workloads(sgf, W, dev, ws_gib, check_n, reps=5, only=None):
+def extra_workloads(sgf, W, dev, ws_gib, check_n, reps=5, only=None, models=None):
     """The other workloads, each a warm-up solve and then `reps` timed solves
     (median), with the seed and shift passes timed per launch by HIP events:
 
@@ -337,8 +343,13 @@ def extra_workloads(sgf, W, dev, ws_gib, check_n, reps=5, only=None):
       density matrix only: G alone would be 328 GB) in streamed launches.
 
     All FP64 at the workloads' own tolerances, in workspace-sized launches.
-    Returns the timings and, per workload, the outputs of `check_n` seeded
-    columns (all of them for the chain) for the oracle comparison."""
+    A workload with a trained iteration-count network in `models` is also
+    timed in the learned order (features, prediction and the grouped order
+    inside the timed region), `reps` solves after a warm-up, and the gain
+    over the natural order reported; the results of the two orders are
+    checked to be the same bits.  Returns the timings and, per workload, the
+    outputs of `check_n` seeded columns (all of them for the chain) for the
+    oracle comparison."""
     import torch
     out, keep = {}, {}
     cases = (("chain", W.config_chain(), True, True, "2000-site chain (S = I, whole system)"),
@@ -408,6 +419,25 @@ def extra_workloads(sgf, W, dev, ws_gib, check_n, reps=5, only=None):
                                                    "kernel": "k_seed_kr" if per_atom else "k_seed_gen2s / k_seed_gen2"}}
         log(f"[bench] {name}: {wl.columns.size} columns x {ns} shifts in {ms:.1f} ms (median of {n_reps}; "
             f"{conv / (ms * 1e-3):.3g} solves/s, {prof[2]} launches)")
+        if models and name in models:
+            lt = []
+            rho_nat = res.rho.clone()
+            for rep in range(n_reps + 1):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                order = sgf.learned_order(prep, models[name])
+                res = sgf.solve_prepared(prep, wl.z, wl.w, tol=wl.tol, g_out=g_out, batch_cols=batch, out=buf,
+                                         order=order, shift_iters=True)
+                torch.cuda.synchronize()
+                if rep:
+                    lt.append((time.perf_counter() - t0) * 1e3)
+            same = bool(torch.equal(res.rho, rho_nat))
+            lms = float(np.median(lt))
+            out[name]["learned_order"] = {"ms": lms, "ms_all_reps": lt, "gain_vs_natural": ms / lms,
+                                          "rho_bitwise_equal": same}
+            log(f"[bench] {name}: learned order {lms:.1f} ms (gain {ms / lms:.4f} over natural order; "
+                f"rho bitwise equal: {same})")
+            del rho_nat
         if wl.tb and wl.tb.overlap:
             out[name]["after_rho"] = overlap_forces(sgf, prep, res, wl)
         n_check = wl.columns.size if name == "chain" else min(check_n, wl.columns.size)
@@ -703,7 +733,12 @@ def main(argv=None):
         print(json.dumps({"wavepacket": wp_stream(sgf, W, dev)}), flush=True)
         return 0
     if args.extra_only:
-        extra, _ = extra_workloads(sgf, W, dev, min(args.ws_gib, 64.0), 1, only=only)
+        models = {}
+        if only is None or "large_share" in only:
+            models["large_share"] = train_scheduler(sgf, W, dev)[0]
+        if only is None or "bundle_overlap_uneven" in only:
+            models["bundle_overlap_uneven"] = train_scheduler(sgf, W, dev, kind="overlap")[0]
+        extra, _ = extra_workloads(sgf, W, dev, min(args.ws_gib, 64.0), 1, only=only, models=models)
         print(json.dumps({"other_workloads": extra}), flush=True)
         return 0
     wl = W.config_bundle()
@@ -865,7 +900,14 @@ def main(argv=None):
         fewer, fewer_keep = fermi_poles_leg(sgf, W, dev, min(args.ws_gib, 64.0))
     if not args.no_extra:
         torch.cuda.empty_cache()
-        extra, extra_keep = extra_workloads(sgf, W, dev, min(args.ws_gib, 64.0), 1000, only=only)
+        models = {"large_share": model}
+        if only is None or "bundle_overlap_uneven" in only:
+            models["bundle_overlap_uneven"], train_ovl = train_scheduler(sgf, W, dev, kind="overlap")
+            train_info["overlap"] = train_ovl
+            log(f"[bench] overlap scheduler: held-out MSE {train_ovl['heldout_mse']:.4f} (target variance "
+                f"{train_ovl['target_var']:.4f})")
+        torch.cuda.empty_cache()
+        extra, extra_keep = extra_workloads(sgf, W, dev, min(args.ws_gib, 64.0), 1000, only=only, models=models)
 
     cpu = None
     if not args.no_cpu_baseline:

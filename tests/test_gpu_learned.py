@@ -180,3 +180,68 @@ def test_grouped_order_keeps_plans_together(sgf):
     g = sgf.solve_prepared(prep, wl.z, wl.w, tol=wl.tol, order=torch.as_tensor(order, device="cuda")).numpy()
     np.testing.assert_array_equal(a.G, g.G)
     np.testing.assert_array_equal(a.rho, g.rho)
+
+
+def test_learned_order_balances_plain_launches(sgf):
+    """What the trained network gains over the natural order: the network is
+    trained on solves of one bundle and orders the columns of another into
+    fixed launches of 2048 columns.  A launch this small gives each
+    wavefront at most one column group, so it lasts as long as its slowest
+    column; the sum over launches of the largest iteration count is the
+    modelled cost.  The learned order must cost less than the natural one
+    (and no less than the order by the true counts); the measured times of
+    the two launch sequences are printed beside it."""
+    import time
+    import torch
+    train_wl = W.bundle_workload(6, 6, 400, n_shifts=128, config_no=20)
+    s_tr = sgf.system_for(train_wl)
+    prep_tr = sgf.prepare(s_tr, train_wl.columns, radius=train_wl.radius, prune=True)
+    res_tr = sgf.solve_prepared(prep_tr, train_wl.z, train_wl.w, tol=train_wl.tol, g_out=False)
+    feat = sgf.features(prep_tr)
+    target = torch.log(res_tr.iters.to(torch.float32))
+    model = sgf.IterationModel(W.mlp_init(3))
+    hist, test_mse = model.fit(feat, target, epochs=20, lr=1e-3, seed=4)
+    var = float(target.var())
+    del prep_tr, res_tr, s_tr
+
+    wl = W.bundle_workload(6, 6, 400, n_shifts=128, config_no=21)
+    s = sgf.system_for(wl)
+    prep = sgf.prepare(s, wl.columns, radius=wl.radius, prune=True)
+    nat = sgf.solve_prepared(prep, wl.z, wl.w, tol=wl.tol, g_out=False)
+    it = nat.iters.cpu().numpy()
+    pred = model.predict(sgf.features(prep)).cpu().numpy()
+    heldout_r2 = 1.0 - np.mean((pred - np.log(it)) ** 2) / np.var(np.log(it))
+    learned = sgf.learned_order(prep, model).cpu().numpy()
+    # the order by the true counts, plans together (the bound for any order)
+    cp = prep.col_plan.cpu().numpy()
+    pk = np.zeros(prep.plan.n_plans)
+    np.maximum.at(pk, cp, it)
+    best = np.lexsort((cp, -pk[cp]))
+    B = 2048
+
+    def cost(order):
+        o = np.arange(it.size) if order is None else order
+        return sum(int(it[o[i:i + B]].max()) for i in range(0, o.size, B))
+
+    c_nat, c_lrn, c_best = cost(None), cost(learned), cost(best)
+
+    def timed(order):
+        ts = []
+        od = None if order is None else torch.as_tensor(order.astype(np.int32), device="cuda")
+        for _ in range(4):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = sgf.solve_prepared(prep, wl.z, wl.w, tol=wl.tol, g_out=False, batch_cols=B, order=od)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts[1:])), r
+
+    t_nat, r_nat = timed(None)
+    t_lrn, r_lrn = timed(learned)
+    print(f"  held-out MSE {test_mse:.4f} vs variance {var:.4f} (training geometry); other geometry R^2 "
+          f"{heldout_r2:.3f}; modelled launch cost natural {c_nat}, learned {c_lrn}, by true counts {c_best} "
+          f"(gain {c_nat / c_lrn:.3f}, bound {c_nat / c_best:.3f}); measured {t_nat * 1e3:.1f} ms natural, "
+          f"{t_lrn * 1e3:.1f} ms learned (gain {t_nat / t_lrn:.3f})", flush=True)
+    np.testing.assert_array_equal(r_nat.rho.cpu().numpy(), r_lrn.rho.cpu().numpy())
+    assert test_mse < 0.8 * var
+    assert c_best <= c_lrn < c_nat
