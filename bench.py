@@ -244,6 +244,58 @@ def recorded_traffic(kernel, kind):
     return k["fetch_kib"] * 1024 * sc["fetch_scale"] + k["write_kib"] * 1024 * sc["write_scale"]
 
 
+def record_traffic(dirs):
+    """Write profiles/pmc_traffic.json from four rocprofv3 --pmc CSV folders:
+    FETCH_SIZE and WRITE_SIZE of one bench step (the solver passes: the
+    second dispatch of each, the full bundle, after the scheduler's training
+    solve) and of `--spmv-only` (the operator apply, mean over its
+    dispatches, and the ten 1 GiB copies that scale the counters).  Each
+    kernel's entry carries the fingerprint of the source it was measured
+    on; recorded_traffic() ignores it once the source changes."""
+    import collections
+    import csv
+    import glob
+    import re
+    mf, mw, sf, sw = dirs.split(",")
+
+    def load(d):
+        out = collections.defaultdict(list)
+        for f in sorted(glob.glob(os.path.join(d, "*counter_collection.csv"))):
+            rows = sorted(csv.DictReader(open(f)), key=lambda r: int(r["Dispatch_Id"]))
+            for r in rows:
+                out[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return out
+
+    F, Wr, SF, SW = load(mf), load(mw), load(sf), load(sw)
+    cf = [v for v in SF["__amd_rocclr_copyBuffer"] if v > 1000]
+    cw = [v for v in SW["__amd_rocclr_copyBuffer"] if v > 1000]
+    sc = {"bytes": 1 << 30, "dispatches": len(cf), "fetch_kib": sum(cf) / len(cf), "write_kib": sum(cw) / len(cw)}
+    sc["fetch_scale"] = (1 << 20) / sc["fetch_kib"]
+    sc["write_scale"] = (1 << 20) / sc["write_kib"]
+    kernels = {}
+    for name, vals in F.items():
+        kind = ("seed_q4" if "k_seed_q4<" in name else "seed" if "k_seed_r1<" in name else
+                "shift" if "k_shift<" in name else None)
+        if kind is None or len(vals) < 2 or len(Wr.get(name, [])) < 2:
+            continue
+        short = re.search(r"(k_\w+<[^>]*>)", name).group(1)
+        kernels[short] = {"launch": "full bundle, 473,200 columns, one launch (second dispatch of the run)",
+                          "fetch_kib": vals[1], "write_kib": Wr[name][1], "fingerprint": kernel_fingerprint(kind)}
+    for name, vals in SF.items():
+        if "k_bsr_apply" not in name or name not in SW:
+            continue
+        short = re.search(r"(k_\w+<[^>]*>)", name).group(1)
+        kernels[short] = {"launch": f"1,000,300-atom operator, mean of {len(vals)} dispatches",
+                          "fetch_kib": sum(vals) / len(vals), "write_kib": sum(SW[name]) / len(SW[name]),
+                          "fingerprint": kernel_fingerprint("apply")}
+    for v in kernels.values():
+        v["traffic_bytes"] = v["fetch_kib"] * 1024 * sc["fetch_scale"] + v["write_kib"] * 1024 * sc["write_scale"]
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    json.dump({"copy_reference": sc, "kernels": kernels}, open(path, "w"), indent=1)
+    for k, v in kernels.items():
+        print(f"{k}: {v['traffic_bytes'] / 1e9:.3f} GB per launch")
+
+
 def hbm_stream(sgf, W, dev, reps=50):
     """The global operator apply y = (z - H) x on the 1,000,300-atom share
     (570 MB of FP64 blocks, larger than the 256 MB last-level cache), timed
@@ -330,7 +382,9 @@ def wp_stream(sgf, W, dev, steps=10):
             "peak_GBps": PEAK_HBM_GBS, "steps": steps, "cases": cases}
 
 
-def extra_workloads(sgf, W, dev, ws_gib, check_n, reps=5, only=None, models=None):
+def extra_workloads(sgf, W, dev, ws_gib, check_n, reps=5, only=None, models=None,
+                    graph_cases=("bundle_overlap_uneven",), plain_cases=("bundle_overlap_uneven",),
+                    plain_cols=16384):
     """The other workloads, each a warm-up solve and then `reps` timed solves
     (median), with the seed and shift passes timed per launch by HIP events:
 
@@ -349,7 +403,10 @@ def extra_workloads(sgf, W, dev, ws_gib, check_n, reps=5, only=None, models=None
     over the natural order reported; the results of the two orders are
     checked to be the same bits.  Returns the timings and, per workload, the
     outputs of `check_n` seeded columns (all of them for the chain) for the
-    oracle comparison."""
+    oracle comparison.  The workloads in `graph_cases` are also timed as
+    replays of that solve captured into a HIP graph, and those in
+    `plain_cases` in fixed launches of `plain_cols` columns, natural order
+    against the learned one (median of 2 after a warm-up)."""
     import torch
     out, keep = {}, {}
     cases = (("chain", W.config_chain(), True, True, "2000-site chain (S = I, whole system)"),
@@ -437,6 +494,50 @@ def extra_workloads(sgf, W, dev, ws_gib, check_n, reps=5, only=None, models=None
                                           "rho_bitwise_equal": same}
             log(f"[bench] {name}: learned order {lms:.1f} ms (gain {ms / lms:.4f} over natural order; "
                 f"rho bitwise equal: {same})")
+            if name in plain_cases:
+                # fixed launches of plain_cols columns (each waits for its
+                # slowest column): natural order against the learned one
+                pt = {"natural": [], "learned": []}
+                for mode in ("natural", "learned"):
+                    for rep in range(3):
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        od = sgf.learned_order(prep, models[name]) if mode == "learned" else None
+                        res = sgf.solve_prepared(prep, wl.z, wl.w, tol=wl.tol, g_out=g_out,
+                                                 batch_cols=min(plain_cols, batch), out=buf, order=od)
+                        torch.cuda.synchronize()
+                        if rep:
+                            pt[mode].append((time.perf_counter() - t0) * 1e3)
+                pn, pl_ = float(np.median(pt["natural"])), float(np.median(pt["learned"]))
+                out[name]["plain_launches"] = {"batch_cols": int(min(plain_cols, batch)), "natural_ms": pn,
+                                               "learned_ms": pl_, "gain_vs_natural": pn / pl_,
+                                               "rho_bitwise_equal": bool(torch.equal(res.rho, rho_nat))}
+                log(f"[bench] {name}: launches of {min(plain_cols, batch)} columns: natural {pn:.1f} ms, "
+                    f"learned {pl_:.1f} ms (gain {pn / pl_:.4f})")
+            if name in graph_cases:
+                # the same solve (learned order) captured once into a HIP graph
+                # and replayed: kernel launches only, on the solve's own buffers
+                gr = sgf.SolveGraph(prep, wl.z, wl.w, tol=wl.tol, order=order, out=buf, g_out=g_out,
+                                    batch_cols=batch)
+                gt = []
+                for rep in range(n_reps + 1):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    gr.replay()
+                    torch.cuda.synchronize()
+                    if rep:
+                        gt.append((time.perf_counter() - t0) * 1e3)
+                    if rep == 1:
+                        # eager work between replays (a graph must not depend on what ran before it)
+                        sgf.learned_order(prep, models[name])
+                gsame = bool(torch.equal(gr.result.rho, rho_nat))
+                gms = float(np.median(gt))
+                out[name]["graph_replay"] = {"ms": gms, "ms_all_reps": gt, "rho_bitwise_equal": gsame,
+                                             "what": "solve in the learned order captured into one HIP graph "
+                                                     "(ticket clears, seed and shift passes of every batch)"}
+                log(f"[bench] {name}: HIP-graph replay {gms:.1f} ms (rho bitwise equal: {gsame})")
+                res = gr.result
+                del gr
             del rho_nat
         if wl.tb and wl.tb.overlap:
             out[name]["after_rho"] = overlap_forces(sgf, prep, res, wl)
@@ -696,6 +797,10 @@ def main(argv=None):
     ap.add_argument("--ws-gib", type=float, default=112.0, help="solve workspace budget for the automatic batch")
     ap.add_argument("--plain-batch", type=int, default=8192, help="columns per launch of the plain variant")
     ap.add_argument("--no-variants", action="store_true", help="time only the full solver")
+    ap.add_argument("--variant-only", default="", help="comma list: time only these variants (no ratios)")
+    ap.add_argument("--record-traffic", default="",
+                    help="no GPU work: write profiles/pmc_traffic.json from the rocprofv3 CSV folders "
+                         "MAIN_FETCH,MAIN_WRITE,SPMV_FETCH,SPMV_WRITE of the FETCH_SIZE / WRITE_SIZE runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-g", action="store_true", help="skip writing G (rho only)")
@@ -712,6 +817,9 @@ def main(argv=None):
     ap.add_argument("--extra-only", action="store_true",
                     help="only the overlap and 1,000,300-atom workloads (one timed solve each)")
     args = ap.parse_args(argv)
+    if args.record_traffic:
+        record_traffic(args.record_traffic)
+        return 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: every run of this path uses a single MI355X; columns are "
               "independent, so a multi-GPU run shards columns spatially with no communication in the "
@@ -855,12 +963,18 @@ def main(argv=None):
         del res, prep, s
         mixed_batch = args.batch or sgf.batch_limit(p_probe, ns, int(args.ws_gib * (1 << 30)), precision="mixed")
         specs = [("fp64_batched", "natural", batch, "fp64", wl.tol, launch),
+                 # one column per wavefront, rows in registers: the FP64 form of the
+                 # mixed path's seed kernel (the same mapping)
+                 ("fp64_batched_register_rows", "natural", batch, "fp64", wl.tol, {"stage_lds": 3}),
                  ("fp64_plain", "natural", args.plain_batch, "fp64", wl.tol, None),
                  ("fp64_plain_learned", "learned", args.plain_batch, "fp64", wl.tol, None),
                  ("fp64_batched_learned_tol1e-13", "learned", batch, "fp64", 1e-13, launch),
                  ("mixed_batched_learned", "learned", mixed_batch, "mixed", 1e-5, None),
                  ("fp64_batched_learned_tol1e-8", "learned", batch, "fp64", 1e-8, launch),
                  ("fp64_plain_tol1e-8", "natural", args.plain_batch, "fp64", 1e-8, None)]
+        if args.variant_only:
+            keep_v = set(args.variant_only.split(","))
+            specs = [sp for sp in specs if sp[0] in keep_v]
         for name, mode, b, prec, tol, lopts in specs:
             torch.cuda.empty_cache()
             ms_v, sd_v, sh_v, l_v, (_, p_v, r_v) = timed(make_step(mode, b, prec, tol, lopts),
@@ -876,15 +990,16 @@ def main(argv=None):
                 variants[name]["rho_bitwise_equal"] = bool(torch.equal(r_v.rho, rho_ref))
             keep_sample(name, p_v, r_v)
             del r_v, p_v
-        plain_eq = variants["fp64_plain_tol1e-8"]["ms_per_step"]
-        variants["speedup_vs_fp64_plain"] = variants["fp64_plain"]["ms_per_step"] / ms_step
-        variants["learned_gain_vs_natural_order"] = variants["fp64_batched"]["ms_per_step"] / ms_step
-        variants["learned_gain_vs_natural_order_plain_launches"] = (variants["fp64_plain"]["ms_per_step"] /
-                                                                    variants["fp64_plain_learned"]["ms_per_step"])
-        variants["speedup_mixed_vs_fp64_plain_equal_accuracy"] = plain_eq / variants["mixed_batched_learned"][
-            "ms_per_step"]
-        variants["speedup_fp64_batched_learned_vs_plain_equal_accuracy"] = plain_eq / variants[
-            "fp64_batched_learned_tol1e-8"]["ms_per_step"]
+        if not args.variant_only:
+            plain_eq = variants["fp64_plain_tol1e-8"]["ms_per_step"]
+            variants["speedup_vs_fp64_plain"] = variants["fp64_plain"]["ms_per_step"] / ms_step
+            variants["learned_gain_vs_natural_order"] = variants["fp64_batched"]["ms_per_step"] / ms_step
+            variants["learned_gain_vs_natural_order_plain_launches"] = (
+                variants["fp64_plain"]["ms_per_step"] / variants["fp64_plain_learned"]["ms_per_step"])
+            variants["speedup_mixed_vs_fp64_plain_equal_accuracy"] = plain_eq / variants["mixed_batched_learned"][
+                "ms_per_step"]
+            variants["speedup_fp64_batched_learned_vs_plain_equal_accuracy"] = plain_eq / variants[
+                "fp64_batched_learned_tol1e-8"]["ms_per_step"]
 
     hbm = None
     if not args.no_hbm:

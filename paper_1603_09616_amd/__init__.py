@@ -617,9 +617,11 @@ class SolveGraph:
     batch) and writes the same output buffers on every replay.  Device data
     the graph reads (H, the plan, the column order) may change in place
     between replays, e.g. new Hamiltonian values on the same bond pattern.
-    The column order, if any, must be a device tensor."""
+    The column order, if any, must be a device tensor.  ``out`` (the _out of
+    an earlier Result of the same prepared set) reuses that solve's output
+    buffers and workspace instead of allocating new ones."""
 
-    def __init__(self, prep: Prepared, z, w=None, tol=1e-10, order=None, **kw):
+    def __init__(self, prep: Prepared, z, w=None, tol=1e-10, order=None, out=None, **kw):
         torch = _torch()
         if kw.get("precision", "fp64") == "mixed":
             kw["fallback"] = False   # the FP64 re-solve reads the status array (a synchronisation)
@@ -627,7 +629,7 @@ class SolveGraph:
             raise TypeError("SolveGraph: order must be a device tensor")
         kw.pop("profile", None)
         self.prep, self.z, self.w, self.tol, self.order, self.kw = prep, z, w, tol, order, kw
-        self.result = solve_prepared(prep, z, w, tol, order=order, **kw)
+        self.result = solve_prepared(prep, z, w, tol, order=order, out=out, **kw)
         torch.cuda.synchronize()
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
