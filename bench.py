@@ -384,7 +384,7 @@ def wp_stream(sgf, W, dev, steps=10):
 
 def extra_workloads(sgf, W, dev, ws_gib, check_n, reps=5, only=None, models=None,
                     graph_cases=("bundle_overlap_uneven",), plain_cases=("bundle_overlap_uneven",),
-                    plain_cols=16384):
+                    plain_cols=16384, mixed_cases=("large_share",)):
     """The other workloads, each a warm-up solve and then `reps` timed solves
     (median), with the seed and shift passes timed per launch by HIP events:
 
@@ -406,7 +406,8 @@ def extra_workloads(sgf, W, dev, ws_gib, check_n, reps=5, only=None, models=None
     oracle comparison.  The workloads in `graph_cases` are also timed as
     replays of that solve captured into a HIP graph, and those in
     `plain_cases` in fixed launches of `plain_cols` columns, natural order
-    against the learned one (median of 2 after a warm-up)."""
+    against the learned one (median of 2 after a warm-up); those in
+    `mixed_cases` also run once on the mixed-precision path."""
     import torch
     out, keep = {}, {}
     cases = (("chain", W.config_chain(), True, True, "2000-site chain (S = I, whole system)"),
@@ -494,6 +495,36 @@ def extra_workloads(sgf, W, dev, ws_gib, check_n, reps=5, only=None, models=None
                                           "rho_bitwise_equal": same}
             log(f"[bench] {name}: learned order {lms:.1f} ms (gain {ms / lms:.4f} over natural order; "
                 f"rho bitwise equal: {same})")
+            if name in mixed_cases:
+                # the mixed path on this workload (complex-FP32 Krylov vectors,
+                # FP64 scalars, FP64 true-residual monitor every 50
+                # iterations), columns it does not certify re-solved in FP64;
+                # one solve, its diagonal density-matrix entries checked
+                # against the oracle
+                torch.cuda.empty_cache()
+                mb = sgf.batch_limit(prep, ns, int(ws_gib * (1 << 30)), precision="mixed")
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rm = sgf.solve_prepared(prep, wl.z, wl.w, tol=1e-5, precision="mixed", g_out=g_out,
+                                        batch_cols=mb, monitor_every=50, profile=True)
+                torch.cuda.synchronize()
+                mms = (time.perf_counter() - t0) * 1e3
+                stm = rm.status.cpu().numpy()
+                acc_cols = int(np.sum((stm == sgf.CONVERGED) | (stm == sgf.DIAG_ONLY)))
+                out[name]["mixed"] = {"ms": mms, "tol": 1e-5, "monitor_every": 50, "batch_cols": int(mb),
+                                      "fp64_fallback_columns": int(rm.n_fallback),
+                                      "columns_accepted": acc_cols,
+                                      "solves_per_s": acc_cols * ns / (mms * 1e-3)}
+                log(f"[bench] {name}: mixed {mms:.0f} ms ({int(rm.n_fallback)} of {wl.columns.size} columns "
+                    f"re-solved in FP64)")
+                mpick = np.sort(np.random.default_rng(1603).choice(wl.columns.size, min(check_n, wl.columns.size),
+                                                                   replace=False))
+                moff = prep.proj_off.cpu().numpy()
+                mrows = np.concatenate([np.arange(moff[c], moff[c + 1]) for c in mpick])
+                keep[name + "_mixed"] = (wl, mpick, None, rm.rho[torch.as_tensor(mrows, device=dev)].cpu().numpy(),
+                                         stm[mpick], prune)
+                del rm
+                torch.cuda.empty_cache()
             if name in plain_cases:
                 # fixed launches of plain_cols columns (each waits for its
                 # slowest column): natural order against the learned one
@@ -605,20 +636,26 @@ def check_extra(keep):
         ref = oracle.solve_workload(wl, b, cols=wl.columns[pick], prune=prune, threads=threads)
         dt = time.perf_counter() - t0
         a = {"columns": int(pick.size), "oracle_s": dt, "oracle_threads": threads}
-        e_rho = e_g = e_jj = 0.0
+        e_rho = e_g = e_jj = e_rjj = 0.0
         for i in range(pick.size):
             lo, hi = ref.proj_ptr[i], ref.proj_ptr[i + 1]
             e_rho = max(e_rho, np.abs(rho[lo:hi] - ref.rho[lo:hi]).max() / max(np.abs(ref.rho[lo:hi]).max(), 1e-300))
+            d = lo + int(np.nonzero(ref.proj_row[lo:hi] == wl.columns[pick[i]])[0][0])
+            e_rjj = max(e_rjj, abs(rho[d] - ref.rho[d]) / max(np.abs(ref.rho[lo:hi]).max(), 1e-300))
             if G is not None:
                 e_g = max(e_g, np.abs(G[lo:hi] - ref.G[lo:hi]).max() / np.abs(ref.G[lo:hi]).max())
                 d = lo + int(np.nonzero(ref.proj_row[lo:hi] == wl.columns[pick[i]])[0][0])
                 e_jj = max(e_jj, float((np.abs(G[d] - ref.G[d]) / np.abs(ref.G[d])).max()))
         a["rho_normwise"] = e_rho
+        a["rho_jj"] = e_rjj
         if G is not None:
             a["G_rows_normwise"] = e_g
             a["G_jj_worst_shift"] = e_jj
-        a["not_converged"] = int(np.sum(st != 0))
-        a["status_equal"] = bool(np.array_equal(st, ref.status))
+        if name.endswith("_mixed"):   # accepted mixed columns end DIAG_ONLY (only G_jj, rho_jj certified)
+            a["not_accepted"] = int(np.sum((st != 0) & (st != 6)))
+        else:
+            a["not_converged"] = int(np.sum(st != 0))
+            a["status_equal"] = bool(np.array_equal(st, ref.status))
         acc[name] = a
         log(f"[bench] {name}: oracle on {pick.size} columns in {dt:.1f} s; rho err {e_rho:.2e}")
     return acc
@@ -1029,7 +1066,10 @@ def main(argv=None):
         cpu, ref = cpu_baseline(wl, args.cpu_seconds)
         if extra:
             for name, a in check_extra(extra_keep).items():
-                extra[name]["accuracy_vs_oracle"] = a
+                if name.endswith("_mixed"):
+                    extra[name[:-len("_mixed")]]["mixed"]["accuracy_vs_oracle"] = a
+                else:
+                    extra[name]["accuracy_vs_oracle"] = a
         if fewer:
             fewer["rho_vs_f_H_L"] = check_fermi(fewer_keep)
         ref13 = None
