@@ -85,12 +85,15 @@ def path_bytes(nrow, iters, ns, g_out):
 
 def seed_kernel_name(ns, max_row_blocks, stage_lds=-1):
     """The S = I seed kernel the library launches for subspaces of <= 16
-    atoms: four columns per wavefront (k_seed_q4) up to 128 shifts with the
-    default choice, one column per wavefront (k_seed_r1) otherwise."""
+    atoms: with the default choice four columns per wavefront (k_seed_q4) up
+    to 128 shifts and two (k_seed_q2) up to 256; with stage_lds 5 two; one
+    column per wavefront (k_seed_r1) otherwise."""
     b = 5 if max_row_blocks <= 5 else 6 if max_row_blocks <= 6 else 8
     ns_pad = (ns + 63) // 64 * 64
     if stage_lds == -1 and ns_pad <= 128:
         return f"k_seed_q4<{ns_pad // 16}, {b}>"
+    if stage_lds in (-1, 5) and ns_pad <= 256:
+        return f"k_seed_q2<{4 if ns_pad <= 128 else 8}, {b}>"
     m = (ns + 63) // 64
     m = {1: 1, 2: 2, 3: 4, 4: 4}.get(m, 8)
     return f"k_seed_r1<{m}, {b}>"
@@ -120,7 +123,7 @@ def solve_figures(prep, res, ns, seed_ms, shift_ms, g_out, stage_lds=-1):
     whole_tf = (a4 + a8) / ((seed_ms + shift_ms) * 1e-3) / 1e12
     r1 = t.max_loc_atoms <= 16 and t.max_row_blocks <= 8
     return {
-        "seed_kernel": (seed_kernel_name(ns, t.max_row_blocks, stage_lds) if r1 and stage_lds in (-1, 3)
+        "seed_kernel": (seed_kernel_name(ns, t.max_row_blocks, stage_lds) if r1 and stage_lds in (-1, 3, 5)
                         else "k_seed (LDS-staged or global operator)"),
         "shift_kernel": shift_kernel_name(t.max_proj_atoms),
         "column_iterations": float(iters.sum()), "active_shift_steps": float(nk.sum()),
@@ -222,10 +225,12 @@ def kernel_fingerprint(kind):
         if m is None:
             return None
         start = m.start()
-        if kind == "seed_q4":   # with the row-sum helper and constants in front of it
+        end = src.find("\n}\n", m.start())
+        if kind == "seed_q4":   # the kernels of two and four columns per wavefront and their shared body
             h = src.find("constexpr int Q4_HS")
             start = h if 0 <= h < start else start
-        end = src.find("\n}\n", m.start())
+            q2 = src.find("void k_seed_q2(SolveArgs a)", m.start())
+            end = src.find("\n}\n", q2) if q2 > 0 else end
         text = src[start:end + 3]
     return hashlib.sha256((text + common).encode()).hexdigest()
 
@@ -274,7 +279,7 @@ def record_traffic(dirs):
     sc["write_scale"] = (1 << 20) / sc["write_kib"]
     kernels = {}
     for name, vals in F.items():
-        kind = ("seed_q4" if "k_seed_q4<" in name else "seed" if "k_seed_r1<" in name else
+        kind = ("seed_q4" if ("k_seed_q4<" in name or "k_seed_q2<" in name) else "seed" if "k_seed_r1<" in name else
                 "shift" if "k_shift<" in name else None)
         if kind is None or len(vals) < 2 or len(Wr.get(name, [])) < 2:
             continue
@@ -973,8 +978,8 @@ def main(argv=None):
     converged = int(np.sum(resid <= wl.tol))
     value = converged / (ms_step * 1e-3)
     fig = solve_figures(prep, res, ns, seed_ms, shift_ms, not args.no_g, launch.get("stage_lds", -1))
-    traffic_seed = recorded_traffic(fig["seed_kernel"], "seed_q4" if fig["seed_kernel"].startswith("k_seed_q4")
-                                    else "seed")
+    traffic_seed = recorded_traffic(fig["seed_kernel"], "seed_q4" if fig["seed_kernel"].startswith(
+        ("k_seed_q4", "k_seed_q2")) else "seed")
     traffic_shift = recorded_traffic(fig["shift_kernel"], "shift")
     hbm_counted = None
     if traffic_seed is not None and traffic_shift is not None:

@@ -272,10 +272,12 @@ typedef struct {
                               other shift and its residual cannot underflow first */
     int32_t monitor_every; /* mixed: FP64 true residual every K iterations (0: only at the end) */
     int32_t stage_lds;     /* seed pass, S = I: -1 auto (for subspaces of <= 64 orbitals and <= 8 blocks per
-                              row: four columns per wavefront with the blocks in LDS at <= 128 shifts,
-                              one column per wavefront with its rows in registers above; else an
-                              LDS-staged operator when it fits); 3 one column per wavefront with rows in
-                              registers; 1 LDS-staged operator; 0 operator read from global.
+                              row: four columns of a plan per wavefront with the blocks in LDS at <= 128
+                              shifts, two columns per wavefront at <= 256, one column per wavefront with
+                              its rows in registers above; else an LDS-staged operator when it fits);
+                              3 one column per wavefront with rows in registers; 5 two columns per
+                              wavefront (<= 256 shifts); 1 LDS-staged operator; 0 operator read from
+                              global.
                               S != I: -1 auto: with s_orbital_diagonal, subspaces of <= 32 atoms,
                               rows of <= 8 blocks and <= 256 shifts, the per-atom overlap inverse
                               (a launch for <= 16 atoms with one wavefront per column, a row per
@@ -286,7 +288,8 @@ typedef struct {
                               dense; 1 one launch, packed; 2 the split of -1 with one wavefront
                               per column throughout; 4 the per-atom inverse of -1 with one
                               wavefront per column (two rows per lane) in the launch for 17-32
-                              atoms, else as 0 (S = I treats 2 and 4 as 0).  0, 1 and 2 never
+                              atoms, else as 0 (S = I treats 2 and 4 as 0, S != I treats 3 and 5
+                              as 0).  0, 1 and 2 never
                               take the per-atom inverse */
     int32_t grid;          /* seed-pass persistent workgroups; 0: fill the device */
     int32_t profile;       /* 1: record HIP events around each pass (read with sgf_solve_profile) */

@@ -4,9 +4,10 @@ The choices that do not change the method, only how it maps onto the chip:
 
 * ``stage_lds``: the seed-pass variant.  S = I: -1, when every local
   subspace fits a wavefront, four columns of a plan per wavefront with its
-  blocks in LDS up to 128 shifts and register rows above; 3: register rows,
-  one column per wavefront; 1: local operator staged in LDS; 0: operator
-  read from global memory.  S != I, for the subspaces of more than 16
+  blocks in LDS up to 128 shifts, two columns up to 256 and register rows
+  above; 5: two columns per wavefront; 3: register rows, one column per
+  wavefront; 1: local operator staged in LDS; 0: operator read from global
+  memory.  S != I, for the subspaces of more than 16
   atoms: -1 the library's default (two wavefronts per column); 4 (overlap
   blocks s_ab I4) one wavefront per column with two rows per lane; 2 (a
   general overlap) one wavefront per column with the orbital-level inverse;
@@ -50,7 +51,7 @@ def candidates(totals, precision: str, has_overlap: bool, per_atom_overlap: bool
         # the variants differ only where some subspace has more than 16 atoms
         seeds = [-1] if totals.max_loc_atoms <= 16 else [-1, 4 if per_atom_overlap else 2]
     else:
-        seeds = [-1, 3, 1, 0] if register_ok else [-1, 0]
+        seeds = [-1, 5, 3, 1, 0] if register_ok else [-1, 0]
     lanes = [1, 2] if (precision == "fp64" and totals.max_proj_atoms <= 5) else [1]
     grids = [0, 2048, 1024]
     out = []

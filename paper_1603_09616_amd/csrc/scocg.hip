@@ -473,19 +473,22 @@ __global__ __launch_bounds__(SEED_T) void k_seed_r1(SolveArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Seed pass, S = I, four columns per wavefront.  Lane l serves column slot
-// cs = l / 16 of a group of four consecutive work-queue entries and local atom
-// a = l % 16 of that column's subspace (at most 16 atoms, 64 orbitals): its
-// four orbital rows of s, p and w stay in registers, and the subspace's
-// blocks of H sit in LDS, shared by the columns of the group that have the
-// same plan (the four orbitals of one atom).  The recurrence scalars of a
-// column are formed by its 16 lanes only: per iteration a wavefront pays
-// the complex divisions and the branch logic of the COCG recurrence once for
-// four columns, and its sums are 16-lane row reductions (DPP row shifts, the
-// row total handed to the row's lanes through LDS, so all of them hold the
-// same bits).  Each lane steps the collinearity factors of ns/16 shifts of
-// its own column.  The columns of a group whose plans differ run one after
-// another, each with its own plan's blocks in LDS.
+// Seed pass, S = I, four (or two) columns per wavefront.  Lane l serves
+// column slot cs = l / 16 of a group of four consecutive work-queue entries
+// and local atom a = l % 16 of that column's subspace (at most 16 atoms, 64
+// orbitals): its four orbital rows of s, p and w stay in registers, and the
+// subspace's blocks of H sit in LDS, shared by the columns of the group that
+// have the same plan (the four orbitals of one atom).  The recurrence
+// scalars of a column are formed by its 16 lanes only: per iteration a
+// wavefront pays the complex divisions and the branch logic of the COCG
+// recurrence once for four columns, and its sums are 16-lane row reductions
+// (DPP row shifts, the row total handed to the row's lanes through LDS, so
+// all of them hold the same bits).  Each lane steps the collinearity factors
+// of ns/16 shifts of its own column, which bounds the four-column form at
+// 128 shifts; up to 256, two columns per wavefront take 32 lanes each (two
+// lanes per atom, two rows each) and ns/32 shifts per lane.  The columns of
+// a group whose plans differ run one after another, each with its own plan's
+// blocks in LDS.
 // ---------------------------------------------------------------------------
 constexpr int Q4_HS = 18;   // doubles per staged block: 16 values and 2 of padding (bank spread)
 constexpr int Q4_VP = 17;   // double2 per (column slot, orbital) row of p: 16 atoms and 1 of padding
@@ -789,6 +792,338 @@ __global__ __launch_bounds__(SEED_T) void k_seed_q4(SolveArgs a) {
         }
         wave_lds_fence();  // hs and vp are reused by the next group
     }
+}
+
+// Sums over the lanes of each column (16 or 32 consecutive lanes), delivered
+// to every lane of the column in a fixed order, so that they all hold the
+// same bits: DPP row shifts sum each 16-lane row, the row totals go through
+// LDS, and a 32-lane column adds its two row totals, lower row first.
+// rb: 4 rows x 8 doubles of LDS scratch.
+template <int NV, int LPC>
+__device__ __forceinline__ void column_sums(double (&v)[NV], double *rb) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double t = v[i];
+        t += dpp_shr<0x111>(t);  // row_shr:1
+        t += dpp_shr<0x112>(t);  // row_shr:2
+        t += dpp_shr<0x114>(t);  // row_shr:4
+        t += dpp_shr<0x118>(t);  // row_shr:8
+        v[i] = t;
+    }
+    if ((lane & 15) == 15) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) rb[(lane >> 4) * 8 + i] = v[i];
+    }
+    wave_lds_fence();
+    if (LPC == 16) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) v[i] = rb[(lane >> 4) * 8 + i];
+    } else {
+        const int r0 = (lane >> 5) * 2;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) v[i] = rb[r0 * 8 + i] + rb[(r0 + 1) * 8 + i];
+    }
+    wave_lds_fence();  // rb may be written again by the next call
+}
+
+// The seed pass with CPW columns of one plan per wavefront (CPW = 4: sixteen
+// lanes per column, a lane per local atom and its four orbital rows; CPW = 2:
+// thirty-two lanes per column, two lanes per local atom, each with two of
+// its rows).  A lane steps the collinearity factors of M4 shifts of its own
+// column: shift k = l + LPC m for its lane l of the column.  Only the
+// two-column kernel is built from this body: k_seed_q4 keeps its own, since
+// compiling the four-column case from it reorders the compiler's floating
+// point and changes the rounding (and the iteration count) of columns that
+// pass close to a breakdown.
+template <int CPW, int M4, int BMAX>
+__device__ __forceinline__ void seed_columns(const SolveArgs &a) {
+    constexpr int LPC = 64 / CPW;   // lanes per column
+    constexpr int RPL = 64 / LPC;   // orbital rows per lane (4 or 2)
+    static_assert(CPW == 4 || CPW == 2, "two or four columns per wavefront");
+    __shared__ __align__(16) double hs[16 * BMAX * Q4_HS];  // block b of local atom A's row in slot 16 b + A
+    __shared__ int hcol[16 * BMAX];                         // local column atom of each slot's block
+    __shared__ __align__(16) double2 vp[4 * CPW * Q4_VP];   // p: [column slot][orbital] rows of 16 atoms
+    __shared__ __align__(16) double rb[4 * 8];              // row sums
+    __shared__ __align__(16) double2 sg[LPC * M4];          // sigma_k = z_k - z_s
+    const int lane = threadIdx.x;
+    const int cs = lane / LPC, l = lane % LPC;  // column slot, lane within the column
+    const int al = l & 15, o0 = (l >> 4) * RPL;  // local atom, first of this lane's rows
+    constexpr uint64_t CMASK = LPC == 64 ? ~0ull : ((1ull << LPC) - 1);
+    const double2 zs = a.z[a.seed];
+    for (int k = lane; k < LPC * M4; k += 64) sg[k] = k < a.ns ? csub(a.z[k], zs) : make_double2(0.0, 0.0);
+    const double tol2 = a.tol * a.tol;
+    const double2 zero = make_double2(0.0, 0.0), one = make_double2(1.0, 0.0);
+    const int64_t nbatch = a.batch_end - a.batch_begin;
+
+    for (;;) {
+        int64_t ticket = 0;
+        if (lane == 0) ticket = (int64_t)atomicAdd(reinterpret_cast<unsigned long long *>(a.ticket), 1ull);
+        ticket = __shfl(ticket, 0, 64);
+        if (CPW * ticket >= nbatch) break;
+        // this lane's column: queue entry CPW ticket + cs of the batch
+        const int64_t slot = CPW * ticket + cs;
+        const bool have = slot < nbatch;
+        int64_t c = -1, j = -1;
+        int32_t pl = -1;
+        int64_t a0 = 0, b0 = 0, p0 = 0;
+        int n_loc = 0, nblk = 0, npa = 0, cl = 0;
+        bool bad = !have;
+        if (have) {
+            c = a.order ? (int64_t)a.order[a.batch_begin + slot] : a.batch_begin + slot;
+            bad = c < 0 || c >= a.n_cols;
+        }
+        if (!bad) {
+            j = a.cols[c];
+            pl = a.col_plan[c];
+            bad = pl < 0 || pl >= a.n_plans || j < 0;
+        }
+        if (!bad) {
+            a0 = a.atom_off[pl];
+            n_loc = (int)(a.atom_off[pl + 1] - a0);
+            b0 = a.blk_off[pl];
+            nblk = (int)(a.blk_off[pl + 1] - b0);
+            p0 = a.pa_off[pl];
+            npa = (int)(a.pa_off[pl + 1] - p0);
+            cl = a.center_loc[pl];
+            bad = n_loc < 1 || n_loc > 16 || nblk > 16 * BMAX || npa < 1 || 4 * npa > a.rmax || cl < 0 ||
+                  cl >= n_loc || a.loc_atom[a0 + cl] != (int32_t)(j >> 2);
+        }
+        if (!bad) {  // rows of more than BMAX blocks: this kernel cannot take the column
+            int nb = 0;
+            if (al < n_loc) nb = (al + 1 < n_loc ? a.lrow[a0 + al + 1] : nblk) - a.lrow[a0 + al];
+            const uint64_t over = __ballot(nb > BMAX);
+            bad = ((over >> (LPC * cs)) & CMASK) != 0;
+        }
+        if (have && bad && l == 0) {
+            a.meta[slot] = ColMeta{-1, 0, 0, SGF_BADCOLUMN};
+            if (c >= 0 && c < a.n_cols) {
+                a.iters[c] = 0;
+                a.status[c] = SGF_BADCOLUMN;
+            }
+        }
+        // column slots still to run (bit cs), one plan at a time
+        uint32_t todo = 0;
+        {
+            const uint64_t ok = __ballot(!bad && l == 0);
+#pragma unroll
+            for (int g = 0; g < CPW; ++g) todo |= ((ok >> (LPC * g)) & 1ull) ? (1u << g) : 0u;
+        }
+        while (todo) {
+            const int lead = __builtin_ctz(todo);
+            const int32_t plead = __shfl(pl, LPC * lead, 64);
+            const uint64_t same = __ballot(l == 0 && ((todo >> cs) & 1u) && pl == plead);
+            uint32_t pass = 0;
+#pragma unroll
+            for (int g = 0; g < CPW; ++g) pass |= ((same >> (LPC * g)) & 1ull) ? (1u << g) : 0u;
+            todo &= ~pass;
+            const bool mine = (pass >> cs) & 1u;   // this lane's column runs in this pass
+            // the plan's sizes, from the lead column's lanes (all equal within the pass)
+            const int64_t pa0 = __shfl(a0, LPC * lead, 64), pb0 = __shfl(b0, LPC * lead, 64);
+            const int64_t pp0 = __shfl(p0, LPC * lead, 64);
+            const int pn_loc = __shfl(n_loc, LPC * lead, 64), pnblk = __shfl(nblk, LPC * lead, 64);
+            const int pnpa = __shfl(npa, LPC * lead, 64), pcl = __shfl(cl, LPC * lead, 64);
+            // stage the plan's blocks of H: block b of local atom A's row in
+            // slot 16 b + A, a zero block (times atom 0's p) where the row has
+            // b or fewer blocks or there is no atom A.  At step b the 16 lanes
+            // of a column read 16 consecutive slots, whose stride of 9 x 16 B
+            // starts them on 8 different 16-byte bank groups (the row-major
+            // order put the rows' first blocks about 4 slots apart, on 2)
+            wave_lds_fence();
+            for (int i = lane; i < 16 * BMAX * 8; i += 64) {
+                const int sl = i >> 3, h2 = i & 7, A = sl & 15, b = sl >> 4;
+                double2 v = zero;
+                int cb = 0;
+                if (A < pn_loc) {
+                    const int u0 = a.lrow[pa0 + A];
+                    const int u1 = A + 1 < pn_loc ? a.lrow[pa0 + A + 1] : pnblk;
+                    if (b < u1 - u0) {
+                        const int32_t *lb = &a.lblk[2 * (pb0 + u0 + b)];
+                        v = reinterpret_cast<const double2 *>(a.h + 16 * (int64_t)lb[1])[h2];
+                        cb = lb[0];
+                    }
+                }
+                reinterpret_cast<double2 *>(hs + sl * Q4_HS)[h2] = v;
+                if (h2 == 0) hcol[sl] = cb;
+            }
+            // this lane's rows
+            const bool row = mine && al < pn_loc;
+            int pq = -1;  // projection index of this lane's atom
+            for (int q = 0; q < pnpa; ++q)
+                if (row && a.pa_loc[pp0 + q] == al) pq = q;
+            const int jo = (int)(j & 3);
+            double2 *hab = a.hab + (size_t)slot * a.cap * 2;
+            double2 *hr = a.hr + (size_t)slot * (a.cap + 1) * a.rmax;
+            // start: x = 0, s_0 = p_0 = e_j
+            double2 sv[RPL], pv[RPL];
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                const int o = o0 + r;
+                sv[r] = (row && al == pcl && o == jo) ? one : zero;
+                pv[r] = sv[r];
+                vp[(4 * cs + o) * Q4_VP + al] = pv[r];
+                if (mine && pq >= 0) hr[4 * pq + o] = sv[r];
+            }
+            wave_lds_fence();
+
+            double2 pc[M4], po[M4];
+            uint32_t act = 0;
+#pragma unroll
+            for (int m = 0; m < M4; ++m) {
+                pc[m] = po[m] = one;
+                if (mine && l + LPC * m < a.ns) act |= 1u << m;
+            }
+            double2 rho = one, inv_rho = one, ba_old = zero;
+            int status = SGF_MAXITER, iters = 0, applied = 0;
+            bool running = mine;
+            double snorm2 = 1.0;
+            const int max_iter = a.max_iter > 0 ? a.max_iter : 40 * pn_loc;  // 10 per local orbital
+
+            const double *hsl = hs + al * Q4_HS + 4 * o0;  // this lane's rows of its slots (slot stride 16 Q4_HS)
+            const double2 *vpc = vp + 4 * cs * Q4_VP;      // this lane's column of p
+
+            for (int it = 0; it < max_iter; ++it) {
+                // w = z_s p - H p on this lane's rows
+                double ax[RPL], ay[RPL];
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) ax[r] = ay[r] = 0.0;
+#pragma unroll
+                for (int b = 0; b < BMAX; ++b) {
+                    const double2 *hb = reinterpret_cast<const double2 *>(hsl + 16 * Q4_HS * b);
+                    const int bcol = hcol[16 * b + al];
+                    double2 pb[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) pb[q] = vpc[q * Q4_VP + bcol];
+#pragma unroll
+                    for (int r = 0; r < RPL; ++r) {
+                        const double2 h01 = hb[2 * r], h23 = hb[2 * r + 1];
+                        ax[r] = fma(h01.x, pb[0].x, ax[r]);
+                        ay[r] = fma(h01.x, pb[0].y, ay[r]);
+                        ax[r] = fma(h01.y, pb[1].x, ax[r]);
+                        ay[r] = fma(h01.y, pb[1].y, ay[r]);
+                        ax[r] = fma(h23.x, pb[2].x, ax[r]);
+                        ay[r] = fma(h23.x, pb[2].y, ay[r]);
+                        ax[r] = fma(h23.y, pb[3].x, ax[r]);
+                        ay[r] = fma(h23.y, pb[3].y, ay[r]);
+                    }
+                }
+                double2 wv[RPL];
+                double sm[2] = {0.0, 0.0};
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) {
+                    wv[r] = make_double2(zs.x * pv[r].x - zs.y * pv[r].y - ax[r],
+                                         zs.x * pv[r].y + zs.y * pv[r].x - ay[r]);
+                    sm[0] = fma(pv[r].x, wv[r].x, fma(-pv[r].y, wv[r].y, sm[0]));
+                    sm[1] = fma(pv[r].x, wv[r].y, fma(pv[r].y, wv[r].x, sm[1]));
+                }
+                column_sums<2, LPC>(sm, rb);
+                const double2 mu = make_double2(sm[0], sm[1]);
+                if (running) {
+                    iters = it + 1;
+                    if (!cfinite(mu)) { status = SGF_NONFINITE; running = false; }
+                    else if (mu.x == 0.0 && mu.y == 0.0) { status = SGF_BREAKDOWN; running = false; }
+                }
+                const double2 alpha = cmul(rho, crcp(mu));
+                const double2 ia = cmul(mu, inv_rho);  // 1/alpha
+                double sr[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) {
+                    sv[r] = csub(sv[r], cmul(alpha, wv[r]));
+                    sr[0] = fma(sv[r].x, sv[r].x, fma(-sv[r].y, sv[r].y, sr[0]));
+                    sr[1] = fma(2.0 * sv[r].x, sv[r].y, sr[1]);
+                    sr[2] = fma(sv[r].x, sv[r].x, fma(sv[r].y, sv[r].y, sr[2]));
+                }
+                column_sums<3, LPC>(sr, rb);
+                const double2 rho_new = make_double2(sr[0], sr[1]);
+                const double2 beta = cmul(rho_new, inv_rho);
+                const double2 ba = cmul(beta, ia);  // beta_n / alpha_n
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) {
+                    pv[r] = cfma(beta, pv[r], sv[r]);
+                    vp[(4 * cs + o0 + r) * Q4_VP + al] = pv[r];
+                }
+                if (running) {
+                    snorm2 = sr[2];
+                    // history: 1/alpha_n, beta_n/alpha_n, r_{n+1} on P
+                    if (l == 0) {
+                        hab[2 * it] = ia;
+                        hab[2 * it + 1] = ba;
+                    }
+                    if (pq >= 0) {
+#pragma unroll
+                        for (int r = 0; r < RPL; ++r) hr[(size_t)(it + 1) * a.rmax + 4 * pq + o0 + r] = sv[r];
+                    }
+                    // collinearity factors and the freeze test ||s|| <= tol |pi^k|;
+                    // a slot whose shifts have all frozen, in every running
+                    // column of the wavefront, is not stepped (its factors
+                    // are never read again)
+                    const double2 coup = cmul(alpha, ba_old);
+                    const double2 c1 = cadd(one, coup), ncoup = make_double2(-coup.x, -coup.y);
+#pragma unroll
+                    for (int m = 0; m < M4; ++m) {
+                        if (!__any((act >> m) & 1u)) continue;
+                        const double2 pn = cfma(cfma(alpha, sg[l + LPC * m], c1), pc[m], cmul(ncoup, po[m]));
+                        const double pn2 = fma(pn.x, pn.x, pn.y * pn.y);
+                        po[m] = pc[m];
+                        pc[m] = pn;
+                        if (((act >> m) & 1u) && snorm2 <= tol2 * pn2) {
+                            // the estimate ||s|| / |pi^k| is formed after the
+                            // column from the two squares kept here
+                            act &= ~(1u << m);
+                            const int k = l + LPC * m;
+                            a.nk[(size_t)slot * a.ns_pad + k] = it + 1;
+                            if (a.resid) {
+                                a.resid[c * a.ns + k] = pn2;
+                                a.fz[(size_t)slot * a.ns_pad + k] = snorm2;
+                            }
+                            if (a.shift_iters) a.shift_iters[c * a.ns + k] = it + 1;
+                        }
+                    }
+                    applied = it + 1;
+                    ba_old = ba;
+                    rho = rho_new;
+                    // the column stops when none of its lanes holds an active shift
+                    const uint64_t alive = __ballot(act != 0);
+                    const bool any_alive = ((alive >> (LPC * cs)) & CMASK) != 0;
+                    if (!any_alive || snorm2 == 0.0) { status = SGF_CONVERGED; running = false; }
+                    else if (rho_new.x == 0.0 && rho_new.y == 0.0) { status = SGF_BREAKDOWN; running = false; }
+                    else if (!isfinite(rho_new.x + rho_new.y + snorm2)) { status = SGF_NONFINITE; running = false; }
+                    else inv_rho = crcp(rho_new);
+                }
+                wave_lds_fence();  // p is in LDS for the next block product
+                if (!__any(running)) break;
+            }
+            if (mine) {
+#pragma unroll
+                for (int m = 0; m < M4; ++m) {
+                    const int k = l + LPC * m;
+                    if (k >= a.ns) continue;
+                    if (!((act >> m) & 1u)) {  // frozen: ||s|| / |pi^k| at its freeze
+                        if (a.resid)
+                            a.resid[c * a.ns + k] = sqrt(a.fz[(size_t)slot * a.ns_pad + k] / a.resid[c * a.ns + k]);
+                        continue;
+                    }
+                    const double pn2 = fma(pc[m].x, pc[m].x, pc[m].y * pc[m].y);
+                    const double res = applied > 0 ? sqrt(snorm2 / pn2) : 1.0;
+                    a.nk[(size_t)slot * a.ns_pad + k] = applied;
+                    if (a.resid) a.resid[c * a.ns + k] = res;
+                    if (a.shift_iters) a.shift_iters[c * a.ns + k] = applied;
+                }
+                if (l == 0) {
+                    a.meta[slot] = ColMeta{(int32_t)c, iters, pnpa, status};
+                    a.iters[c] = iters;
+                    a.status[c] = status;
+                }
+            }
+        }
+        wave_lds_fence();  // hs and vp are reused by the next group
+    }
+}
+
+// Two columns of a plan per wavefront: up to 256 shifts (M2 = ns_pad / 32).
+template <int M2, int BMAX>
+__global__ __launch_bounds__(SEED_T) void k_seed_q2(SolveArgs a) {
+    seed_columns<2, M2, BMAX>(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -2209,6 +2544,12 @@ static KernelFn pick_seed_q4_m(int M4) { return M4 <= 4 ? k_seed_q4<4, BMAX> : k
 static KernelFn pick_seed_q4(int M4, int bmax) {
     return bmax <= 5 ? pick_seed_q4_m<5>(M4) : bmax <= 6 ? pick_seed_q4_m<6>(M4) : pick_seed_q4_m<8>(M4);
 }
+// two columns per wavefront; M2 = shifts per lane (ns_pad / 32 rounded up to 4 or 8)
+template <int BMAX>
+static KernelFn pick_seed_q2_m(int M2) { return M2 <= 4 ? k_seed_q2<4, BMAX> : k_seed_q2<8, BMAX>; }
+static KernelFn pick_seed_q2(int M2, int bmax) {
+    return bmax <= 5 ? pick_seed_q2_m<5>(M2) : bmax <= 6 ? pick_seed_q2_m<6>(M2) : pick_seed_q2_m<8>(M2);
+}
 
 template <int BMAX, bool PACKED>
 static KernelFn pick_seed_gen_m(int M) {
@@ -2473,10 +2814,15 @@ static sgf_status shifted_solve_in(const sgf_system *sys, const sgf_plan *plan, 
     const int M = hs.ns_pad / 64;
     // register variant when every subspace has <= 64 orbitals and <= 8 blocks per row
     const bool gen = sys->s != nullptr;
-    const bool r1 = !gen && (opts->stage_lds < 0 || opts->stage_lds == 3) && totals->max_loc_atoms <= 16 &&
-                    totals->max_row_blocks <= 8;
-    // four columns per wavefront when there are at most 128 shifts (8 per lane)
-    const bool q4 = r1 && !mixed && opts->stage_lds < 0 && hs.ns_pad <= 128;
+    const bool r1 = !gen && (opts->stage_lds < 0 || opts->stage_lds == 3 || opts->stage_lds == 5) &&
+                    totals->max_loc_atoms <= 16 && totals->max_row_blocks <= 8;
+    // columns of a plan per wavefront: four at up to 128 shifts, two at up to
+    // 256 (eight shifts per lane either way); stage_lds 5 takes two at any
+    // shift count up to 256
+    const int cpw = (!r1 || mixed || (opts->stage_lds >= 0 && opts->stage_lds != 5) || hs.ns_pad > 256)
+                        ? 0
+                        : (opts->stage_lds == 5 || hs.ns_pad > 128) ? 2 : 4;
+    const bool q4 = cpw == 4, q2 = cpw == 2;
     // S != I, dense-LDS variant.  stage_lds < 0: subspaces of up to 16 atoms
     // in a launch of their own with the dense inverse, the larger ones in a
     // second launch with the packed triangle (half the LDS, so twice the
@@ -2508,6 +2854,7 @@ static sgf_status shifted_solve_in(const sgf_system *sys, const sgf_plan *plan, 
                        : gen2_one ? pick_seed_gen2s((hs.ns_pad + GEN2_T - 1) / GEN2_T, totals->max_row_blocks)
                        : gen ? pick_seed_gen(M, totals->max_row_blocks, gen_packed)
                              : q4 ? pick_seed_q4(hs.ns_pad / 16, totals->max_row_blocks)
+                             : q2 ? pick_seed_q2((hs.ns_pad + 31) / 32, totals->max_row_blocks)
                              : (r1 ? pick_seed_r1(M, totals->max_row_blocks) : pick_seed(stage, M));
     const int seed_threads = (gen2 || gen2_one || kron_two_waves) ? GEN2_T : SEED_T;
     size_t seed_lds = (r1 || mixed || kron) ? 0 : lds;
@@ -2602,7 +2949,7 @@ static sgf_status shifted_solve_in(const sgf_system *sys, const sgf_plan *plan, 
         const int64_t b1 = b0 + slots < n_tickets ? b0 + slots : n_tickets;
         a.batch_begin = b0;
         a.batch_end = b1;
-        const int64_t n_tk = q4 ? (b1 - b0 + 3) / 4 : b1 - b0;  // work-queue tickets of this batch
+        const int64_t n_tk = cpw ? (b1 - b0 + cpw - 1) / cpw : b1 - b0;  // work-queue tickets of this batch
         const int64_t grid = seed_grid_max < n_tk ? seed_grid_max : n_tk;
         k_zero_ticket<<<1, 64, 0, st>>>(L.ticket);
         SGF_LAUNCHED();

@@ -10,7 +10,7 @@ def totals(atoms=15, row_blocks=5, proj=5):
 
 def test_candidates_follow_the_workload_shape():
     c = AT.candidates(totals(), "fp64", False)
-    assert {x["stage_lds"] for x in c} == {-1, 0, 1, 3}
+    assert {x["stage_lds"] for x in c} == {-1, 0, 1, 3, 5}
     assert {x["shifts_per_lane"] for x in c} == {1, 2}
     # large subspaces: no register variant; wide projections: one shift per lane
     c = AT.candidates(totals(atoms=60, proj=7), "fp64", False)

@@ -169,12 +169,14 @@ def test_bundle_at_looser_tol(sgf, O):
     compare(got, ref, rtol=1e-8, tol=wl.tol)
 
 
-@pytest.mark.parametrize("stage", [-1, 0, 1])
+@pytest.mark.parametrize("stage", [-1, 0, 1, 3, 5])
 @pytest.mark.parametrize("batch", [0, 7])
 def test_launch_shapes_agree(sgf, O, stage, batch):
-    """Each seed-pass variant (register rows, LDS-staged operator, operator
-    from global memory) gives the oracle's result, and history batching (with
-    a ragged last batch) does not change a single bit."""
+    """Each seed-pass variant (four columns per wavefront, LDS-staged
+    operator, operator from global memory, one column per wavefront with its
+    rows in registers, two columns per wavefront) gives the oracle's result,
+    and history batching (with a ragged last batch) does not change a single
+    bit."""
     wl = W.bundle_workload(2, 2, 50, n_shifts=128, config_no=74)
     cols = wl.columns[::2]
     got = sgf.solve_workload(wl, cols=cols, batch_cols=batch, stage_lds=stage).numpy()
@@ -183,6 +185,28 @@ def test_launch_shapes_agree(sgf, O, stage, batch):
     base = sgf.solve_workload(wl, cols=cols, stage_lds=stage).numpy()
     np.testing.assert_array_equal(got.G, base.G)
     np.testing.assert_array_equal(got.rho, base.rho)
+
+
+@pytest.mark.parametrize("n_shifts", [256, 200])
+def test_two_columns_per_wavefront(sgf, O, n_shifts):
+    """Above 128 shifts the default seed pass runs two columns of a plan per
+    wavefront (32 lanes per column, two rows per lane, up to eight shifts per
+    lane): against the oracle, against one column per wavefront
+    (stage_lds 3) within the parity bar, bitwise under a ragged batching and
+    a repeat."""
+    wl = W.bundle_workload(3, 2, 60, n_shifts=n_shifts, config_no=76)
+    cols = wl.columns[::3]
+    got = sgf.solve_workload(wl, cols=cols).numpy()
+    ref = O.solve_workload(wl, cols=cols, threads=8)
+    compare(got, ref)
+    again = sgf.solve_workload(wl, cols=cols, batch_cols=7).numpy()
+    np.testing.assert_array_equal(got.G, again.G)
+    np.testing.assert_array_equal(got.rho, again.rho)
+    r1 = sgf.solve_workload(wl, cols=cols, stage_lds=3).numpy()
+    r1.proj_ptr = r1.proj_off
+    e_g, e_r = col_rel_err(got, r1), rho_rel_err(got, r1)
+    print(f"  two columns vs one column per wavefront: G {e_g:.2e}, rho {e_r:.2e}", flush=True)
+    assert e_g < FP64_RTOL and e_r < FP64_RTOL
 
 
 @pytest.mark.parametrize("spl", [1, 2])
