@@ -225,12 +225,10 @@ def kernel_fingerprint(kind):
         if m is None:
             return None
         start = m.start()
-        end = src.find("\n}\n", m.start())
-        if kind == "seed_q4":   # the kernels of two and four columns per wavefront and their shared body
+        if kind == "seed_q4":   # with the row-sum helper and constants in front of it
             h = src.find("constexpr int Q4_HS")
             start = h if 0 <= h < start else start
-            q2 = src.find("void k_seed_q2(SolveArgs a)", m.start())
-            end = src.find("\n}\n", q2) if q2 > 0 else end
+        end = src.find("\n}\n", m.start())
         text = src[start:end + 3]
     return hashlib.sha256((text + common).encode()).hexdigest()
 

@@ -90,7 +90,7 @@ SolveLayout solve_layout(const HistoryShape &hs, int ns, int64_t slots, void *ba
 using KernelFn = void (*)(SolveArgs);
 
 // Mixed-precision passes (mixed.hip).
-KernelFn pick_seed_mx(int M, int bmax);
+KernelFn pick_seed_mx(int M, int bmax, bool overlap);
 KernelFn shift_mx_kernel();
 
 // S != I seed pass with the per-atom overlap inverse (seed_kron.hip):
