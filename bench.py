@@ -214,6 +214,8 @@ def kernel_fingerprint(kind):
     import hashlib
     import re
     common = open(os.path.join(CSRC, "common.hpp")).read()
+    if kind != "apply":  # the solver passes also depend on their shared header (layout, chunk sizes)
+        common += open(os.path.join(CSRC, "scocg.hpp")).read()
     if kind == "apply":
         text = open(os.path.join(CSRC, "apply.hip")).read()
     else:

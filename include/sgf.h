@@ -57,7 +57,7 @@ typedef enum {
     SGF_MAXITER = 1,    /* max_iter reached with at least one shift unconverged */
     SGF_BREAKDOWN = 2,  /* mu = p^T (z_s S - H) p or rho = r^T s vanished with s != 0 */
     SGF_NONFINITE = 3,  /* a recurrence scalar became Inf/NaN */
-    SGF_DRIFT = 4,      /* mixed path: not certified (residual drift, error bound, or a subspace above 16 atoms) */
+    SGF_DRIFT = 4,      /* mixed path: recursive and FP64 true residual disagree */
     SGF_BADCOLUMN = 5,  /* column, plan index or plan sizes inconsistent; nothing computed */
     SGF_DIAG_ONLY = 6   /* mixed path: G_jj and rho_jj are certified (a-posteriori bound within g_tol);
                            the other projection rows hold the complex-FP32 Krylov values, so the
@@ -379,29 +379,21 @@ sgf_status sgf_solve_workspace(const sgf_system *sys, const sgf_plan_totals *tot
  * is larger than the kernels' LDS allows, a column has more than 8
  * projection atoms or n_shifts > 512.
  *
- * Mixed precision (opts->precision = 1; S = I or an overlap stated as
- * blocks s_ab I4 (sys->s_orbital_diagonal = 1), <= 8 blocks per row,
- * n_shifts <= 256, sys->h32 required, else EUNSUPPORTED / EINVAL): the seed
- * iteration runs on the FP32 shadow of H with complex-FP32 vectors and FP64
- * scalars (mu, rho, alpha, beta, pi^k), and keeps the seed iterate x_s in
- * FP64; with an overlap it is COCG in the S-bilinear form with
- * r = S_L^{-1} s applied from the FP64 inverse of the atoms' overlap matrix,
- * rounded to FP32.  The FP64 true residual b - (z_s S - H) x_s is compared
+ * Mixed precision (opts->precision = 1; S = I, local subspaces of <= 16
+ * atoms with <= 8 blocks per row, n_shifts <= 256, sys->h32 required, else
+ * EUNSUPPORTED / EINVAL): the seed iteration runs on the FP32 shadow of H with
+ * complex-FP32 vectors and FP64 scalars (mu, rho, alpha, beta, pi^k), and
+ * keeps the seed iterate x_s in FP64; its FP64 true residual is compared
  * with the recursive one every monitor_every iterations and at the end
- * (SGF_DRIFT beyond drift_tol).  A column whose subspace has more than 16
- * atoms is not run by the mixed passes: it ends SGF_DRIFT with 0 iterations
- * and no output.  The shift pass rebuilds the full iterate x~^k on the
- * local subspace (complex FP32) and writes for the diagonal element the FP64
- * variational estimate 2 x~_j - x~^T (z_k S - H) x~^k, whose error is
- * quadratic in that of x~ (the stationary property of the Green's-function
- * functional for the complex symmetric z S - H).  The other projection rows
- * are the FP32-Krylov values.  From the FP64 true residual r_k of the full
- * iterate (written to d_resid instead of the recursive residual) the shift
- * pass bounds the error of the estimate rigorously,
- * |G_jj - G~_jj| <= ||r_k||^2 / (lam Im z_k), with lam = 1 for S = I and
- * otherwise the Gershgorin lower bound min_i (S_ii - sum_{l != i} |S_il|)
- * of the smallest eigenvalue of the local overlap (a column with lam <= 0
- * is rejected), and sets SGF_DRIFT on a column
+ * (SGF_DRIFT beyond drift_tol).  The shift pass rebuilds the full iterate
+ * x~^k on the local subspace (complex FP32) and writes for the diagonal
+ * element the FP64 variational estimate 2 x~_j - x~^T (z_k - H) x~^k, whose
+ * error is quadratic in that of x~ (the stationary property of the
+ * Green's-function functional for the complex symmetric z - H).  The other
+ * projection rows are the FP32-Krylov values.  From the FP64 true residual
+ * r_k of the full iterate (written to d_resid instead of the recursive
+ * residual) the shift pass bounds the error of the estimate rigorously,
+ * |G_jj - G~_jj| <= ||r_k||^2 / Im z_k, and sets SGF_DRIFT on a column
  * whose bound exceeds opts->g_tol max_k |G~_jj|.  A column whose bound
  * holds ends with SGF_DIAG_ONLY, not SGF_CONVERGED: its G_jj and rho_jj are
  * certified, its other rows are not.  A caller that needs every column

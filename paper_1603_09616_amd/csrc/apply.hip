@@ -37,27 +37,49 @@ __global__ __launch_bounds__(256) void k_bsr_apply(int64_t n_atoms, const int32_
 #pragma unroll
     for (int r = 0; r < NRHS; ++r) hx[r] = hy[r] = sx[r] = sy[r] = T(0);
     const int t0 = row_ptr[A], t1 = row_ptr[A + 1];
-    for (int t = t0; t < t1; ++t) {
+    // Two blocks per trip: both blocks' rows and both neighbours' x are
+    // loaded before either product, two loads in flight per thread instead
+    // of one (same products in the same order).
+    auto block = [&](const T (&hr)[4], const T (&sr)[4], const C (&v)[4][NRHS]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < NRHS; ++r) {
+                hx[r] = fma(hr[q], v[q][r].x, hx[r]);
+                hy[r] = fma(hr[q], v[q][r].y, hy[r]);
+                if (HAS_S) {
+                    sx[r] = fma(sr[q], v[q][r].x, sx[r]);
+                    sy[r] = fma(sr[q], v[q][r].y, sy[r]);
+                }
+            }
+    };
+    auto load = [&](int t, T (&hr)[4], T (&sr)[4], C (&v)[4][NRHS]) {
         const int64_t B = col[t];
-        T hr[4], sr[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             hr[q] = h[16 * (int64_t)t + 4 * o + q];
-            if (HAS_S) sr[q] = s[16 * (int64_t)t + 4 * o + q];
+            sr[q] = HAS_S ? s[16 * (int64_t)t + 4 * o + q] : T(0);
         }
         const C *xb = x + 4 * B * NRHS;
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int r = 0; r < NRHS; ++r) {
-                const C v = xb[q * NRHS + r];
-                hx[r] = fma(hr[q], v.x, hx[r]);
-                hy[r] = fma(hr[q], v.y, hy[r]);
-                if (HAS_S) {
-                    sx[r] = fma(sr[q], v.x, sx[r]);
-                    sy[r] = fma(sr[q], v.y, sy[r]);
-                }
-            }
+            for (int r = 0; r < NRHS; ++r) v[q][r] = xb[q * NRHS + r];
+    };
+    int t = t0;
+    for (; t + 1 < t1; t += 2) {
+        T h0[4], s0[4], h1[4], s1[4];
+        C v0[4][NRHS], v1[4][NRHS];
+        load(t, h0, s0, v0);
+        load(t + 1, h1, s1, v1);
+        block(h0, s0, v0);
+        block(h1, s1, v1);
+    }
+    if (t < t1) {
+        T h0[4], s0[4];
+        C v0[4][NRHS];
+        load(t, h0, s0, v0);
+        block(h0, s0, v0);
     }
     const int64_t row = 4 * A + o;
     const T zx = (T)zr, zy = (T)zi;
@@ -89,7 +111,8 @@ __global__ __launch_bounds__(256) void k_bsr_apply(int64_t n_atoms, const int32_
 // and 8 RHS staging takes
 // FP64 from 277 and 429 us to 211 and 308 us, and RPT 2 at 8 RHS (and at 4
 // in FP32) halves the redundant block reads of the threads of a block row
-// (FP32 x8: 260 -> 160 us).
+// (FP32 x8: 260 -> 160 us).  Two blocks per loop trip then take FP32 x1
+// from 81 to 71 us, x4 from 125 to 116 us and x8 from 160 to 156 us.
 constexpr int APPLY_T = 256;
 constexpr int APPLY_HALO = 2;
 
@@ -127,15 +150,13 @@ __global__ __launch_bounds__(APPLY_T) void k_bsr_apply_lx(int64_t n_atoms, const
     for (int o = 0; o < 4; ++o)
 #pragma unroll
         for (int u = 0; u < RPT; ++u) hx[o][u] = hy[o][u] = sx[o][u] = sy[o][u] = T(0);
-    for (int t = t0; t < t1; ++t) {
+    auto load = [&](int t, T (&hb)[NV], C (&v)[4][RPT]) {
         const int64_t B = col[t];
-        T hb[NV];   // the block of H (and of S)
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             hb[i] = h[16 * (int64_t)t + i];
             if (HAS_S) hb[16 + i] = s[16 * (int64_t)t + i];
         }
-        C v[4][RPT];
         if (B >= lo && B < hi) {
 #pragma unroll
             for (int q = 0; q < 4; ++q)
@@ -147,6 +168,8 @@ __global__ __launch_bounds__(APPLY_T) void k_bsr_apply_lx(int64_t n_atoms, const
 #pragma unroll
                 for (int u = 0; u < RPT; ++u) v[q][u] = x[(4 * B + q) * NRHS + r0 + u];
         }
+    };
+    auto block = [&](const T (&hb)[NV], const C (&v)[4][RPT]) {
 #pragma unroll
         for (int o = 0; o < 4; ++o)
 #pragma unroll
@@ -163,6 +186,47 @@ __global__ __launch_bounds__(APPLY_T) void k_bsr_apply_lx(int64_t n_atoms, const
                     }
                 }
             }
+    };
+    // FP32: two blocks per trip, both loaded before either product (FP64
+    // keeps one: at 8 right-hand sides the second block's registers cost
+    // more than the extra load in flight gains)
+    constexpr bool PAIR = sizeof(T) == 4;
+    int t = t0;
+    for (; PAIR && t + 1 < t1; t += 2) {
+        // both blocks' values first, then both neighbours' x, then the products
+        const int64_t Bp[2] = {col[t], col[t + 1]};
+        T hp[2][NV];
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                hp[e][i] = h[16 * (int64_t)(t + e) + i];
+                if (HAS_S) hp[e][16 + i] = s[16 * (int64_t)(t + e) + i];
+            }
+        C vv[2][4][RPT];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int64_t B = Bp[e];
+            if (B >= lo && B < hi) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int u = 0; u < RPT; ++u) vv[e][q][u] = xs[((B - lo) * 4 + q) * NRHS + r0 + u];
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int u = 0; u < RPT; ++u) vv[e][q][u] = x[(4 * B + q) * NRHS + r0 + u];
+            }
+        }
+        block(hp[0], vv[0]);
+        block(hp[1], vv[1]);
+    }
+    for (; t < t1; ++t) {
+        T hb[NV];   // the block of H (and of S)
+        C v[4][RPT];
+        load(t, hb, v);
+        block(hb, v);
     }
     const T zx = (T)zr, zy = (T)zi;
 #pragma unroll

@@ -1,35 +1,27 @@
-// mixed.hip -- mixed-precision shifted COCG for the generalized shifted
-// equations (z S - H) x = e_j (Introduction), S = I or the orbital-diagonal
-// overlap S_ab = s_ab I4, local subspaces of at most 16 atoms (64 orbitals).
+// mixed.hip -- mixed-precision shifted COCG (S = I, local subspaces of at
+// most 64 orbitals).
 //
 // Seed pass: the operator (FP32 shadow of H) and the Krylov vectors s, p, w
-// (and with an overlap r = S^{-1} s and q = S p) are complex FP32; every
-// scalar of the recurrence (mu, rho, alpha, beta and the per-shift collinear
-// factors pi^k) is FP64, and the reductions that produce them sum exact FP64
-// products of the FP32 entries.  With an overlap the iteration is COCG in
-// the S-bilinear form, as in the FP64 seed passes: mu = p^T w, rho = r^T s,
-// q kept by q <- s + beta q, and r = S_L^{-1} s from the FP64 inverse of
-// the atoms' overlap matrix S_a (S_L^{-1} = S_a^{-1} (x) I4), rounded to
-// FP32.  The seed iterate x_s = sum alpha_n p_n is kept in FP64, and every
-// monitor_every iterations (and at the end) the FP64 true residual
-// b - (z_s S - H) x_s is formed with the FP64 operator: if it departs from
-// the recursive residual s by more than drift_tol ||b||, the column stops
-// with status DRIFT.  The pass records the full vectors r_n (complex FP32)
-// instead of their projection rows.
+// are complex FP32; every scalar of the recurrence (mu, rho, alpha, beta and
+// the per-shift collinear factors pi^k) is FP64, and the reductions that
+// produce them sum exact FP64 products of the FP32 entries.  The seed
+// iterate x_s = sum alpha_n p_n is kept in FP64, and every monitor_every
+// iterations (and at the end) the FP64 true residual b - (z_s - H) x_s is
+// formed with the FP64 operator: if it departs from the recursive residual s
+// by more than drift_tol ||b||, the column stops with status DRIFT.  The
+// pass records the full residual vectors r_n (complex FP32) instead of their
+// projection rows.
 //
 // Shift pass: the same backward UL factorization of the shifted tridiagonal
 // as the FP64 pass, accumulated over every local row, gives the full iterate
 // x~^k of each shift (complex FP32, staged in LDS).  The diagonal element is
 // then replaced by the FP64 variational estimate
-//     G_jj(z_k) ~ 2 x~_j - x~^T (z_k S - H) x~,
-// whose error is -e^T (z_k S - H) e for e = x - x~, i.e. quadratic in the
-// error of x~ (this holds for any approximation x~ because z_k S - H is
-// complex symmetric).  The other projection rows are the FP32-Krylov iterate
-// itself.  The residual of the full iterate gives a rigorous bound on the
-// error of the estimate, which accepts or rejects (DRIFT) each column.
-//
-// A column whose subspace has more than 16 atoms is not run: it ends DRIFT
-// with no iterations and no output, for the caller's FP64 re-solve.
+//     G_jj(z_k) ~ 2 x~_j - x~^T (z_k - H) x~,
+// whose error is -e^T (z_k - H) e for e = x - x~, i.e. quadratic in the error
+// of x~ (this holds for any approximation x~ because z_k - H is complex
+// symmetric).  The other projection rows are the FP32-Krylov iterate itself.
+// The residual of the full iterate gives a rigorous bound on the error of
+// the estimate, which accepts or rejects (DRIFT) each column.
 #include "scocg.hpp"
 
 namespace sgf {
@@ -39,18 +31,10 @@ namespace {
 __device__ __forceinline__ double2 to_d(float2 v) { return make_double2((double)v.x, (double)v.y); }
 __device__ __forceinline__ float2 to_f(double2 v) { return make_float2((float)v.x, (float)v.y); }
 
-// OVL: the orbital-diagonal overlap (a.s holds blocks s_ab I4); lane l
-// owns orbital row l = 4 A + o of the subspace.
-template <int M, int BMAX, bool OVL>
+template <int M, int BMAX>
 __global__ __launch_bounds__(SEED_T) void k_seed_mx(SolveArgs a) {
-    constexpr int KP = 17;      // LDS row stride of S_a and its inverse (odd: atoms on different banks)
-    constexpr int NS = OVL ? 16 * KP : 1;
     __shared__ float2 vp[64];   // p, for the neighbour reads of the block product
     __shared__ double2 vx[64];  // x_s, for the FP64 monitor
-    __shared__ float2 vs[OVL ? 64 : 1];  // s, for r = S^{-1} s
-    __shared__ double sa[NS];   // S_a (FP64), for the monitor
-    __shared__ double si[NS];   // S_a^{-1} (FP64, Gauss-Jordan)
-    __shared__ float sif[NS];   // S_a^{-1} rounded to FP32, for the iteration
     const int lane = threadIdx.x;
     const double2 zs = a.z[a.seed];
     const float2 zsf = to_f(zs);
@@ -91,16 +75,8 @@ __global__ __launch_bounds__(SEED_T) void k_seed_mx(SolveArgs a) {
             p0 = a.pa_off[pl];
             npa = (int)(a.pa_off[pl + 1] - p0);
             cl = a.center_loc[pl];
-            bad = n_loc < 1 || npa < 1 || npa > 8 || cl < 0 || cl >= n_loc ||
+            bad = n_loc < 1 || n_loc > 16 || npa < 1 || npa > 8 || cl < 0 || cl >= n_loc ||
                   a.loc_atom[a0 + cl] != (int32_t)(j >> 2);
-        }
-        if (!bad && n_loc > 16) {  // beyond this pass: left to the FP64 re-solve
-            if (lane == 0) {
-                *meta = ColMeta{-1, 0, 0, SGF_DRIFT};
-                a.iters[c] = 0;
-                a.status[c] = SGF_DRIFT;
-            }
-            continue;
         }
         const int nl = 4 * n_loc;
         const int A = lane >> 2, o = lane & 3;
@@ -111,54 +87,6 @@ __global__ __launch_bounds__(SEED_T) void k_seed_mx(SolveArgs a) {
             nb = (A + 1 < n_loc ? a.lrow[a0 + A + 1] : nblk) - t0;
         }
         bad = bad || __any(nb > BMAX);
-        if constexpr (OVL) {
-            // S_a from the blocks of S: lane A < n_loc reads its atom's row
-            // and checks that each block is s_ab I4
-            wave_lds_fence();  // the previous column's LDS reads are done
-            for (int e = lane; e < NS; e += 64) sa[e] = si[e] = 0.0;
-            wave_lds_fence();
-            bool notk = false;
-            if (!bad && lane < n_loc) {
-                const int u0 = a.lrow[a0 + lane], u1 = lane + 1 < n_loc ? a.lrow[a0 + lane + 1] : nblk;
-                for (int t = u0; t < u1; ++t) {
-                    const int B = a.lblk[2 * (b0 + t)];
-                    if (B < 0 || B >= n_loc) {
-                        notk = true;
-                        break;
-                    }
-                    const double *sb = &a.s[16 * (int64_t)a.lblk[2 * (b0 + t) + 1]];
-                    const double d = sb[0];
-                    bool ok = sb[5] == d && sb[10] == d && sb[15] == d;
-#pragma unroll
-                    for (int e = 1; e < 15; ++e)
-                        if (e % 5 != 0) ok = ok && sb[e] == 0.0;
-                    notk = notk || !ok;
-                    sa[KP * lane + B] = d;
-                    si[KP * lane + B] = d;
-                }
-            }
-            bad = __any(bad || notk);
-            if (!bad) {
-                wave_lds_fence();  // S_a is complete
-                // S_a^{-1} in place: Gauss-Jordan elimination without
-                // pivoting (S_a is positive definite); lane l updates row l
-                for (int kk = 0; kk < n_loc; ++kk) {
-                    const double piv = 1.0 / si[KP * kk + kk];
-                    const double f = (lane < n_loc && lane != kk) ? si[KP * lane + kk] : 0.0;
-                    wave_lds_fence();
-                    if (lane < n_loc) si[KP * kk + lane] = lane == kk ? piv : si[KP * kk + lane] * piv;
-                    wave_lds_fence();
-                    if (lane < n_loc && lane != kk) {
-                        for (int jj = 0; jj < n_loc; ++jj)
-                            si[KP * lane + jj] = fma(-f, si[KP * kk + jj], si[KP * lane + jj]);
-                        si[KP * lane + kk] = -f * piv;
-                    }
-                    wave_lds_fence();
-                }
-                for (int e = lane; e < NS; e += 64) sif[e] = (float)si[e];
-                wave_lds_fence();
-            }
-        }
         if (bad) {
             if (lane == 0) {
                 *meta = ColMeta{-1, 0, 0, SGF_BADCOLUMN};
@@ -203,20 +131,10 @@ __global__ __launch_bounds__(SEED_T) void k_seed_mx(SolveArgs a) {
                     }
                 }
             }
-            double2 sx = x;  // (S x_s) on this row
-            if constexpr (OVL) {
-                sx = zero;
-                for (int B = 0; B < n_loc; ++B) {
-                    const double sv = sa[KP * A + B];
-                    const double2 xv = vx[4 * B + o];
-                    sx.x = fma(sv, xv.x, sx.x);
-                    sx.y = fma(sv, xv.y, sx.y);
-                }
-            }
             double d = 0.0;
             if (row) {
-                const double tx = (lane == jl ? 1.0 : 0.0) - (zs.x * sx.x - zs.y * sx.y - hx);
-                const double ty = -(zs.x * sx.y + zs.y * sx.x - hy);
+                const double tx = (lane == jl ? 1.0 : 0.0) - (zs.x * x.x - zs.y * x.y - hx);
+                const double ty = -(zs.x * x.y + zs.y * x.x - hy);
                 const double ex = tx - (double)s.x, ey = ty - (double)s.y;
                 d = fma(ex, ex, ey * ey);
             }
@@ -225,17 +143,10 @@ __global__ __launch_bounds__(SEED_T) void k_seed_mx(SolveArgs a) {
             return g;
         };
 
-        // start: x = 0, s_0 = q_0 = e_j, r_0 = p_0 = S^{-1} e_j, rho_0 = r_0^T s_0
-        float2 s = (row && lane == jl) ? make_float2(1.f, 0.f) : fzero, p = s, q = s;
-        double2 rho = one, inv_rho = one;
-        if constexpr (OVL) {
-            p = (row && o == (int)(j & 3)) ? make_float2(sif[KP * A + cl], 0.f) : fzero;
-            rho = make_double2((double)sif[KP * cl + cl], 0.0);
-            inv_rho = crcp(rho);
-        }
+        float2 s = (row && lane == jl) ? make_float2(1.f, 0.f) : fzero, p = s;
         double2 x = zero;
         vp[lane] = p;
-        hist[lane] = p;
+        hist[lane] = s;
         wave_lds_fence();
 
         double2 pc[M], po[M];
@@ -249,6 +160,7 @@ __global__ __launch_bounds__(SEED_T) void k_seed_mx(SolveArgs a) {
             nkm[m] = 0;
             res[m] = 1.0;
         }
+        double2 rho = one, inv_rho = one;
         double2 beta_old = zero, ia_old = one;
         int status = SGF_MAXITER, iters = 0, applied = 0;
         double snorm2 = 1.0;
@@ -273,8 +185,7 @@ __global__ __launch_bounds__(SEED_T) void k_seed_mx(SolveArgs a) {
                     }
                 }
             }
-            const float2 qv = OVL ? q : p;  // S p
-            const float2 w = make_float2(zsf.x * qv.x - zsf.y * qv.y - ax, zsf.x * qv.y + zsf.y * qv.x - ay);
+            const float2 w = make_float2(zsf.x * p.x - zsf.y * p.y - ax, zsf.x * p.y + zsf.y * p.x - ay);
             const double2 mu =
                 make_double2(wave_reduce((double)p.x * (double)w.x - (double)p.y * (double)w.y),
                              wave_reduce((double)p.x * (double)w.y + (double)p.y * (double)w.x));
@@ -284,42 +195,23 @@ __global__ __launch_bounds__(SEED_T) void k_seed_mx(SolveArgs a) {
             const double2 alpha = cmul(rho, crcp(mu));
             const double2 ia = cmul(mu, inv_rho);  // 1/alpha
 
-            // x_s += alpha p (FP64) ; s -= alpha w (FP32) ; r = S^{-1} s (FP32) ;
-            // rho' = r^T s, ||s||^2 (FP64)
+            // x_s += alpha p (FP64) ; s -= alpha w (FP32) ; rho', ||s||^2 (FP64)
             x = cfma(alpha, to_d(p), x);
             const float2 af = to_f(alpha);
             s = make_float2(s.x - (af.x * w.x - af.y * w.y), s.y - (af.x * w.y + af.y * w.x));
-            float2 r = s;
             const double sx = (double)s.x, sy = (double)s.y;
-            double2 rho_new;
-            if constexpr (OVL) {
-                vs[lane] = s;
-                wave_lds_fence();
-                float rx = 0.f, ry = 0.f;
-                for (int B = 0; B < n_loc; ++B) {
-                    const float sv = sif[KP * A + B];
-                    const float2 v = vs[4 * B + o];
-                    rx = fmaf(sv, v.x, rx);
-                    ry = fmaf(sv, v.y, ry);
-                }
-                r = row ? make_float2(rx, ry) : fzero;
-                const double rdx = (double)r.x, rdy = (double)r.y;
-                rho_new = make_double2(wave_reduce(rdx * sx - rdy * sy), wave_reduce(rdx * sy + rdy * sx));
-            } else {
-                rho_new = make_double2(wave_reduce(sx * sx - sy * sy), wave_reduce(2.0 * sx * sy));
-            }
+            const double2 rho_new = make_double2(wave_reduce(sx * sx - sy * sy), wave_reduce(2.0 * sx * sy));
             snorm2 = wave_reduce(fma(sx, sx, sy * sy));
             const double2 beta = cmul(rho_new, inv_rho);
             const float2 bf = to_f(beta);
-            p = make_float2(r.x + (bf.x * p.x - bf.y * p.y), r.y + (bf.x * p.y + bf.y * p.x));
-            if constexpr (OVL) q = make_float2(s.x + (bf.x * q.x - bf.y * q.y), s.y + (bf.x * q.y + bf.y * q.x));
+            p = make_float2(s.x + (bf.x * p.x - bf.y * p.y), s.y + (bf.x * p.y + bf.y * p.x));
             vp[lane] = p;
 
             if (lane == 0) {
                 hab[2 * it] = ia;
                 hab[2 * it + 1] = cmul(beta, ia);
             }
-            hist[(size_t)(it + 1) * 64 + lane] = r;
+            hist[(size_t)(it + 1) * 64 + lane] = s;
 
             const double2 coup = cmul(cmul(alpha, beta_old), ia_old);
             int alive = 0;
@@ -479,23 +371,17 @@ __global__ __launch_bounds__(256) void k_shift_mx(SolveArgs a) {
         if (r < nl) xt[r * a.ns_pad + tid] = nk > 0 ? to_f(cmul(y0, to_d(S[r]))) : make_float2(0.f, 0.f);
     __syncthreads();
 
-    // FP64 variational estimate of G_jj: 2 x~_j - x~^T (z_k S - H) x~, and
-    // the true residual r = e_j - (z_k S - H) x~ of the full iterate.  With
-    // an overlap, lam is the Gershgorin lower bound of the smallest
-    // eigenvalue of S_L, min over rows of S_ii - sum_{l != i} |S_il| (every
-    // thread forms the same value); S = I has lam = 1.
-    const bool has_s = a.s != nullptr;
+    // FP64 variational estimate of G_jj: 2 x~_j - x~^T (z_k - H) x~, and the
+    // true residual r = e_j - (z_k - H) x~ of the full iterate
     double2 quad = zero;
-    double rr = 0.0, lam = 1.0;
+    double rr = 0.0;
     for (int Aa = 0; Aa < n_loc; ++Aa) {
         const int t0 = a.lrow[a0 + Aa];
         const int t1 = Aa + 1 < n_loc ? a.lrow[a0 + Aa + 1] : nblk;
-        double2 hx[4] = {zero, zero, zero, zero}, sx[4] = {zero, zero, zero, zero};
-        double sd[4] = {0.0, 0.0, 0.0, 0.0}, so[4] = {0.0, 0.0, 0.0, 0.0};
+        double2 hx[4] = {zero, zero, zero, zero};
         for (int t = t0; t < t1; ++t) {
             const int Bb = a.lblk[2 * (b0 + t)];
-            const int64_t bi = a.lblk[2 * (b0 + t) + 1];
-            const double *hb = &a.h[16 * bi];
+            const double *hb = &a.h[16 * (int64_t)a.lblk[2 * (b0 + t) + 1]];
             double2 xb[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) xb[q] = to_d(xt[(4 * Bb + q) * a.ns_pad + tid]);
@@ -506,25 +392,11 @@ __global__ __launch_bounds__(256) void k_shift_mx(SolveArgs a) {
                     hx[oo].x = fma(hb[4 * oo + q], xb[q].x, hx[oo].x);
                     hx[oo].y = fma(hb[4 * oo + q], xb[q].y, hx[oo].y);
                 }
-            if (has_s) {  // uniform
-                const double *sb = &a.s[16 * bi];
-#pragma unroll
-                for (int oo = 0; oo < 4; ++oo)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const double v = sb[4 * oo + q];
-                        sx[oo].x = fma(v, xb[q].x, sx[oo].x);
-                        sx[oo].y = fma(v, xb[q].y, sx[oo].y);
-                        if (Bb == Aa && q == oo) sd[oo] = v;
-                        else so[oo] += fabs(v);
-                    }
-            }
         }
 #pragma unroll
         for (int oo = 0; oo < 4; ++oo) {
             const double2 xi = to_d(xt[(4 * Aa + oo) * a.ns_pad + tid]);
-            if (has_s) lam = fmin(lam, sd[oo] - so[oo]);
-            const double2 ax = csub(cmul(zk, has_s ? sx[oo] : xi), hx[oo]);
+            const double2 ax = csub(cmul(zk, xi), hx[oo]);
             quad = cfma(xi, ax, quad);
             const double tx = (4 * Aa + oo == jl ? 1.0 : 0.0) - ax.x, ty = -ax.y;
             rr = fma(tx, tx, fma(ty, ty, rr));
@@ -533,15 +405,14 @@ __global__ __launch_bounds__(256) void k_shift_mx(SolveArgs a) {
     const double2 xj = to_d(xt[jl * a.ns_pad + tid]);
     const double2 gjj = csub(make_double2(2.0 * xj.x, 2.0 * xj.y), quad);
 
-    // A-posteriori bound: G_jj - G~_jj = r^T (z_k S - H)^{-1} r.  With
-    // u = S^{-1/2} r this is u^T (z_k - S^{-1/2} H S^{-1/2})^{-1} u, the
-    // inverse of a shifted real symmetric matrix, of norm <= 1 / Im z_k, and
-    // ||u||^2 <= ||r||^2 / lam_min(S_L), so
-    // |G_jj - G~_jj| <= ||r||^2 / (lam Im z_k).  A column whose lam is not
-    // positive cannot be bounded this way and is rejected.  The column is
-    // accepted when the largest bound over its shifts is within g_tol of
-    // max_k |G~_jj|; otherwise its status becomes DRIFT.  resid receives ||r||.
-    const double bound = (live && nk > 0) ? (lam > 0.0 ? rr / (zk.y * lam) : INFINITY) : 0.0;
+    // A-posteriori bound: G_jj - G~_jj = r^T (z_k - H)^{-1} r, and z_k - H is
+    // normal with ||(z_k - H)^{-1}||_2 <= 1 / Im z_k, so
+    // |G_jj - G~_jj| <= ||r||^2 / Im z_k.  The column is accepted when the
+    // largest bound over its shifts is within g_tol of max_k |G~_jj|;
+    // otherwise its status becomes DRIFT.  resid receives ||r||.
+    // a non-finite estimate or residual has no bound (fmax below would drop a NaN)
+    const bool fin = isfinite(rr) && isfinite(gjj.x) && isfinite(gjj.y);
+    const double bound = (live && nk > 0) ? (fin ? rr / zk.y : INFINITY) : 0.0;
     const double gmag = (live && nk > 0) ? sqrt(fma(gjj.x, gjj.x, gjj.y * gjj.y)) : 0.0;
     if (live && a.resid) a.resid[c * a.ns + kof] = sqrt(rr);
     double wb = bound, wg = gmag;
@@ -595,24 +466,19 @@ __global__ __launch_bounds__(256) void k_shift_mx(SolveArgs a) {
 
 }  // namespace
 
-template <bool OVL>
-static KernelFn pick_seed_mx_s(int M, int bmax) {
+KernelFn pick_seed_mx(int M, int bmax) {
     if (bmax <= 6) {
         switch (M) {
-            case 1: return k_seed_mx<1, 6, OVL>;
-            case 2: return k_seed_mx<2, 6, OVL>;
-            default: return k_seed_mx<4, 6, OVL>;
+            case 1: return k_seed_mx<1, 6>;
+            case 2: return k_seed_mx<2, 6>;
+            default: return k_seed_mx<4, 6>;
         }
     }
     switch (M) {
-        case 1: return k_seed_mx<1, 8, OVL>;
-        case 2: return k_seed_mx<2, 8, OVL>;
-        default: return k_seed_mx<4, 8, OVL>;
+        case 1: return k_seed_mx<1, 8>;
+        case 2: return k_seed_mx<2, 8>;
+        default: return k_seed_mx<4, 8>;
     }
-}
-
-KernelFn pick_seed_mx(int M, int bmax, bool overlap) {
-    return overlap ? pick_seed_mx_s<true>(M, bmax) : pick_seed_mx_s<false>(M, bmax);
 }
 
 KernelFn shift_mx_kernel() { return k_shift_mx; }

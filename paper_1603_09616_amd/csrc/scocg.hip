@@ -2467,9 +2467,7 @@ __global__ void k_zero_ticket(int64_t *t) {
 HistoryShape history_shape(const sgf_plan_totals &tot, int ns, const sgf_solve_opts &o) {
     HistoryShape h;
     h.ns_pad = (ns + 63) / 64 * 64;
-    // the mixed pass runs subspaces of at most 16 atoms (larger ones are left to FP64)
-    const int la = tot.max_loc_atoms > 0 ? tot.max_loc_atoms : 1;
-    const int nl_max = 4 * (o.precision == 1 && la > 16 ? 16 : la);
+    const int nl_max = 4 * (tot.max_loc_atoms > 0 ? tot.max_loc_atoms : 1);
     h.cap = o.max_iter > 0 ? o.max_iter : (o.precision == 1 ? 40 : 10) * nl_max;
     h.rmax = o.precision == 1 ? 32 : 4 * (tot.max_proj_atoms > 0 ? tot.max_proj_atoms : 1);
     h.per_col = align_up(sizeof(ColMeta), 16) + align_up((size_t)h.ns_pad * 4, 16) + (size_t)h.ns_pad * 8 +
@@ -2692,13 +2690,13 @@ static sgf_status shifted_solve_in(const sgf_system *sys, const sgf_plan *plan, 
     }
     const bool mixed = opts->precision == 1;
     if (mixed) {
-        if (sys->s && sys->s_orbital_diagonal != 1) {
-            set_error("sgf_shifted_solve: the mixed-precision path takes S = I or an overlap of blocks s_ab I4 "
-                      "(s_orbital_diagonal = 1)");
+        if (sys->s) {
+            set_error("sgf_shifted_solve: the mixed-precision path supports S = I only");
             return SGF_EUNSUPPORTED;
         }
-        if (totals->max_row_blocks > 8) {
-            set_error("sgf_shifted_solve: the mixed-precision path needs <= 8 blocks per row (got %d)",
+        if (totals->max_loc_atoms > 16 || totals->max_row_blocks > 8) {
+            set_error("sgf_shifted_solve: the mixed-precision path needs local subspaces of <= 16 atoms with "
+                      "<= 8 blocks per row (got %d atoms, %d blocks)", totals->max_loc_atoms,
                       totals->max_row_blocks);
             return SGF_EUNSUPPORTED;
         }
@@ -2849,7 +2847,7 @@ static sgf_status shifted_solve_in(const sgf_system *sys, const sgf_plan *plan, 
     const bool gen2_one = gen && !kron && !mixed && opts->stage_lds < 0 && !gen_split &&
                           totals->max_loc_atoms <= 16 && totals->max_row_blocks <= 8;
     const bool gen_packed = gen_split || (gen && opts->stage_lds == 1);
-    KernelFn seed_fn = mixed ? pick_seed_mx(M, totals->max_row_blocks, sys->s != nullptr)
+    KernelFn seed_fn = mixed ? pick_seed_mx(M, totals->max_row_blocks)
                        : kron ? (kron_two_waves ? pick_seed_kron2((hs.ns_pad + 127) / 128, totals->max_row_blocks)
                                                 : pick_seed_kron(kron_split ? 2 : 1, M, totals->max_row_blocks))
                        : gen2 ? pick_seed_gen2((hs.ns_pad + GEN2_T - 1) / GEN2_T, totals->max_row_blocks)

@@ -8,6 +8,8 @@ namespace sgf {
 
 constexpr int SEED_T = 64;    // seed pass: one wavefront per workgroup
 constexpr int SHIFT_CH = 16;  // shift pass: backward steps staged in LDS at a time
+// the 2 SHIFT_CH + 2 recurrence scalars of a chunk are staged one per thread
+static_assert(2 * SHIFT_CH + 2 <= 64, "a 64-thread shift workgroup stages a chunk's scalars in one pass");
 constexpr double INV_PI = 0.318309886183790671537767526745;
 
 // Column metadata written by the seed pass for the shift pass.
@@ -90,7 +92,7 @@ SolveLayout solve_layout(const HistoryShape &hs, int ns, int64_t slots, void *ba
 using KernelFn = void (*)(SolveArgs);
 
 // Mixed-precision passes (mixed.hip).
-KernelFn pick_seed_mx(int M, int bmax, bool overlap);
+KernelFn pick_seed_mx(int M, int bmax);
 KernelFn shift_mx_kernel();
 
 // S != I seed pass with the per-atom overlap inverse (seed_kron.hip):
