@@ -2264,8 +2264,14 @@ __device__ __forceinline__ void cfma_rows2(double2 &S0, double2 &S1, double2 r0,
 // the MS shifts of a lane) end their sweeps together.
 template <int NPA, int MS>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MS == 1 && NPA <= 4 ? 4 : (MS == 1 && NPA <= 6 ? 3 : 1)))) void k_shift(SolveArgs a) {
-    __shared__ double2 sab[SHIFT_CH + 1][2];       // 1/alpha, beta/alpha of steps lo-1 .. hi
-    __shared__ double2 srow[SHIFT_CH][4 * NPA];    // r_m on P for steps lo .. hi
+    // backward steps staged per chunk: 24 where the larger staging still fits
+    // the register budget without spilling (up to three projection atoms, and
+    // five at one shift per lane: 2.7% faster on the bundle than 16, from
+    // fewer barriers), 16 elsewhere
+    constexpr int CH = (NPA <= 3 || (NPA == 5 && MS == 1)) ? 24 : SHIFT_CH;
+    static_assert(2 * CH + 2 <= 64, "a 64-thread shift workgroup stages a chunk's scalars in one pass");
+    __shared__ double2 sab[CH + 1][2];             // 1/alpha, beta/alpha of steps lo-1 .. hi
+    __shared__ double2 srow[CH][4 * NPA];          // r_m on P for steps lo .. hi
     __shared__ int skey[512];                      // (N_k << 10) | k, sorted ascending
     __shared__ double rpart[32 * 8];               // [row][wave] partial rho sums
     const int64_t slot = blockIdx.x;
@@ -2323,15 +2329,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MS == 1 && 
 #pragma unroll
         for (int r = 0; r < 4 * NPA; ++r) S[u][r] = zero;
     }
-    for (int hi = top - 1; hi >= 0; hi -= SHIFT_CH) {
-        const int lo = hi - SHIFT_CH + 1 > 0 ? hi - SHIFT_CH + 1 : 0;
+    for (int hi = top - 1; hi >= 0; hi -= CH) {
+        const int lo = hi - CH + 1 > 0 ? hi - CH + 1 : 0;
         const int nstep = hi - lo + 1;
         // The chunk's loads are all issued before the barrier that ends the
         // previous chunk's reads, and written to LDS after it: one memory
         // latency per chunk instead of one per staged element a thread holds.
         // UR covers the rows at 128 threads and more; a 64-thread workgroup
         // stages the rest in a plain loop.
-        constexpr int UR = (SHIFT_CH * 4 * NPA + 127) / 128;
+        constexpr int UR = (CH * 4 * NPA + 127) / 128;
         const int nab = (nstep + 1) * 2, nrv = nstep * nrow;
         double2 vab = zero;  // (assigned, not selected: a select of two lvalues goes through scratch)
         if (tid < nab && lo - 1 + (tid >> 1) >= 0) vab = hab[2 * (lo - 1 + (tid >> 1)) + (tid & 1)];
