@@ -2259,19 +2259,31 @@ __device__ __forceinline__ void cfma_rows2(double2 &S0, double2 &S1, double2 r0,
         : [gx] "v"(g.x), [gy] "v"(g.y), [r0x] "v"(r0.x), [r0y] "v"(r0.y), [r1x] "v"(r1.x), [r1y] "v"(r1.y));
 }
 
+// Orders this wavefront's LDS accesses (release, wave barrier, acquire)
+// and waits for them: lanes read what other lanes of the wavefront wrote.
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+}
+
 // One workgroup per column; each lane carries MS shifts.  The shifts are
 // first sorted by their step count N_k so that the lanes of a wavefront (and
 // the MS shifts of a lane) end their sweeps together.
 template <int NPA, int MS>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MS == 1 && NPA <= 4 ? 4 : (MS == 1 && NPA <= 6 ? 3 : 1)))) void k_shift(SolveArgs a) {
-    // backward steps staged per chunk: 24 where the larger staging still fits
-    // the register budget without spilling (up to three projection atoms, and
-    // five at one shift per lane: 2.7% faster on the bundle than 16, from
-    // fewer barriers), 16 elsewhere
-    constexpr int CH = (NPA <= 3 || (NPA == 5 && MS == 1)) ? 24 : SHIFT_CH;
+    // The history is staged in LDS a chunk of backward steps at a time.
+    // PWV: each wavefront stages its own chunks (dynamic LDS, a region per
+    // wavefront) and sweeps only its own steps, so a wavefront of short
+    // shifts does not wait at the chunk barriers of a longer one (bundle
+    // 28.9 -> 28.1 ms, overlap bundle 57.3 -> 53.3 ms).  With four or six
+    // and more projection atoms the extra staging registers spill, and the
+    // workgroup stages each chunk once (static LDS, 24 steps where that
+    // still fits the register budget, else 16).
+    constexpr bool PWV = NPA <= 5 && NPA != 4;
+    constexpr int CH = PWV ? SHIFT_CH : (NPA <= 3 || (NPA == 5 && MS == 1)) ? 24 : SHIFT_CH;
     static_assert(2 * CH + 2 <= 64, "a 64-thread shift workgroup stages a chunk's scalars in one pass");
-    __shared__ double2 sab[CH + 1][2];             // 1/alpha, beta/alpha of steps lo-1 .. hi
-    __shared__ double2 srow[CH][4 * NPA];          // r_m on P for steps lo .. hi
     __shared__ int skey[512];                      // (N_k << 10) | k, sorted ascending
     __shared__ double rpart[32 * 8];               // [row][wave] partial rho sums
     const int64_t slot = blockIdx.x;
@@ -2329,65 +2341,128 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MS == 1 && 
 #pragma unroll
         for (int r = 0; r < 4 * NPA; ++r) S[u][r] = zero;
     }
-    for (int hi = top - 1; hi >= 0; hi -= CH) {
-        const int lo = hi - CH + 1 > 0 ? hi - CH + 1 : 0;
-        const int nstep = hi - lo + 1;
-        // The chunk's loads are all issued before the barrier that ends the
-        // previous chunk's reads, and written to LDS after it: one memory
-        // latency per chunk instead of one per staged element a thread holds.
-        // UR covers the rows at 128 threads and more; a 64-thread workgroup
-        // stages the rest in a plain loop.
-        constexpr int UR = (CH * 4 * NPA + 127) / 128;
-        const int nab = (nstep + 1) * 2, nrv = nstep * nrow;
-        double2 vab = zero;  // (assigned, not selected: a select of two lvalues goes through scratch)
-        if (tid < nab && lo - 1 + (tid >> 1) >= 0) vab = hab[2 * (lo - 1 + (tid >> 1)) + (tid & 1)];
-        double2 vr[UR];
+    if constexpr (PWV) {
+        constexpr int PW = (CH + 1) * 2 + CH * 4 * NPA;  // double2 per wavefront
+        extern __shared__ __align__(16) double2 shift_dyn[];
+        double2 (*sab)[2] = reinterpret_cast<double2 (*)[2]>(shift_dyn + (size_t)wv * PW);
+        double2 (*srow)[4 * NPA] = reinterpret_cast<double2 (*)[4 * NPA]>(shift_dyn + (size_t)wv * PW + (CH + 1) * 2);
+        for (int hi = wtop - 1; hi >= 0; hi -= CH) {
+            const int lo = hi - CH + 1 > 0 ? hi - CH + 1 : 0;
+            const int nstep = hi - lo + 1;
+            // every load of the chunk issued before this wavefront's reads of
+            // the previous one are ordered, written to its LDS region after
+            constexpr int UR = (CH * 4 * NPA + 63) / 64;
+            const int nab = (nstep + 1) * 2, nrv = nstep * nrow;
+            double2 vab = zero;
+            if (lane < nab && lo - 1 + (lane >> 1) >= 0) vab = hab[2 * (lo - 1 + (lane >> 1)) + (lane & 1)];
+            double2 vr[UR];
 #pragma unroll
-        for (int u = 0; u < UR; ++u) {
-            const int idx = tid + u * T;
-            vr[u] = zero;
-            if (idx < nrv) {
-                const int sm = idx / nrow, r = idx - sm * nrow;
-                vr[u] = hr[(size_t)(lo + sm) * a.rmax + r];
-            }
-        }
-        __syncthreads();  // the previous chunk has been consumed
-        if (tid < nab) sab[tid >> 1][tid & 1] = vab;
-#pragma unroll
-        for (int u = 0; u < UR; ++u) {
-            const int idx = tid + u * T;
-            if (idx < nrv) {
-                const int sm = idx / nrow, r = idx - sm * nrow;
-                srow[sm][r] = vr[u];
-            }
-        }
-        for (int idx = tid + UR * T; idx < nrv; idx += T) {
-            const int sm = idx / nrow, r = idx - sm * nrow;
-            srow[sm][r] = hr[(size_t)(lo + sm) * a.rmax + r];
-        }
-        __syncthreads();
-        if (lo >= wtop) continue;  // nothing for this wavefront in this chunk
-        for (int m = hi; m >= lo; --m) {
-            // 1/alpha and beta/alpha of steps m and m - 1, read from LDS at every
-            // step (carrying the step-m pair over would cost register moves)
-            const double2 ia_m = sab[m - lo + 1][0], ba_m = sab[m - lo + 1][1];
-            const double2 ia_p = sab[m - lo][0], ba_p = sab[m - lo][1];
-            const double2 *rm = srow[m - lo];
-#pragma unroll
-            for (int u = 0; u < MS; ++u) {
-                if (m >= nk[u]) continue;
-                // g is exactly zero up to the shift's first step (m = N_k - 1),
-                // where this is the bare diagonal
-                const double2 d = csub(cadd(cadd(ia_m, ba_p), sigma[u]), cmul(ba_m, g[u]));
-#pragma unroll
-                for (int q = 0; q < NPA; ++q) {
-                    if (q < npa) {
-                        cfma_rows2(S[u][4 * q], S[u][4 * q + 1], rm[4 * q], rm[4 * q + 1], g[u]);
-                        cfma_rows2(S[u][4 * q + 2], S[u][4 * q + 3], rm[4 * q + 2], rm[4 * q + 3], g[u]);
-                    }
+            for (int u = 0; u < UR; ++u) {
+                const int idx = lane + u * 64;
+                vr[u] = zero;
+                if (idx < nrv) {
+                    const int sm = idx / nrow, r = idx - sm * nrow;
+                    vr[u] = hr[(size_t)(lo + sm) * a.rmax + r];
                 }
-                y0[u] = crcp_fast(d);  // the last step of every shift is m = 0: y_0 = 1 / d_0
-                g[u] = cmul(ia_p, y0[u]);  // (at m = 0, ia_p is the zero staged for step -1)
+            }
+            wave_sync_lds();  // this wavefront's reads of the previous chunk are done
+            if (lane < nab) sab[lane >> 1][lane & 1] = vab;
+#pragma unroll
+            for (int u = 0; u < UR; ++u) {
+                const int idx = lane + u * 64;
+                if (idx < nrv) {
+                    const int sm = idx / nrow, r = idx - sm * nrow;
+                    srow[sm][r] = vr[u];
+                }
+            }
+            wave_sync_lds();
+            for (int m = hi; m >= lo; --m) {
+                // 1/alpha and beta/alpha of steps m and m - 1, read from LDS at every
+                // step (carrying the step-m pair over would cost register moves)
+                const double2 ia_m = sab[m - lo + 1][0], ba_m = sab[m - lo + 1][1];
+                const double2 ia_p = sab[m - lo][0], ba_p = sab[m - lo][1];
+                const double2 *rm = srow[m - lo];
+#pragma unroll
+                for (int u = 0; u < MS; ++u) {
+                    if (m >= nk[u]) continue;
+                    // g is exactly zero up to the shift's first step (m = N_k - 1),
+                    // where this is the bare diagonal
+                    const double2 d = csub(cadd(cadd(ia_m, ba_p), sigma[u]), cmul(ba_m, g[u]));
+#pragma unroll
+                    for (int q = 0; q < NPA; ++q) {
+                        if (q < npa) {
+                            cfma_rows2(S[u][4 * q], S[u][4 * q + 1], rm[4 * q], rm[4 * q + 1], g[u]);
+                            cfma_rows2(S[u][4 * q + 2], S[u][4 * q + 3], rm[4 * q + 2], rm[4 * q + 3], g[u]);
+                        }
+                    }
+                    y0[u] = crcp_fast(d);  // the last step of every shift is m = 0: y_0 = 1 / d_0
+                    g[u] = cmul(ia_p, y0[u]);  // (at m = 0, ia_p is the zero staged for step -1)
+                }
+            }
+        }
+    } else {
+        __shared__ double2 sab[CH + 1][2];             // 1/alpha, beta/alpha of steps lo-1 .. hi
+        __shared__ double2 srow[CH][4 * NPA];          // r_m on P for steps lo .. hi
+        for (int hi = top - 1; hi >= 0; hi -= CH) {
+            const int lo = hi - CH + 1 > 0 ? hi - CH + 1 : 0;
+            const int nstep = hi - lo + 1;
+            // The chunk's loads are all issued before the barrier that ends the
+            // previous chunk's reads, and written to LDS after it: one memory
+            // latency per chunk instead of one per staged element a thread holds.
+            // UR covers the rows at 128 threads and more; a 64-thread workgroup
+            // stages the rest in a plain loop.
+            constexpr int UR = (CH * 4 * NPA + 127) / 128;
+            const int nab = (nstep + 1) * 2, nrv = nstep * nrow;
+            double2 vab = zero;  // (assigned, not selected: a select of two lvalues goes through scratch)
+            if (tid < nab && lo - 1 + (tid >> 1) >= 0) vab = hab[2 * (lo - 1 + (tid >> 1)) + (tid & 1)];
+            double2 vr[UR];
+#pragma unroll
+            for (int u = 0; u < UR; ++u) {
+                const int idx = tid + u * T;
+                vr[u] = zero;
+                if (idx < nrv) {
+                    const int sm = idx / nrow, r = idx - sm * nrow;
+                    vr[u] = hr[(size_t)(lo + sm) * a.rmax + r];
+                }
+            }
+            __syncthreads();  // the previous chunk has been consumed
+            if (tid < nab) sab[tid >> 1][tid & 1] = vab;
+#pragma unroll
+            for (int u = 0; u < UR; ++u) {
+                const int idx = tid + u * T;
+                if (idx < nrv) {
+                    const int sm = idx / nrow, r = idx - sm * nrow;
+                    srow[sm][r] = vr[u];
+                }
+            }
+            for (int idx = tid + UR * T; idx < nrv; idx += T) {
+                const int sm = idx / nrow, r = idx - sm * nrow;
+                srow[sm][r] = hr[(size_t)(lo + sm) * a.rmax + r];
+            }
+            __syncthreads();
+            if (lo >= wtop) continue;  // nothing for this wavefront in this chunk
+            for (int m = hi; m >= lo; --m) {
+                // 1/alpha and beta/alpha of steps m and m - 1, read from LDS at every
+                // step (carrying the step-m pair over would cost register moves)
+                const double2 ia_m = sab[m - lo + 1][0], ba_m = sab[m - lo + 1][1];
+                const double2 ia_p = sab[m - lo][0], ba_p = sab[m - lo][1];
+                const double2 *rm = srow[m - lo];
+#pragma unroll
+                for (int u = 0; u < MS; ++u) {
+                    if (m >= nk[u]) continue;
+                    // g is exactly zero up to the shift's first step (m = N_k - 1),
+                    // where this is the bare diagonal
+                    const double2 d = csub(cadd(cadd(ia_m, ba_p), sigma[u]), cmul(ba_m, g[u]));
+#pragma unroll
+                    for (int q = 0; q < NPA; ++q) {
+                        if (q < npa) {
+                            cfma_rows2(S[u][4 * q], S[u][4 * q + 1], rm[4 * q], rm[4 * q + 1], g[u]);
+                            cfma_rows2(S[u][4 * q + 2], S[u][4 * q + 3], rm[4 * q + 2], rm[4 * q + 3], g[u]);
+                        }
+                    }
+                    y0[u] = crcp_fast(d);  // the last step of every shift is m = 0: y_0 = 1 / d_0
+                    g[u] = cmul(ia_p, y0[u]);  // (at m = 0, ia_p is the zero staged for step -1)
+                }
             }
         }
     }
@@ -2913,10 +2988,15 @@ static sgf_status shifted_solve_in(const sgf_system *sys, const sgf_plan *plan, 
     // shift-pass workgroup: ns_pad / ms lanes rounded up to whole wavefronts (<= 512)
     const int shift_threads = ((hs.ns_pad / ms + 63) / 64) * 64;
     // mixed: the full iterates of every shift, complex FP32 [64][ns_pad]
-    const size_t shift_lds = mixed ? (size_t)64 * hs.ns_pad * 8 : 0;
-    if (mixed)
-        SGF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(shift_fn),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shift_lds));
+    // per-wavefront history staging of the FP64 shift pass (up to five
+    // projection atoms, not four): a chunk of SHIFT_CH steps per wavefront
+    const int npa_t = totals->max_proj_atoms < 1 ? 1 : (totals->max_proj_atoms > 8 ? 8 : totals->max_proj_atoms);
+    const bool shift_pwv = npa_t <= 5 && npa_t != 4;
+    const size_t shift_lds = mixed       ? (size_t)64 * hs.ns_pad * 8
+                             : shift_pwv ? (size_t)(shift_threads / 64) * ((SHIFT_CH + 1) * 2 + SHIFT_CH * 4 * npa_t) * 16
+                                         : 0;
+    SGF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(shift_fn),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shift_lds));
     SGF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(seed_fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)seed_lds));
     int per_cu = 0;
