@@ -44,7 +44,7 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_tiles(int64_t *data, int64_t n,
 #pragma unroll
     for (int i = 0; i < SCAN_ITEMS; ++i)
         if (base + i < n) data[base + i] = v[i] + prefix;
-    if (threadIdx.x == SCAN_T - 1) sums[blockIdx.x] = part[SCAN_T - 1];
+    if (sums && threadIdx.x == SCAN_T - 1) sums[blockIdx.x] = part[SCAN_T - 1];
 }
 
 // One workgroup scans the tile totals (exclusive result in place).
@@ -98,55 +98,62 @@ sgf_status inclusive_scan_i64(int64_t *d_data, int64_t n, void *d_scratch, hipSt
     return SGF_OK;
 }
 
-// One workgroup of 1024 threads, in place, tile by tile (SCAN_ITEMS
-// consecutive items per thread) with a running carry: per tile, a wavefront
-// scan of the thread totals with cross-lane shifts, then one wavefront scans
-// the 16 wavefront totals.  Two barriers per tile.
-constexpr int SCAN1_T = 1024;
-constexpr int SCAN1_TILE = SCAN1_T * SCAN_ITEMS;
-
-__device__ __forceinline__ int64_t wave_scan_i64(int64_t v, int lane) {
+// The same inclusive scan with no scratch, in three launches over tiles of
+// SCAN_TILE items: (1) each tile scanned in place, so a full tile's last
+// item holds the tile's total; (2) tile b adds the totals of tiles 0 .. b-1,
+// read from those last items, to its other items (a full tile's last item
+// is left alone, since later tiles still read it); (3) one workgroup turns
+// the last items of the full tiles into their running sums.  Integer sums,
+// so the result is that of the sequential scan.
+__global__ __launch_bounds__(SCAN_T) void k_scan_carry_in(int64_t *data, int64_t n) {
+    __shared__ int64_t wsum[SCAN_T / 64];
+    const int64_t b = blockIdx.x + 1;  // tile 0 has nothing to add
+    int64_t s = 0;
+    for (int64_t j = threadIdx.x; j < b; j += SCAN_T) s += data[(j + 1) * SCAN_TILE - 1];
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int64_t u = __shfl_up(v, off, 64);
-        if (lane >= off) v += u;
-    }
-    return v;
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = s;
+    __syncthreads();
+    int64_t off = 0;
+#pragma unroll
+    for (int w = 0; w < SCAN_T / 64; ++w) off += wsum[w];
+    const int64_t t0 = b * SCAN_TILE;
+    const int64_t t1 = t0 + SCAN_TILE < n ? t0 + SCAN_TILE - 1 : n;  // a full tile keeps its last item
+    for (int64_t i = t0 + threadIdx.x; i < t1; i += SCAN_T) data[i] += off;
 }
 
-__global__ __launch_bounds__(SCAN1_T) void k_scan_one_block(int64_t *data, int64_t n) {
-    __shared__ int64_t wsum[SCAN1_T / 64];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    int64_t carry = 0;  // uniform: every thread adds the same tile totals
-    for (int64_t start = 0; start < n; start += SCAN1_TILE) {
-        const int64_t base = start + (int64_t)threadIdx.x * SCAN_ITEMS;
-        int64_t v[SCAN_ITEMS];
-        int64_t run = 0;
-#pragma unroll
-        for (int i = 0; i < SCAN_ITEMS; ++i) {
-            run += (base + i < n) ? data[base + i] : 0;
-            v[i] = run;
-        }
-        const int64_t incl = wave_scan_i64(run, lane);
-        if (lane == 63) wsum[wid] = incl;
+__global__ __launch_bounds__(SCAN_T) void k_scan_tile_ends(int64_t *data, int64_t n_full) {
+    __shared__ int64_t part[SCAN_T];
+    int64_t carry = 0;  // uniform
+    for (int64_t start = 0; start < n_full; start += SCAN_T) {
+        const int64_t j = start + threadIdx.x;
+        const int64_t x = j < n_full ? data[(j + 1) * SCAN_TILE - 1] : 0;
+        part[threadIdx.x] = x;
         __syncthreads();
-        const int64_t w = lane < SCAN1_T / 64 ? wsum[lane] : 0;
-        const int64_t wincl = wave_scan_i64(w, lane);
-        const int64_t wpre = __shfl(wincl, wid, 64) - __shfl(w, wid, 64);   // waves before this one
-        const int64_t tile = __shfl(wincl, SCAN1_T / 64 - 1, 64);
-        const int64_t prefix = carry + wpre + incl - run;
-#pragma unroll
-        for (int i = 0; i < SCAN_ITEMS; ++i)
-            if (base + i < n) data[base + i] = v[i] + prefix;
-        carry += tile;
-        __syncthreads();  // wsum is rewritten by the next tile
+        for (int off = 1; off < SCAN_T; off <<= 1) {
+            const int64_t add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+            __syncthreads();
+            part[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (j < n_full) data[(j + 1) * SCAN_TILE - 1] = carry + part[threadIdx.x];
+        carry += part[SCAN_T - 1];
+        __syncthreads();  // part is rewritten by the next round
     }
 }
 
-sgf_status inclusive_scan_one_block(int64_t *d_data, int64_t n, hipStream_t st) {
+sgf_status inclusive_scan_noscratch(int64_t *d_data, int64_t n, hipStream_t st) {
     if (n <= 0) return SGF_OK;
-    k_scan_one_block<<<1, SCAN1_T, 0, st>>>(d_data, n);
+    const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    k_scan_tiles<<<dim3((unsigned)nb), dim3(SCAN_T), 0, st>>>(d_data, n, nullptr);
     SGF_LAUNCHED();
+    if (nb > 1) {
+        k_scan_carry_in<<<dim3((unsigned)(nb - 1)), dim3(SCAN_T), 0, st>>>(d_data, n);
+        SGF_LAUNCHED();
+        // the full tiles: all but the last, which may be partial
+        k_scan_tile_ends<<<1, SCAN_T, 0, st>>>(d_data, nb - 1);
+        SGF_LAUNCHED();
+    }
     return SGF_OK;
 }
 

@@ -198,7 +198,8 @@ __device__ __forceinline__ void wave_sum_lds(const double (&v)[NV], double *buf,
 // ---------------------------------------------------------------------------
 size_t prefix_scratch_bytes(int64_t n);
 sgf_status inclusive_scan_i64(int64_t *d_data, int64_t n, void *d_scratch, hipStream_t st);
-// Same result from a single workgroup and no scratch (for short arrays).
-sgf_status inclusive_scan_one_block(int64_t *d_data, int64_t n, hipStream_t st);
+// Same result with no scratch (three launches; the tile totals are read
+// from the tiles themselves).
+sgf_status inclusive_scan_noscratch(int64_t *d_data, int64_t n, hipStream_t st);
 
 }  // namespace sgf

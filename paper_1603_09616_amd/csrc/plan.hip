@@ -581,7 +581,7 @@ extern "C" sgf_status sgf_proj_layout(const sgf_plan *plan, int64_t n_cols, cons
     k_proj_count<<<g, 256, 0, st>>>(n_cols, plan->n_plans, d_col_plan, plan->pa_off, d_proj_off);
     SGF_LAUNCHED();
     if (n_cols > 0) {
-        sgf_status rc = inclusive_scan_one_block(d_proj_off + 1, n_cols, st);
+        sgf_status rc = inclusive_scan_noscratch(d_proj_off + 1, n_cols, st);
         if (rc) return rc;
     }
     if (d_proj_row && n_cols > 0) {

@@ -99,13 +99,15 @@ def test_capacity_limits(sgf):
     assert e.value.code == sgf.SGF_EUNSUPPORTED
 
 
-def test_projection_layout_many_tiles(sgf):
-    """Output offsets and projection rows of 43,200 columns (the offsets'
-    scan spans several 8192-entry tiles and a ragged tail), recomputed on
-    the host from the plans."""
+@pytest.mark.parametrize("n_cols", [0, 1, 2047, 2048, 2049, 4096, 4097, 6145])
+def test_projection_layout_many_tiles(sgf, n_cols):
+    """Output offsets and projection rows, recomputed on the host from the
+    plans: all 43,200 columns (n_cols 0; the offsets' scan spans 22 tiles of
+    2048 and a ragged tail) and column counts at the tile edges (one tile,
+    exactly one or two full tiles, a full tile and one more)."""
     wl = W.bundle_workload(6, 6, 300, n_shifts=4, config_no=141)
     s = sgf.system_for(wl)
-    cols = wl.columns
+    cols = wl.columns if n_cols == 0 else wl.columns[:n_cols]
     print(f"  {cols.size} columns", flush=True)
     prep = sgf.prepare(s, cols, radius=wl.radius, prune=True)
     cp = prep.col_plan.cpu().numpy()
