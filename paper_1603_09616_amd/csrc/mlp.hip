@@ -77,12 +77,14 @@ __global__ void k_features(FeatArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Forward pass (inference): one sample per thread, parameters in LDS.
+// Forward pass (inference): one sample per thread.  Every parameter index is
+// the same for all lanes, so the parameters are read with scalar loads into
+// SGPRs and feed the multiply-adds directly (staged in LDS, each multiply-add
+// waited for an LDS read of its weight).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_mlp_forward(const float *P, const float *X, int64_t n, float *Y) {
-    __shared__ float sp[NPARAM];
-    for (int i = threadIdx.x; i < NPARAM; i += blockDim.x) sp[i] = P[i];
-    __syncthreads();
+__global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ P, const float *X, int64_t n,
+                                                     float *Y) {
+    const float *sp = P;
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (int64_t)gridDim.x * blockDim.x) {
         float x[NF];
 #pragma unroll
